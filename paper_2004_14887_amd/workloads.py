@@ -1,0 +1,258 @@
+"""Seeded synthetic workloads: mesh layouts and analytic initial fields.
+
+This module holds no part of the lattice Boltzmann method or of the grid
+coupling.  It only describes meshes (a periodic coarse domain and nested
+refined boxes) and evaluates the paper's analytic initial fields at node
+positions, so that the HIP library and the CPU oracle start from the same
+numbers:
+
+* the barotropic convected vortex, an exact steady solution of the isothermal
+  Euler equations (Sec. 4.2, Eq.(init_COVO));
+* the Gaussian acoustic pulse (Sec. 4.1, Eq.(init_Pulse)), read with a radial
+  distance r^2 = x^2 + y^2 (+ z^2);
+* a divergence-free vortex ring for 3-D cases (curl of an azimuthal vector
+  potential), a synthetic stand-in for 3-D vortical structures.
+
+All lengths are in coarse (level-0) cells, all velocities in lattice units;
+under acoustic scaling velocities are the same on every level.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+CS2 = 1.0 / 3.0
+CS = math.sqrt(CS2)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    lattice: str                      # "D2Q9" | "D3Q19"
+    n0: Tuple[int, ...]               # periodic coarse domain, nodes per axis
+    boxes: List[Tuple[Tuple[int, ...], Tuple[int, ...]]]  # per refined level: (lo, hi) in parent node coords
+    tau0: float
+    steps: int
+    coupling: int = 2                 # 1 = DC1, 2 = DC2
+    eq_order: int = 2
+    probes: List[Tuple[int, ...]] = dataclasses.field(default_factory=list)
+    background: Tuple[float, ...] = (0.0, 0.0, 0.0)
+    vortices: List[dict] = dataclasses.field(default_factory=list)   # 2-D barotropic vortices
+    pulses: List[dict] = dataclasses.field(default_factory=list)
+    rings: List[dict] = dataclasses.field(default_factory=list)      # 3-D vortex rings
+    seed: int = 0
+
+    @property
+    def D(self) -> int:
+        return 2 if self.lattice == "D2Q9" else 3
+
+    @property
+    def Q(self) -> int:
+        return 9 if self.lattice == "D2Q9" else 19
+
+    @property
+    def n_levels(self) -> int:
+        return 1 + len(self.boxes)
+
+    def dims(self, l: int) -> Tuple[int, int, int]:
+        return level_dims(self)[l]
+
+    def n_nodes(self, l: int) -> int:
+        d = self.dims(l)
+        return d[0] * d[1] * d[2]
+
+
+def level_dims(wl: Workload) -> List[Tuple[int, int, int]]:
+    """Dense node counts per level: level 0 is n0; level l+1 has 2*(hi-lo)+1
+    nodes per axis (cell-vertex, both box faces included)."""
+    out = []
+    d0 = list(wl.n0[:wl.D]) + [1] * (3 - wl.D)
+    out.append(tuple(d0))
+    for lo, hi in wl.boxes:
+        d = [2 * (hi[a] - lo[a]) + 1 for a in range(wl.D)] + [1] * (3 - wl.D)
+        out.append(tuple(d))
+    return out
+
+
+def level_origin(wl: Workload, l: int) -> np.ndarray:
+    """Level-0 coordinate of node 0 of level l."""
+    off = np.zeros(3)
+    for k in range(1, l + 1):
+        lo = wl.boxes[k - 1][0]
+        for a in range(wl.D):
+            off[a] += lo[a] / float(2 ** (k - 1))
+    return off
+
+
+def node_positions(wl: Workload, l: int) -> np.ndarray:
+    """[3, n] level-0 coordinates of the dense nodes of level l, x fastest."""
+    d = wl.dims(l)
+    off = level_origin(wl, l)
+    h = 1.0 / 2 ** l
+    z, y, x = np.meshgrid(np.arange(d[2]), np.arange(d[1]), np.arange(d[0]), indexing="ij")
+    pos = np.stack([off[0] + h * x.ravel(), off[1] + h * y.ravel(), off[2] + h * z.ravel()])
+    if wl.D == 2:
+        pos[2] = 0.0
+    return pos
+
+
+def _min_image(d: np.ndarray, L: float) -> np.ndarray:
+    return d - L * np.round(d / L)
+
+
+def initial_fields(wl: Workload, l: int) -> Tuple[np.ndarray, np.ndarray]:
+    """(rho[n], u[D, n]) of the analytic initial state on level l."""
+    pos = node_positions(wl, l)
+    n = pos.shape[1]
+    rho = np.ones(n)
+    u = np.zeros((3, n))
+    for a in range(3):
+        u[a] += wl.background[a] if a < len(wl.background) else 0.0
+    L = [float(wl.n0[a]) if a < wl.D else 1.0 for a in range(3)]
+    for v in wl.vortices:
+        dx = _min_image(pos[0] - v["xc"], L[0])
+        dy = _min_image(pos[1] - v["yc"], L[1])
+        r2 = (dx * dx + dy * dy) / (v["Rc"] ** 2)
+        g = np.exp(-0.5 * r2)
+        u[0] += -v["eps"] * (dy / v["Rc"]) * g
+        u[1] += v["eps"] * (dx / v["Rc"]) * g
+        rho *= np.exp(-(v["eps"] ** 2) / (2.0 * CS2) * np.exp(-r2))
+    for p in wl.pulses:
+        r2 = np.zeros(n)
+        for a in range(wl.D):
+            d = _min_image(pos[a] - p["c"][a], L[a])
+            r2 += d * d
+        rho *= 1.0 + p["A"] * np.exp(-r2 / (2.0 * p["Rc"] ** 2))
+    for rg in wl.rings:
+        u += _ring_velocity(pos, rg, L)
+    return rho, u[:wl.D].copy()
+
+
+def _ring_frame(axis):
+    n = np.asarray(axis, float)
+    n = n / np.linalg.norm(n)
+    t = np.array([1.0, 0.0, 0.0]) if abs(n[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = np.cross(n, t)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(n, e1)
+    return n, e1, e2
+
+
+def _ring_profile(r, z, R, s):
+    """(u_r, u_z) for the potential A(r,z) = (r/R) exp(-((r-R)^2+z^2)/(2 s^2)),
+    u = curl(A e_phi), with unit amplitude."""
+    E = np.exp(-((r - R) ** 2 + z ** 2) / (2.0 * s * s))
+    ur = (r / R) * E * z / (s * s)
+    uz = (E / R) * (2.0 - r * (r - R) / (s * s))
+    return ur, uz
+
+
+def _ring_velocity(pos, rg, L):
+    n, e1, e2 = _ring_frame(rg["axis"])
+    d = np.stack([_min_image(pos[a] - rg["c"][a], L[a]) for a in range(3)])
+    zc = n @ d
+    rvec = d - np.outer(n, zc)
+    r = np.sqrt((rvec * rvec).sum(0))
+    ur, uz = _ring_profile(r, zc, rg["R"], rg["core"])
+    # unit amplitude -> peak speed rg["peak"], peak taken on a fixed fine sample
+    rr, zz = np.meshgrid(np.linspace(0, 3 * rg["R"], 601), np.linspace(-3 * rg["R"], 3 * rg["R"], 601))
+    a, b = _ring_profile(rr, zz, rg["R"], rg["core"])
+    scale = rg["peak"] / np.sqrt(a * a + b * b).max()
+    safe = np.where(r > 1e-12, r, 1.0)
+    er = np.where(r > 1e-12, rvec / safe, 0.0)
+    return scale * (er * ur + np.outer(n, uz))
+
+
+# --------------------------------------------------------------------------
+# The configurations
+# --------------------------------------------------------------------------
+
+def _ring_probes(center, radius, count, D):
+    out = []
+    for k in range(count):
+        a = 2.0 * math.pi * k / count
+        p = [int(round(center[0] + radius * math.cos(a))), int(round(center[1] + radius * math.sin(a)))]
+        out.append(tuple(p[:D]))
+    return out
+
+
+def _sphere_probes(center, radius, count):
+    out = []
+    g = math.pi * (3.0 - math.sqrt(5.0))
+    for k in range(count):
+        z = 1.0 - 2.0 * (k + 0.5) / count
+        r = math.sqrt(1.0 - z * z)
+        t = g * k
+        out.append(tuple(int(round(center[a] + radius * v))
+                         for a, v in enumerate((r * math.cos(t), r * math.sin(t), z))))
+    return out
+
+
+def vortex_2level(seed: int = 1, n0: int = 128, steps: int = 200, coupling: int = 2) -> Workload:
+    """D2Q9 BGK FP64: periodic n0^2 with a centred n0/2 patch refined x2;
+    two barotropic vortices (Mach 0.1 background, strength 0.1 U0, radius 8)
+    positioned to cross the coarse->fine and fine->coarse faces; 16 probes."""
+    rng = np.random.default_rng(seed)
+    U0 = 0.1 * CS
+    jit = rng.uniform(-0.5, 0.5, size=2)
+    q = n0 // 4
+    c = n0 / 2.0
+    vort = [dict(xc=q - 6 + jit[0], yc=c + jit[1], eps=0.1 * U0, Rc=8.0),
+            dict(xc=3 * q - 6 + jit[0], yc=c + jit[1], eps=0.1 * U0, Rc=8.0)]
+    probes = _ring_probes((c, c), 0.375 * n0, 8, 2) + _ring_probes((c, c), 0.15625 * n0, 8, 2)
+    return Workload(name=f"vortex_2level_{n0}", lattice="D2Q9", n0=(n0, n0),
+                    boxes=[((q, q), (3 * q, 3 * q))], tau0=0.55, steps=steps, coupling=coupling,
+                    probes=probes, background=(U0, 0.0, 0.0), vortices=vort, seed=seed)
+
+
+def pulse_vortices_3level(seed: int = 2, n0: int = 2048, steps: int = 1000, coupling: int = 2,
+                          tau0: float = 0.55) -> Workload:
+    """D2Q9, 3 levels: periodic n0^2, nested x2 patch over 25% and x4 patch over
+    6.25% of the domain; Gaussian pulse (1e-3, half-width 6) plus 16 seeded
+    barotropic vortices (swirl Mach 0.05-0.2, radius 8); 16 probes."""
+    assert n0 % 16 == 0
+    rng = np.random.default_rng(seed)
+    q = n0 // 4
+    c = n0 / 2.0
+    vort = []
+    for _ in range(16):
+        xc, yc = rng.uniform(0, n0, size=2)
+        vort.append(dict(xc=float(xc), yc=float(yc), eps=float(rng.uniform(0.05, 0.2)) * CS, Rc=8.0))
+    pulses = [dict(c=(c, c, 0.0), A=1e-3, Rc=6.0)]
+    probes = _ring_probes((c, c), 0.375 * n0, 16, 2)
+    return Workload(name=f"pulse_vortices_3level_{n0}", lattice="D2Q9", n0=(n0, n0),
+                    boxes=[((q, q), (3 * q, 3 * q)), ((q, q), (3 * q, 3 * q))], tau0=tau0,
+                    steps=steps, coupling=coupling, probes=probes, vortices=vort, pulses=pulses,
+                    seed=seed)
+
+
+def pulse_ring_3d(seed: int = 3, n0: int = 256, steps: int = 500, coupling: int = 2,
+                  tau0: float = 0.52) -> Workload:
+    """D3Q19, 2 levels: periodic n0^3 with the central (n0/2)^3 region refined
+    x2; spherical pulse (1e-3, half-width 6) plus a vortex ring convected along
+    a seeded axis (background Mach 0.1, ring radius 12, core 3, peak 0.1 U0)."""
+    assert n0 % 8 == 0
+    rng = np.random.default_rng(seed)
+    q = n0 // 4
+    c = n0 / 2.0
+    axis = rng.normal(size=3)
+    axis /= np.linalg.norm(axis)
+    U0 = 0.1 * CS
+    R = min(12.0, n0 / 10.0)
+    rings = [dict(c=tuple(c - 0.3 * n0 * axis), axis=tuple(axis), R=R, core=R / 4.0, peak=0.1 * U0)]
+    pulses = [dict(c=(c, c, c), A=1e-3, Rc=min(6.0, n0 / 16.0))]
+    probes = _sphere_probes((c, c, c), 0.46875 * n0, 16)
+    return Workload(name=f"pulse_ring_3d_{n0}", lattice="D3Q19", n0=(n0, n0, n0),
+                    boxes=[((q, q, q), (3 * q, 3 * q, 3 * q))], tau0=tau0, steps=steps,
+                    coupling=coupling, probes=probes, background=tuple(U0 * axis), rings=rings,
+                    pulses=pulses, seed=seed)
+
+
+def uniform_state(lattice: str, n0, boxes, rho0: float = 1.0, u0=(0.0, 0.0, 0.0), tau0: float = 0.6,
+                  coupling: int = 2, steps: int = 10) -> Workload:
+    """A uniform state (rest or uniform flow) on any mesh."""
+    return Workload(name="uniform", lattice=lattice, n0=tuple(n0), boxes=list(boxes), tau0=tau0,
+                    steps=steps, coupling=coupling, background=tuple(u0), pulses=[])
