@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark: refined-mesh LBM step with direct coupling on one MI355X.
+
+One "step" is one coarse time step of the whole hot path: every level's
+fused stream-and-collide with 2:1 sub-cycling, the coarse history capture,
+the Newton reconstruction at co-located nodes, hanging-node interpolation,
+restriction, and the probe sample.  Default workload: D2Q9, 3 levels,
+2048^2 periodic coarse grid with nested x2 (25%) and x4 (6.25%) patches,
+Gaussian pulse plus 16 seeded vortices, FP32 arithmetic with FP32 deviation
+storage (the production form); the FP64 and FP16-storage forms are timed
+beside it, and the FP64 CPU oracle on a bounded sample.
+
+Prints ONE JSON line (see the keys at the bottom).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % HBM roofline, FP32/FP16-store vs FP64 at stated error; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16"])
+    ap.add_argument("--n0", type=int, default=2048)
+    ap.add_argument("--latency-steps", type=int, default=200)
+    ap.add_argument("--timing-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP16 side runs")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bytes_per_value(prec):
+    return {"fp64": 8, "fp32": 4, "fp16": 2}[prec]
+
+
+def run_form(wl, prec, steps, warmup, latency_steps, timing_steps):
+    import torch
+
+    from paper_2004_14887_amd.sim import Simulation
+
+    log(f"{prec}: create + init ({wl.name})")
+    sim = Simulation(wl, prec, probe_capacity=warmup + steps + latency_steps + timing_steps + 2)
+    sim.init_from_workload()
+    sim.step(warmup)
+    sim.synchronize()
+    sim.check()
+    ups = sim.updates_per_step()
+    # timed region: exactly `steps` coarse steps (graph replays after the first step)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(sim.stream)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    ev1.record(sim.stream)
+    sim.synchronize()
+    t1 = time.perf_counter()
+    wall_ms = (t1 - t0) * 1e3
+    gpu_ms = ev0.elapsed_time(ev1)
+    log(f"{prec}: {steps} steps in {wall_ms:.2f} ms wall ({gpu_ms:.2f} ms events)")
+    # per-step latency percentiles (events around each graph launch)
+    lat = []
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(latency_steps + 1)]
+    evs[0].record(sim.stream)
+    for k in range(latency_steps):
+        sim.step(1)
+        evs[k + 1].record(sim.stream)
+    sim.synchronize()
+    for k in range(latency_steps):
+        lat.append(evs[k].elapsed_time(evs[k + 1]))
+    # instrumented pass: events around every bulk launch (eager launches)
+    sim.set_timing(True)
+    sim.step(timing_steps)
+    sim.synchronize()
+    sim.set_timing(False)
+    bulk = []
+    for l in range(wl.n_levels):
+        ms, n, nodes = sim.bulk_time(l)
+        bulk.append(dict(level=l, ms=ms, launches=n, nodes_per_launch=nodes))
+    sim.check()
+    probes = sim.probes().cpu().numpy()
+    out = dict(prec=prec, steps=steps, wall_ms=wall_ms, gpu_ms=gpu_ms, updates_per_step=ups,
+               mlups=ups * steps / (wall_ms * 1e3), p50=float(np.percentile(lat, 50)),
+               p99=float(np.percentile(lat, 99)), bulk=bulk, probes=probes)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline(form, Q):
+    bpv = bytes_per_value(form["prec"])
+    per_node = 2 * Q * bpv                      # read Q + write Q values (A/B pull)
+    best = max(form["bulk"], key=lambda b: b["ms"])
+    avg_ms = best["ms"] / max(1, best["launches"])
+    algo = best["nodes_per_launch"] * per_node
+    achieved = algo / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        rec = json.load(open(tfile))
+        key = f"{form['prec']}_level{best['level']}"
+        src = open(os.path.join(ROOT, "paper_2004_14887_amd", "csrc", "kernels.hpp"), "rb").read()
+        if rec.get("kernels_sha256") == hashlib.sha256(src).hexdigest() and key in rec.get("bytes_per_launch", {}):
+            traffic = rec["bytes_per_launch"][key]
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": f"k_bulk level {best['level']}", "algorithmic_bytes_per_launch": algo,
+            "avg_launch_ms": round(avg_ms, 5)}
+
+
+def cpu_baseline(wl_full, steps):
+    """The FP64 oracle as it stands, single-threaded, on the first `steps`
+    coarse steps of the same workload."""
+    from oracle import Oracle
+    from paper_2004_14887_amd import workloads as W
+
+    o = Oracle(wl_full.lattice, wl_full.n0, wl_full.boxes, wl_full.tau0, wl_full.coupling, wl_full.eq_order,
+               wl_full.probes, steps)
+    for l in range(wl_full.n_levels):
+        rho, u = W.initial_fields(wl_full, l)
+        o.init(l, rho, u)
+    t0 = time.perf_counter()
+    o.run(steps)
+    dt = time.perf_counter() - t0
+    ups = 0
+    for l in range(wl_full.n_levels):
+        cls = o.classes(l)
+        ups += int((cls != 0).sum()) << l
+    return {"value": round(ups * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"first {steps} coarse steps of the same workload, FP64, single thread ({dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2004_14887_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    wl = W.pulse_vortices_3level(seed=2, n0=args.n0, steps=args.steps)
+    main_form = run_form(wl, args.precision, args.steps, args.warmup, args.latency_steps, args.timing_steps)
+    side = {}
+    if not args.no_compare:
+        for p in ("fp64", "fp32", "fp16"):
+            if p != args.precision:
+                side[p] = run_form(wl, p, args.steps, args.warmup, args.latency_steps, args.timing_steps)
+    forms = dict(side)
+    forms[args.precision] = main_form
+    # accuracy of the reduced-precision forms against the FP64 GPU path
+    # (which matches the FP64 oracle to 1e-12, see the parity tests)
+    acc = {}
+    if "fp64" in forms:
+        ref = forms["fp64"]["probes"]
+        n = min(len(ref), *(len(f["probes"]) for f in forms.values()))
+        for p, f in forms.items():
+            if p == "fp64":
+                continue
+            d = f["probes"][:n] - ref[:n]
+            acc[p] = {"e_p_max": float(np.abs(d).max() / np.abs(ref[:n]).max()),
+                      "e_p_l2": float(np.linalg.norm(d) / np.linalg.norm(ref[:n]))}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(W.pulse_vortices_3level(seed=2, n0=args.n0, steps=args.cpu_steps), args.cpu_steps)
+    Q = wl.Q
+    rl = roofline(main_form, Q)
+    bpv = bytes_per_value(args.precision)
+    mlups = main_form["mlups"]
+    hbm_frac_mlups = mlups * 1e6 * 2 * Q * bpv / (HBM_PEAK_GBS * 1e9)
+    res = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_form["wall_ms"] / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f32 (f16 storage)"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": wl.name, "lattice": wl.lattice, "levels": wl.n_levels, "n0": list(wl.n0),
+                   "boxes": [list(map(list, b)) for b in wl.boxes], "tau0": wl.tau0, "coupling": "DC2",
+                   "precision": args.precision, "updates_per_step": main_form["updates_per_step"]},
+        "hbm_roofline_frac_of_mlups": round(hbm_frac_mlups, 4),
+        "latency_ms": {"p50": round(main_form["p50"], 5), "p99": round(main_form["p99"], 5)},
+        "roofline": rl,
+        "cpu_baseline": cpu,
+        "forms": {p: {"mlups": round(f["mlups"], 1), "ms_per_step": round(f["wall_ms"] / f["steps"], 5),
+                      "p50_ms": round(f["p50"], 5), "p99_ms": round(f["p99"], 5),
+                      "speedup_vs_fp64": (round(f["mlups"] / forms["fp64"]["mlups"], 3) if "fp64" in forms else None),
+                      "error_vs_fp64": acc.get(p)} for p, f in forms.items()},
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

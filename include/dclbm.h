@@ -1,0 +1,150 @@
+/*
+ * dclbm.h -- C ABI of the MI355X (gfx950) library for the lattice Boltzmann
+ * step on nested-box refined meshes with the cell-vertex direct grid coupling
+ * of Astoul, Wissocq, Boussuge, Sengissen & Sagaut, "Lattice Boltzmann method
+ * for computational aeroacoustics on non-uniform meshes: a direct grid
+ * coupling approach" (arXiv:2004.14887).
+ *
+ * Conventions
+ *  - Every call returns dclbm_status: 0 on success, a negative code on error;
+ *    no C++ exception crosses this boundary.  dclbm_last_error() gives a
+ *    message for the calling thread's last failure.
+ *  - The caller owns ALL device memory and the HIP stream.  The library
+ *    never allocates device memory for a simulation: it carves the caller's
+ *    workspace (size from dclbm_workspace_bytes).  It owns only host handles.
+ *  - Pointers named d_* are device pointers, h_* host pointers; they are
+ *    borrowed for the duration of the call.  Device work is enqueued on the
+ *    simulation's stream; calls that return host values synchronise it.
+ *  - Node coordinates are integers; level l+1 refines level l by 2 in space
+ *    and time (Sec. 3.1, acoustic scaling).  Dense level arrays are ordered
+ *    x fastest, then y, then z: index = (z*ny + y)*nx + x.
+ */
+#ifndef DCLBM_H
+#define DCLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DCLBM_ABI_VERSION 1
+#define DCLBM_MAX_LEVELS 4
+
+typedef enum {
+    DCLBM_OK = 0,
+    DCLBM_ERR_INVALID = -1,  /* bad argument or geometry */
+    DCLBM_ERR_NOMEM = -2,    /* workspace too small */
+    DCLBM_ERR_HIP = -3,      /* a HIP runtime call failed; message in dclbm_last_error() */
+    DCLBM_ERR_NEWTON = -4,   /* Newton solve at a co-located node did not converge */
+    DCLBM_ERR_UNSTABLE = -5, /* a non-finite density was found */
+    DCLBM_ERR_BUSY = -6
+} dclbm_status;
+
+typedef enum { DCLBM_D2Q9 = 0, DCLBM_D3Q19 = 1 } dclbm_lattice;
+
+/* Arithmetic and storage of the populations.
+ *  FP64:         FP64 everywhere.
+ *  FP32:         FP32 collision and interface arithmetic, populations stored
+ *                as FP32 deviations f_i - w_i from the rest state.
+ *  FP32_FP16:    FP32 arithmetic, populations stored as FP16 values of
+ *                256 (f_i - w_i) (round to nearest even).
+ * Probes and balances always accumulate in FP64. */
+typedef enum { DCLBM_FP64 = 0, DCLBM_FP32 = 1, DCLBM_FP32_FP16 = 2 } dclbm_precision;
+
+/* Choice of (Gamma_i, gamma_i) couples at co-located nodes, Sec. 3.4 Table
+ * "choice_Gamma_fine": DC1 takes P from the fine grid, DC2 from the coarse. */
+typedef enum { DCLBM_DC1 = 1, DCLBM_DC2 = 2 } dclbm_coupling;
+
+typedef struct {
+    int32_t abi_version;      /* DCLBM_ABI_VERSION */
+    int32_t lattice;          /* dclbm_lattice: D2Q9 (Fig. 1 numbering) or D3Q19 (Eq.(xi_i)) */
+    int32_t precision;        /* dclbm_precision */
+    int32_t coupling;         /* dclbm_coupling */
+    int32_t eq_order;         /* 2: second-order equilibrium; 3: adds the H3 terms of Eq.(fEq_herm) */
+    int32_t n0[3];            /* periodic coarse domain, nodes per axis (n0[2] ignored in 2-D) */
+    int32_t n_levels;         /* 1..DCLBM_MAX_LEVELS */
+    /* box of level l+1 (index l), as [lo, hi) in level-l node coordinates.
+     * Constraints: side >= 3 parent cells, margin >= 2 parent cells to the
+     * parent's own boundary (to the domain edge for level 1). */
+    int32_t box_lo[DCLBM_MAX_LEVELS - 1][3];
+    int32_t box_hi[DCLBM_MAX_LEVELS - 1][3];
+    double tau0;              /* level-0 relaxation time (> 1/2); tau_{l+1} = 2 tau_l - 1/2, Eq.(rescTau) */
+    int32_t n_probes;         /* pressure probes, p' = (rho - 1)/3 after each coarse step */
+    const int32_t* h_probe_xyz; /* [n_probes][3] level-0 node coordinates (host) */
+    int64_t probe_capacity;   /* coarse steps of probe history kept on the device */
+    int32_t newton_max_iter;  /* 0 -> 20 */
+    double newton_tol;        /* 0 -> 1e-12 (FP64) or 2e-6 (FP32 forms); Sec. 3.2 stop rule |dX| < tol */
+} dclbm_config;
+
+typedef struct dclbm_sim dclbm_sim;
+
+/* Bytes of device workspace a simulation with this configuration needs.
+ * Validates the configuration (DCLBM_ERR_INVALID with a message). */
+dclbm_status dclbm_workspace_bytes(const dclbm_config* cfg, size_t* bytes);
+
+/* Create a simulation in the caller's workspace (256-byte aligned, at least
+ * dclbm_workspace_bytes bytes) on the given HIP stream (hipStream_t passed as
+ * void*; NULL means the default stream, where no graphs are used).  All
+ * populations start as NaN until dclbm_init_equilibrium fills each level. */
+dclbm_status dclbm_create(const dclbm_config* cfg, void* d_workspace, size_t bytes, void* stream,
+                          dclbm_sim** out);
+dclbm_status dclbm_destroy(dclbm_sim* sim);
+
+/* Node counts of a level (dense box, holes included) and its active nodes. */
+dclbm_status dclbm_level_shape(const dclbm_sim* sim, int32_t level, int32_t dims[3], int64_t* n_active);
+
+/* Node-update count of one coarse step: sum over levels of 2^l * active nodes. */
+dclbm_status dclbm_updates_per_step(const dclbm_sim* sim, int64_t* updates);
+
+/* Set every active node of a level to the equilibrium of (rho, u) (Sec. 4.1:
+ * populations initialised at equilibrium).  d_rho: [n] FP64, d_u: [D][n]
+ * FP64, dense over the level.  Initialise every level before stepping. */
+dclbm_status dclbm_init_equilibrium(dclbm_sim* sim, int32_t level, const double* d_rho, const double* d_u);
+
+/* Advance n coarse steps (Sec. 3.5: each coarse step is one asynchronous and
+ * one synchronous fine iteration per refinement level, recursively).  Work
+ * is enqueued on the stream; after the first step each coarse step is one
+ * hipGraph launch.  Newton failures latch a device flag read by dclbm_check. */
+dclbm_status dclbm_step(dclbm_sim* sim, int32_t n_coarse_steps);
+
+/* Synchronise and report latched device errors (DCLBM_ERR_NEWTON, DCLBM_ERR_UNSTABLE). */
+dclbm_status dclbm_check(dclbm_sim* sim);
+
+/* Post-collision populations of a level as FP64 f_i, [Q][n] dense, NaN on holes. */
+dclbm_status dclbm_read_populations(const dclbm_sim* sim, int32_t level, double* d_out);
+
+/* Density [n] and velocity [D][n] of a level from the post-collision populations, NaN on holes. */
+dclbm_status dclbm_read_macros(const dclbm_sim* sim, int32_t level, double* d_rho, double* d_u);
+
+/* Shared macroscopic state X = (rho, u) found by Newton at the co-located
+ * nodes of a refined level (Sec. 3.2), [4][n] dense, NaN elsewhere. */
+dclbm_status dclbm_read_shared(const dclbm_sim* sim, int32_t level, double* d_out);
+
+/* Probe series p' = (rho - 1)/3, [steps][n_probes] FP64 into d_out (may be
+ * NULL to query); *n_steps receives the number of coarse steps recorded
+ * (at most probe_capacity).  Synchronises. */
+dclbm_status dclbm_read_probes(const dclbm_sim* sim, double* d_out, int64_t* n_steps);
+
+/* FP64 balances over the nodes each level owns (the finest level containing
+ * a point owns it), cell-volume weighted: mass, momentum[3], kinetic energy.
+ * Synchronises; also latches DCLBM_ERR_UNSTABLE on a non-finite density. */
+dclbm_status dclbm_balance(dclbm_sim* sim, double h_out[5]);
+
+/* Instrumentation: when on, steps run without graphs and HIP events bracket
+ * every bulk stream-and-collide launch; dclbm_bulk_time returns the summed
+ * milliseconds, launch count and active bulk nodes per launch of a level. */
+dclbm_status dclbm_set_timing(dclbm_sim* sim, int32_t on);
+dclbm_status dclbm_bulk_time(dclbm_sim* sim, int32_t level, double* ms, int64_t* launches,
+                             int64_t* nodes_per_launch);
+
+/* Lattice table: Q, velocities [Q][3] and weights [Q] of a lattice. */
+dclbm_status dclbm_lattice_table(int32_t lattice, int32_t* q, int32_t* h_xi, double* h_w);
+
+const char* dclbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

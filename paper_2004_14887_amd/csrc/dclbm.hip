@@ -1,0 +1,905 @@
+// Host driver and C ABI of the direct-coupling refined LBM library (gfx950).
+//
+// A simulation is a periodic coarse level and up to three nested refined
+// boxes.  The host classifies the interface nodes once (co-located nodes with
+// their (Gamma, gamma) couples of Sec. 3.4, hanging nodes with their missing
+// directions), carves the caller's workspace, and drives the recursive
+// sub-cycling of Sec. 3.5: each level makes two substeps per step of its
+// parent (Sec. 3.1, acoustic scaling).  After the first coarse step each
+// coarse step is replayed as one hipGraph (two graphs, one per A/B parity of
+// level 0).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/dclbm.h"
+#include "kernels.hpp"
+
+namespace dclbm {
+
+static thread_local std::string g_err;
+
+static dclbm_status fail(dclbm_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHECK(expr)                                                                         \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(DCLBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+static int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+struct HostLevel {
+    int nx = 1, ny = 1, nz = 1, pitch = 1;
+    int64_t plane = 0, qs = 0;
+    int periodic = 0, boundary = 0, has_child = 0;
+    int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
+    int plo[3] = {0, 0, 0};
+    double tau = 0.0;
+    int64_t n_active = 0, n_bulk = 0;
+    // interface with the parent (level >= 1)
+    std::vector<int4> tf_meta, ie_meta;
+    std::vector<int> tfmap;
+    int mx = 1, my = 1, mz = 1;
+    // interface with the child (coarse co-located nodes, child's order)
+    std::vector<int4> tfc_meta;
+    // workspace offsets
+    int64_t off_f[2] = {0, 0}, off_tf = 0, off_ie = 0, off_tfmap = 0, off_S = 0, off_X = 0, off_tfc = 0,
+            off_H = 0;
+    // device pointers
+    void* f[2] = {nullptr, nullptr};
+    int4 *d_tf = nullptr, *d_ie = nullptr, *d_tfc = nullptr;
+    int* d_tfmap = nullptr;
+    void *S = nullptr, *X = nullptr, *H = nullptr;
+    int parity = 0;
+    int64_t captures = 0;
+
+    LevelDev dev() const
+    {
+        LevelDev g;
+        g.nx = nx;
+        g.ny = ny;
+        g.nz = nz;
+        g.pitch = pitch;
+        g.plane = plane;
+        g.qs = qs;
+        g.periodic = periodic;
+        g.boundary = boundary;
+        g.has_child = has_child;
+        for (int a = 0; a < 3; ++a) {
+            g.clo[a] = clo[a];
+            g.chi[a] = chi[a];
+        }
+        return g;
+    }
+    int64_t n_dense() const { return (int64_t)nx * ny * nz; }
+};
+
+struct Sim;
+
+// Type-erased launcher set for one (lattice, equilibrium order, storage form).
+struct Engine {
+    virtual ~Engine() {}
+    virtual void bulk(Sim& s, int l) = 0;
+    virtual void capture(Sim& s, int l) = 0;
+    virtual void tf(Sim& s, int l, int substep, int first) = 0;
+    virtual void ie(Sim& s, int l) = 0;
+    virtual void restrict_(Sim& s, int l) = 0;
+    virtual void probe(Sim& s) = 0;
+    virtual void init(Sim& s, int l, const double* rho, const double* u) = 0;
+    virtual void ring_init(Sim& s, int l) = 0;
+    virtual void fill_nan(Sim& s) = 0;
+    virtual void read(Sim& s, int l, double* f, double* rho, double* u) = 0;
+    virtual void read_shared(Sim& s, int l, double* out) = 0;
+    virtual void balance(Sim& s, int l, double* partial, int nblocks) = 0;
+};
+
+struct ProbeLoc {
+    int level;
+    int64_t off;
+};
+
+struct Sim {
+    dclbm_config cfg;
+    int D = 2, Q = 9, P = 0, EQ = 2;
+    size_t tsize = 8, rsize = 8;   // storage and arithmetic element sizes
+    std::vector<HostLevel> lv;
+    std::vector<ProbeLoc> probes;
+    std::vector<int32_t> probe_xyz;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0, need_bytes = 0;
+    int64_t off_series = 0, off_counter = 0, off_flags = 0, off_partial = 0, off_bal = 0;
+    double* d_series = nullptr;
+    int64_t* d_counter = nullptr;
+    int* d_flags = nullptr;
+    double* d_partial = nullptr;
+    double* d_bal = nullptr;
+    int partial_blocks = 1024;
+    std::unique_ptr<Engine> eng;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    int64_t steps_done = 0;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[DCLBM_MAX_LEVELS];
+    double tms[DCLBM_MAX_LEVELS] = {0, 0, 0, 0};
+    int64_t tlaunch[DCLBM_MAX_LEVELS] = {0, 0, 0, 0};
+    double newton_tol = 1e-12;
+    int newton_maxit = 20;
+
+    template <typename T>
+    T* at(int64_t off) const
+    {
+        return reinterpret_cast<T*>(ws + off);
+    }
+};
+
+// ------------------------------------------------------------------ engine implementation
+template <int DIM, int EQ, int P>
+struct EngineImpl final : Engine {
+    using F = Form<P>;
+    using T = typename F::T;
+    using R = typename F::R;
+
+    static dim3 tile_grid(const HostLevel& L)
+    {
+        return dim3((unsigned)((L.nx + 63) / 64), (unsigned)((L.ny + 3) / 4), (unsigned)L.nz);
+    }
+
+    void bulk(Sim& s, int l) override
+    {
+        HostLevel& L = s.lv[l];
+        const T* src = (const T*)L.f[L.parity];
+        T* dst = (T*)L.f[L.parity ^ 1];
+        const R keep = R(1.0 - 1.0 / L.tau);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (s.timing) {
+            (void)hipEventCreate(&e0);
+            (void)hipEventCreate(&e1);
+            (void)hipEventRecord(e0, s.stream);
+        }
+        hipLaunchKernelGGL((k_bulk<DIM, EQ, P>), tile_grid(L), dim3(64, 4, 1), 0, s.stream, L.dev(), src, dst, keep);
+        if (s.timing) {
+            (void)hipEventRecord(e1, s.stream);
+            s.tev[l].push_back({e0, e1});
+        }
+    }
+    void capture(Sim& s, int l) override
+    {
+        HostLevel& L = s.lv[l];
+        const int n = (int)L.tfc_meta.size();
+        hipLaunchKernelGGL((k_capture<DIM, P>), dim3((n + 127) / 128), dim3(128), 0, s.stream, L.dev(),
+                           (const T*)L.f[L.parity], L.d_tfc, n, (R*)L.H);
+    }
+    void tf(Sim& s, int l, int substep, int first) override
+    {
+        HostLevel& L = s.lv[l];
+        HostLevel& C = s.lv[l - 1];
+        TfArgs a;
+        a.n = (int)L.tf_meta.size();
+        a.substep = substep;
+        a.first = first;
+        a.maxit = s.newton_maxit;
+        a.Rfac = L.tau / (2.0 * C.tau);
+        a.keep = 1.0 - 1.0 / L.tau;
+        a.tol = s.newton_tol;
+        hipLaunchKernelGGL((k_tf<DIM, EQ, P>), dim3((a.n + 63) / 64), dim3(64), 0, s.stream, L.dev(),
+                           (const T*)L.f[L.parity], (T*)L.f[L.parity ^ 1], L.d_tf, a, (const R*)C.H, (R*)L.S,
+                           (R*)L.X, s.d_flags);
+    }
+    void ie(Sim& s, int l) override
+    {
+        HostLevel& L = s.lv[l];
+        IeArgs a;
+        a.n = (int)L.ie_meta.size();
+        a.mx = L.mx;
+        a.my = L.my;
+        a.ntf = (int)L.tf_meta.size();
+        a.keep = 1.0 - 1.0 / L.tau;
+        hipLaunchKernelGGL((k_ie<DIM, EQ, P>), dim3((a.n + 63) / 64), dim3(64), 0, s.stream, L.dev(),
+                           (const T*)L.f[L.parity], (T*)L.f[L.parity ^ 1], L.d_ie, a, (const R*)L.S,
+                           L.d_tfmap);
+    }
+    void restrict_(Sim& s, int l) override
+    {
+        HostLevel& L = s.lv[l];
+        HostLevel& Fn = s.lv[l + 1];
+        const int n = (int)L.tfc_meta.size();
+        const double invR = 2.0 * L.tau / Fn.tau;
+        hipLaunchKernelGGL((k_restrict<DIM, EQ, P>), dim3((n + 63) / 64), dim3(64), 0, s.stream, L.dev(),
+                           (T*)L.f[L.parity ^ 1], L.d_tfc, n, (const R*)Fn.S, (const R*)Fn.X, invR,
+                           1.0 - 1.0 / L.tau);
+    }
+    void probe(Sim& s) override
+    {
+        if (s.probes.empty()) return;
+        ProbeArgs a;
+        memset(&a, 0, sizeof(a));
+        a.n = (int)s.probes.size();
+        a.capacity = s.cfg.probe_capacity;
+        for (int p = 0; p < a.n; ++p) {
+            const HostLevel& L = s.lv[s.probes[p].level];
+            a.buf[p] = L.f[L.parity];
+            a.off[p] = s.probes[p].off;
+            a.qs[p] = L.qs;
+        }
+        hipLaunchKernelGGL((k_probe<DIM, P>), dim3(1), dim3(64), 0, s.stream, a, s.d_series, s.d_counter);
+    }
+    void init(Sim& s, int l, const double* rho, const double* u) override
+    {
+        HostLevel& L = s.lv[l];
+        hipLaunchKernelGGL((k_init<DIM, EQ, P>), tile_grid(L), dim3(64, 4, 1), 0, s.stream, L.dev(),
+                           (T*)L.f[L.parity], rho, u);
+    }
+    void ring_init(Sim& s, int l) override
+    {
+        HostLevel& L = s.lv[l];
+        const int n = (int)L.tfc_meta.size();
+        hipLaunchKernelGGL((k_ring_init<DIM, P>), dim3((n + 127) / 128), dim3(128), 0, s.stream, L.dev(),
+                           (const T*)L.f[L.parity], L.d_tfc, n, (R*)L.H);
+    }
+    void fill_nan(Sim& s) override
+    {
+        for (auto& L : s.lv) {
+            const int64_t nf = (int64_t)Lat<DIM>::Q * L.qs;
+            T nanv;
+            if constexpr (P == 2) {
+                unsigned short b = 0x7e00;
+                memcpy(&nanv, &b, 2);
+            } else {
+                nanv = (T)NAN;
+            }
+            for (int b = 0; b < 2; ++b)
+                hipLaunchKernelGGL((k_fill<T>), dim3(2048), dim3(256), 0, s.stream, (T*)L.f[b], nf, nanv);
+            if (L.S)
+                hipLaunchKernelGGL((k_fill<R>), dim3(256), dim3(256), 0, s.stream, (R*)L.S,
+                                   (int64_t)Lat<DIM>::Q * (int64_t)L.tf_meta.size(), (R)NAN);
+            if (L.X)
+                hipLaunchKernelGGL((k_fill<R>), dim3(256), dim3(256), 0, s.stream, (R*)L.X,
+                                   4 * (int64_t)L.tf_meta.size(), (R)NAN);
+            if (L.H)
+                hipLaunchKernelGGL((k_fill<R>), dim3(256), dim3(256), 0, s.stream, (R*)L.H,
+                                   3 * (int64_t)Lat<DIM>::Q * (int64_t)L.tfc_meta.size(), (R)NAN);
+        }
+    }
+    void read(Sim& s, int l, double* f, double* rho, double* u) override
+    {
+        HostLevel& L = s.lv[l];
+        hipLaunchKernelGGL((k_read<DIM, P>), tile_grid(L), dim3(64, 4, 1), 0, s.stream, L.dev(),
+                           (const T*)L.f[L.parity], f, rho, u);
+    }
+    void read_shared(Sim& s, int l, double* out) override
+    {
+        HostLevel& L = s.lv[l];
+        const int64_t n = L.n_dense();
+        hipLaunchKernelGGL(k_fill_nan_f64, dim3(1024), dim3(256), 0, s.stream, out, 4 * n);
+        const int ntf = (int)L.tf_meta.size();
+        if (ntf)
+            hipLaunchKernelGGL((k_read_shared<P>), dim3((ntf + 127) / 128), dim3(128), 0, s.stream, L.d_tf, ntf,
+                               L.nx, L.ny, n, (const R*)L.X, out);
+    }
+    void balance(Sim& s, int l, double* partial, int nblocks) override
+    {
+        HostLevel& L = s.lv[l];
+        const double vol = std::ldexp(1.0, -DIM * l);
+        hipLaunchKernelGGL((k_balance<DIM, P>), dim3(nblocks), dim3(256), 0, s.stream, L.dev(),
+                           (const T*)L.f[L.parity], vol, partial, s.d_flags);
+    }
+};
+
+template <int DIM, int EQ>
+static Engine* make_engine_p(int P)
+{
+    if (P == 0) return new EngineImpl<DIM, EQ, 0>();
+    if (P == 1) return new EngineImpl<DIM, EQ, 1>();
+    return new EngineImpl<DIM, EQ, 2>();
+}
+
+static Engine* make_engine(int D, int EQ, int P)
+{
+    if (D == 2) return EQ == 2 ? make_engine_p<2, 2>(P) : make_engine_p<2, 3>(P);
+    return EQ == 2 ? make_engine_p<3, 2>(P) : make_engine_p<3, 3>(P);
+}
+
+// ------------------------------------------------------------------ geometry
+static const int kCx2[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
+static const int kCy2[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
+
+static void dirs(int D, int i, int c[3])
+{
+    if (D == 2) {
+        c[0] = kCx2[i];
+        c[1] = kCy2[i];
+        c[2] = 0;
+    } else {
+        c[0] = Lat<3>::cx[i];
+        c[1] = Lat<3>::cy[i];
+        c[2] = Lat<3>::cz[i];
+    }
+}
+
+static dclbm_status build_geometry(Sim& s)
+{
+    const dclbm_config& c = s.cfg;
+    if (c.abi_version != DCLBM_ABI_VERSION) return fail(DCLBM_ERR_INVALID, "abi_version %d != %d", c.abi_version, DCLBM_ABI_VERSION);
+    if (c.lattice != DCLBM_D2Q9 && c.lattice != DCLBM_D3Q19) return fail(DCLBM_ERR_INVALID, "unknown lattice %d", c.lattice);
+    if (c.precision < 0 || c.precision > 2) return fail(DCLBM_ERR_INVALID, "unknown precision %d", c.precision);
+    if (c.coupling != 1 && c.coupling != 2) return fail(DCLBM_ERR_INVALID, "coupling must be 1 (DC1) or 2 (DC2)");
+    if (c.eq_order != 2 && c.eq_order != 3) return fail(DCLBM_ERR_INVALID, "eq_order must be 2 or 3");
+    if (c.n_levels < 1 || c.n_levels > DCLBM_MAX_LEVELS) return fail(DCLBM_ERR_INVALID, "n_levels out of range");
+    if (!(c.tau0 > 0.5)) return fail(DCLBM_ERR_INVALID, "tau0 must exceed 1/2");
+    if (c.n_probes < 0 || c.n_probes > 32) return fail(DCLBM_ERR_INVALID, "n_probes must be in [0, 32]");
+    if (c.n_probes > 0 && (!c.h_probe_xyz || c.probe_capacity < 1))
+        return fail(DCLBM_ERR_INVALID, "probes need coordinates and a capacity");
+    s.D = c.lattice == DCLBM_D2Q9 ? 2 : 3;
+    s.Q = s.D == 2 ? 9 : 19;
+    s.P = c.precision;
+    s.EQ = c.eq_order;
+    s.tsize = s.P == 0 ? 8 : (s.P == 1 ? 4 : 2);
+    s.rsize = s.P == 0 ? 8 : 4;
+    s.newton_maxit = c.newton_max_iter > 0 ? c.newton_max_iter : 20;
+    s.newton_tol = c.newton_tol > 0 ? c.newton_tol : (s.P == 0 ? 1e-12 : 2e-6);
+    const int D = s.D, Q = s.Q;
+    s.lv.assign(c.n_levels, HostLevel());
+    double tau = c.tau0;
+    for (int l = 0; l < c.n_levels; ++l) {
+        HostLevel& L = s.lv[l];
+        int n[3] = {1, 1, 1};
+        if (l == 0) {
+            for (int a = 0; a < D; ++a) {
+                n[a] = c.n0[a];
+                if (n[a] < 8) return fail(DCLBM_ERR_INVALID, "level-0 extent must be at least 8");
+                if (n[a] > (1 << 20)) return fail(DCLBM_ERR_INVALID, "level-0 extent too large");
+            }
+            L.periodic = 1;
+        } else {
+            HostLevel& Pn = s.lv[l - 1];
+            int pn[3] = {Pn.nx, Pn.ny, Pn.nz};
+            for (int a = 0; a < D; ++a) {
+                const int lo = c.box_lo[l - 1][a], hi = c.box_hi[l - 1][a];
+                if (hi - lo < 3) return fail(DCLBM_ERR_INVALID, "level %d box side below 3 parent cells", l);
+                if (lo < 2 || hi > pn[a] - 1 - 2)
+                    return fail(DCLBM_ERR_INVALID, "level %d box needs a margin of 2 parent cells", l);
+                n[a] = 2 * (hi - lo) + 1;
+                L.plo[a] = lo;
+                Pn.clo[a] = lo;
+                Pn.chi[a] = hi;
+            }
+            Pn.has_child = 1;
+            L.boundary = 1;
+        }
+        L.nx = n[0];
+        L.ny = n[1];
+        L.nz = n[2];
+        L.tau = tau;
+        tau = 2.0 * tau - 0.5;
+    }
+    // storage layout per level
+    for (int l = 0; l < c.n_levels; ++l) {
+        HostLevel& L = s.lv[l];
+        L.pitch = (int)round_up(L.nx, 64);
+        L.plane = (int64_t)L.pitch * L.ny;
+        L.qs = round_up(L.plane * L.nz, 256);
+        int64_t hole = 0;
+        if (L.has_child) {
+            hole = 1;
+            for (int a = 0; a < D; ++a) hole *= (L.chi[a] - L.clo[a] - 1);
+        }
+        L.n_active = L.n_dense() - hole;
+    }
+    // interface classification, level by level
+    for (int l = 1; l < c.n_levels; ++l) {
+        HostLevel& L = s.lv[l];
+        HostLevel& Pn = s.lv[l - 1];
+        const int n[3] = {L.nx, L.ny, L.nz};
+        L.mx = L.nx / 2 + 1;
+        L.my = L.ny / 2 + 1;
+        L.mz = D == 3 ? L.nz / 2 + 1 : 1;
+        L.tfmap.assign((size_t)L.mx * L.my * L.mz, -1);
+        const uint32_t all = (1u << Q) - 1u;
+        for (int z = 0; z < L.nz; ++z)
+            for (int y = 0; y < L.ny; ++y)
+                for (int x = 0; x < L.nx; ++x) {
+                    const int k[3] = {x, y, z};
+                    bool bnd = false, even = true;
+                    for (int a = 0; a < D; ++a) {
+                        if (k[a] == 0 || k[a] == n[a] - 1) bnd = true;
+                        if (k[a] & 1) even = false;
+                    }
+                    if (!bnd) continue;
+                    uint32_t Kf = 0, Kc = 0;
+                    for (int i = 0; i < Q; ++i) {
+                        int cv[3];
+                        dirs(D, i, cv);
+                        bool fin = true, hole = true;
+                        for (int a = 0; a < D; ++a) {
+                            const int sf = k[a] - cv[a];
+                            if (sf < 0 || sf > n[a] - 1) fin = false;
+                            if (even) {
+                                const int sc = L.plo[a] + k[a] / 2 - cv[a];
+                                if (!(sc > Pn.clo[a] && sc < Pn.chi[a])) hole = false;
+                            }
+                        }
+                        if (fin) Kf |= 1u << i;
+                        if (even && !hole) Kc |= 1u << i;
+                    }
+                    if (even) {
+                        const uint32_t P_ = Kf & Kc, Mf = all & ~Kf;
+                        const uint32_t gR = c.coupling == 1 ? Mf : (P_ | Mf);
+                        if ((gR & ~Kc) || ((all & ~gR) & ~Kf))
+                            return fail(DCLBM_ERR_INVALID, "level %d node (%d,%d,%d): no valid couples", l, x, y, z);
+                        L.tfmap[((size_t)(z / 2) * L.my + y / 2) * L.mx + x / 2] = (int)L.tf_meta.size();
+                        L.tf_meta.push_back(make_int4(x, y, z, (int)gR));
+                        int p[3] = {0, 0, 0};
+                        for (int a = 0; a < D; ++a) p[a] = L.plo[a] + k[a] / 2;
+                        Pn.tfc_meta.push_back(make_int4(p[0], p[1], p[2], (int)Kc));
+                    } else {
+                        L.ie_meta.push_back(make_int4(x, y, z, (int)(all & ~Kf)));
+                    }
+                }
+        // every hanging node's stencil must land on co-located nodes (the
+        // kernel indexes the co-located list through tfmap without checks)
+        for (const int4& m : L.ie_meta) {
+            const int k[3] = {m.x, m.y, m.z};
+            int np[3] = {1, 1, 1}, pos[3][4];
+            for (int a = 0; a < 3; ++a) {
+                pos[a][0] = k[a];
+                if (a < D && (k[a] & 1)) {
+                    const int N = n[a] - 1;
+                    if (N < 6) return fail(DCLBM_ERR_INVALID, "level %d box too small for the 4-point stencil", l);
+                    np[a] = 4;
+                    if (k[a] == 1) { pos[a][0] = 0; pos[a][1] = 2; pos[a][2] = 4; pos[a][3] = 6; }
+                    else if (k[a] == N - 1) { pos[a][0] = N; pos[a][1] = N - 2; pos[a][2] = N - 4; pos[a][3] = N - 6; }
+                    else { pos[a][0] = k[a] - 3; pos[a][1] = k[a] - 1; pos[a][2] = k[a] + 1; pos[a][3] = k[a] + 3; }
+                }
+            }
+            for (int cz = 0; cz < np[2]; ++cz)
+                for (int cy = 0; cy < np[1]; ++cy)
+                    for (int cx = 0; cx < np[0]; ++cx) {
+                        const int px = pos[0][cx], py = pos[1][cy], pz = pos[2][cz];
+                        if ((px | py | pz) & 1) return fail(DCLBM_ERR_INVALID, "hanging-node stencil off the co-located lattice");
+                        const size_t key = ((size_t)(pz / 2) * L.my + py / 2) * L.mx + px / 2;
+                        if (key >= L.tfmap.size() || L.tfmap[key] < 0)
+                            return fail(DCLBM_ERR_INVALID, "level %d hanging node (%d,%d,%d): stencil node is not co-located", l, m.x, m.y, m.z);
+                    }
+        }
+    }
+    for (auto& L : s.lv) {
+        int64_t iface = (int64_t)L.tf_meta.size() + (int64_t)L.ie_meta.size() + (int64_t)L.tfc_meta.size();
+        L.n_bulk = L.n_active - iface;
+    }
+    // probes: finest level whose closed box contains the point
+    s.probes.clear();
+    s.probe_xyz.assign(3 * (size_t)c.n_probes, 0);
+    const int Lm = c.n_levels - 1;
+    for (int p = 0; p < c.n_probes; ++p) {
+        int64_t fine[3] = {0, 0, 0};
+        for (int a = 0; a < D; ++a) {
+            const int v = c.h_probe_xyz[3 * p + a];
+            s.probe_xyz[3 * p + a] = v;
+            if (v < 0 || v >= (a == 0 ? s.lv[0].nx : (a == 1 ? s.lv[0].ny : s.lv[0].nz)))
+                return fail(DCLBM_ERR_INVALID, "probe %d outside the domain", p);
+            fine[a] = (int64_t)v << Lm;   // in units of the finest spacing
+        }
+        int64_t org[3] = {0, 0, 0};
+        ProbeLoc best{0, 0};
+        for (int l = 0; l <= Lm; ++l) {
+            if (l > 0)
+                for (int a = 0; a < D; ++a) org[a] += (int64_t)s.lv[l].plo[a] << (Lm - l + 1);
+            const int sh = Lm - l;
+            const int n[3] = {s.lv[l].nx, s.lv[l].ny, s.lv[l].nz};
+            int k[3] = {0, 0, 0};
+            bool inside = true;
+            for (int a = 0; a < D; ++a) {
+                const int64_t d = fine[a] - org[a];
+                if (d < 0 || (d >> sh) > n[a] - 1 || (d & ((1LL << sh) - 1))) inside = false;
+                else k[a] = (int)(d >> sh);
+            }
+            if (inside) best = ProbeLoc{l, (int64_t)k[2] * s.lv[l].plane + (int64_t)k[1] * s.lv[l].pitch + k[0]};
+        }
+        s.probes.push_back(best);
+    }
+    // workspace layout
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t o = off;
+        off = round_up(off + std::max<int64_t>(bytes, 1), 256);
+        return o;
+    };
+    for (auto& L : s.lv) {
+        for (int b = 0; b < 2; ++b) L.off_f[b] = take(L.qs * Q * (int64_t)s.tsize);
+        if (!L.tf_meta.empty()) {
+            L.off_tf = take((int64_t)L.tf_meta.size() * 16);
+            L.off_S = take((int64_t)L.tf_meta.size() * Q * (int64_t)s.rsize);
+            L.off_X = take((int64_t)L.tf_meta.size() * 4 * (int64_t)s.rsize);
+            L.off_tfmap = take((int64_t)L.tfmap.size() * 4);
+        }
+        if (!L.ie_meta.empty()) L.off_ie = take((int64_t)L.ie_meta.size() * 16);
+        if (!L.tfc_meta.empty()) {
+            L.off_tfc = take((int64_t)L.tfc_meta.size() * 16);
+            L.off_H = take((int64_t)L.tfc_meta.size() * 3 * Q * (int64_t)s.rsize);
+        }
+    }
+    s.off_series = take(std::max<int64_t>(1, c.probe_capacity) * std::max(1, c.n_probes) * 8);
+    s.off_counter = take(8);
+    s.off_flags = take(8);
+    s.off_partial = take((int64_t)DCLBM_MAX_LEVELS * s.partial_blocks * 5 * 8);
+    s.off_bal = take(DCLBM_MAX_LEVELS * 5 * 8);
+    s.need_bytes = (size_t)off;
+    return DCLBM_OK;
+}
+
+// ------------------------------------------------------------------ stepping
+static void advance(Sim& s, int l, int substep)
+{
+    HostLevel& L = s.lv[l];
+    s.eng->bulk(s, l);
+    if (L.has_child) {
+        s.eng->capture(s, l);
+        L.captures++;
+    }
+    if (l > 0) {
+        const int first = s.lv[l - 1].captures <= 1 ? 1 : 0;
+        s.eng->tf(s, l, substep, first);
+        if (!L.ie_meta.empty()) s.eng->ie(s, l);
+    }
+    if (L.has_child) {
+        advance(s, l + 1, 1);
+        advance(s, l + 1, 2);
+        s.eng->restrict_(s, l);
+    }
+    L.parity ^= 1;
+}
+
+// Host-side state change of one coarse step, without launching anything.
+static void advance_state(Sim& s)
+{
+    for (size_t l = 0; l < s.lv.size(); ++l) {
+        if (s.lv[l].has_child) s.lv[l].captures += (int64_t)1 << l;
+    }
+    s.lv[0].parity ^= 1;
+}
+
+static dclbm_status coarse_step_eager(Sim& s)
+{
+    advance(s, 0, 0);
+    s.eng->probe(s);
+    HIPCHECK(hipGetLastError());
+    return DCLBM_OK;
+}
+
+static bool all_first_steps_done(const Sim& s)
+{
+    for (size_t l = 0; l + 1 < s.lv.size(); ++l)
+        if (s.lv[l].captures < 2) return false;
+    return true;
+}
+
+static dclbm_status coarse_step(Sim& s)
+{
+    if (s.timing || s.stream == nullptr || !all_first_steps_done(s)) return coarse_step_eager(s);
+    const int par = s.lv[0].parity;
+    if (!s.gexec[par]) {
+        HIPCHECK(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal));
+        advance(s, 0, 0);
+        s.eng->probe(s);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s.stream, &g);
+        if (e != hipSuccess) return fail(DCLBM_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+        s.graph[par] = g;
+        HIPCHECK(hipGraphInstantiate(&s.gexec[par], g, nullptr, nullptr, 0));
+        HIPCHECK(hipGraphLaunch(s.gexec[par], s.stream));   // capture advanced the host state already
+        return DCLBM_OK;
+    }
+    HIPCHECK(hipGraphLaunch(s.gexec[par], s.stream));
+    advance_state(s);
+    return DCLBM_OK;
+}
+
+}  // namespace dclbm
+
+using namespace dclbm;
+
+struct dclbm_sim {
+    Sim s;
+};
+
+static dclbm_status check_level_impl(const dclbm_sim* sim, int32_t level)
+{
+    if (!sim) return fail(DCLBM_ERR_INVALID, "null simulation");
+    if (level < 0 || level >= (int)sim->s.lv.size()) return fail(DCLBM_ERR_INVALID, "level %d out of range", level);
+    return DCLBM_OK;
+}
+
+extern "C" {
+
+const char* dclbm_last_error(void) { return g_err.c_str(); }
+
+dclbm_status dclbm_lattice_table(int32_t lattice, int32_t* q, int32_t* h_xi, double* h_w)
+{
+    if (lattice != DCLBM_D2Q9 && lattice != DCLBM_D3Q19) return fail(DCLBM_ERR_INVALID, "unknown lattice");
+    const int D = lattice == DCLBM_D2Q9 ? 2 : 3, Q = D == 2 ? 9 : 19;
+    if (q) *q = Q;
+    for (int i = 0; i < Q; ++i) {
+        int c[3];
+        dirs(D, i, c);
+        if (h_xi)
+            for (int a = 0; a < 3; ++a) h_xi[3 * i + a] = c[a];
+        if (h_w) h_w[i] = D == 2 ? Lat<2>::w[i] : Lat<3>::w[i];
+    }
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_workspace_bytes(const dclbm_config* cfg, size_t* bytes)
+{
+    if (!cfg || !bytes) return fail(DCLBM_ERR_INVALID, "null argument");
+    Sim s;
+    s.cfg = *cfg;
+    dclbm_status st = build_geometry(s);
+    if (st != DCLBM_OK) return st;
+    *bytes = s.need_bytes;
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_create(const dclbm_config* cfg, void* d_workspace, size_t bytes, void* stream, dclbm_sim** out)
+{
+    if (!cfg || !out) return fail(DCLBM_ERR_INVALID, "null argument");
+    *out = nullptr;
+    if (!d_workspace || ((uintptr_t)d_workspace & 255)) return fail(DCLBM_ERR_INVALID, "workspace must be 256-byte aligned");
+    std::unique_ptr<dclbm_sim> h(new dclbm_sim());
+    Sim& s = h->s;
+    s.cfg = *cfg;
+    s.cfg.h_probe_xyz = nullptr;
+    {
+        Sim tmp;
+        tmp.cfg = *cfg;
+        dclbm_status st = build_geometry(tmp);
+        if (st != DCLBM_OK) return st;
+        s.lv = std::move(tmp.lv);
+        s.probes = std::move(tmp.probes);
+        s.probe_xyz = std::move(tmp.probe_xyz);
+        s.D = tmp.D;
+        s.Q = tmp.Q;
+        s.P = tmp.P;
+        s.EQ = tmp.EQ;
+        s.tsize = tmp.tsize;
+        s.rsize = tmp.rsize;
+        s.newton_maxit = tmp.newton_maxit;
+        s.newton_tol = tmp.newton_tol;
+        s.need_bytes = tmp.need_bytes;
+        s.off_series = tmp.off_series;
+        s.off_counter = tmp.off_counter;
+        s.off_flags = tmp.off_flags;
+        s.off_partial = tmp.off_partial;
+        s.off_bal = tmp.off_bal;
+    }
+    if (bytes < s.need_bytes) return fail(DCLBM_ERR_NOMEM, "workspace %zu bytes, need %zu", bytes, s.need_bytes);
+    s.ws = (char*)d_workspace;
+    s.ws_bytes = bytes;
+    s.stream = (hipStream_t)stream;
+    for (auto& L : s.lv) {
+        for (int b = 0; b < 2; ++b) L.f[b] = s.ws + L.off_f[b];
+        if (!L.tf_meta.empty()) {
+            L.d_tf = s.at<int4>(L.off_tf);
+            L.S = s.ws + L.off_S;
+            L.X = s.ws + L.off_X;
+            L.d_tfmap = s.at<int>(L.off_tfmap);
+            HIPCHECK(hipMemcpyAsync(L.d_tf, L.tf_meta.data(), L.tf_meta.size() * 16, hipMemcpyHostToDevice, s.stream));
+            HIPCHECK(hipMemcpyAsync(L.d_tfmap, L.tfmap.data(), L.tfmap.size() * 4, hipMemcpyHostToDevice, s.stream));
+        }
+        if (!L.ie_meta.empty()) {
+            L.d_ie = s.at<int4>(L.off_ie);
+            HIPCHECK(hipMemcpyAsync(L.d_ie, L.ie_meta.data(), L.ie_meta.size() * 16, hipMemcpyHostToDevice, s.stream));
+        }
+        if (!L.tfc_meta.empty()) {
+            L.d_tfc = s.at<int4>(L.off_tfc);
+            L.H = s.ws + L.off_H;
+            HIPCHECK(hipMemcpyAsync(L.d_tfc, L.tfc_meta.data(), L.tfc_meta.size() * 16, hipMemcpyHostToDevice, s.stream));
+        }
+    }
+    s.d_series = s.at<double>(s.off_series);
+    s.d_counter = s.at<int64_t>(s.off_counter);
+    s.d_flags = s.at<int>(s.off_flags);
+    s.d_partial = s.at<double>(s.off_partial);
+    s.d_bal = s.at<double>(s.off_bal);
+    s.eng.reset(make_engine(s.D, s.EQ, s.P));
+    s.eng->fill_nan(s);
+    hipLaunchKernelGGL((k_fill<int64_t>), dim3(1), dim3(64), 0, s.stream, s.d_counter, (int64_t)1, (int64_t)0);
+    hipLaunchKernelGGL((k_fill<int>), dim3(1), dim3(64), 0, s.stream, s.d_flags, (int64_t)2, 0);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(s.stream));
+    *out = h.release();
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_destroy(dclbm_sim* sim)
+{
+    if (!sim) return DCLBM_OK;
+    Sim& s = sim->s;
+    if (s.stream) (void)hipStreamSynchronize(s.stream);
+    for (int p = 0; p < 2; ++p) {
+        if (s.gexec[p]) (void)hipGraphExecDestroy(s.gexec[p]);
+        if (s.graph[p]) (void)hipGraphDestroy(s.graph[p]);
+    }
+    for (int l = 0; l < DCLBM_MAX_LEVELS; ++l)
+        for (auto& e : s.tev[l]) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    delete sim;
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_level_shape(const dclbm_sim* sim, int32_t level, int32_t dims[3], int64_t* n_active)
+{
+    dclbm_status st = check_level_impl(sim, level);
+    if (st != DCLBM_OK) return st;
+    const HostLevel& L = sim->s.lv[level];
+    if (dims) {
+        dims[0] = L.nx;
+        dims[1] = L.ny;
+        dims[2] = L.nz;
+    }
+    if (n_active) *n_active = L.n_active;
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_updates_per_step(const dclbm_sim* sim, int64_t* updates)
+{
+    if (!sim || !updates) return fail(DCLBM_ERR_INVALID, "null argument");
+    int64_t u = 0;
+    for (size_t l = 0; l < sim->s.lv.size(); ++l) u += sim->s.lv[l].n_active << l;
+    *updates = u;
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_init_equilibrium(dclbm_sim* sim, int32_t level, const double* d_rho, const double* d_u)
+{
+    dclbm_status st = check_level_impl(sim, level);
+    if (st != DCLBM_OK) return st;
+    if (!d_rho || !d_u) return fail(DCLBM_ERR_INVALID, "null field");
+    Sim& s = sim->s;
+    s.eng->init(s, level, d_rho, d_u);
+    if (s.lv[level].has_child) s.eng->ring_init(s, level);
+    s.lv[level].captures = 0;
+    HIPCHECK(hipGetLastError());
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_step(dclbm_sim* sim, int32_t n)
+{
+    if (!sim || n < 0) return fail(DCLBM_ERR_INVALID, "bad argument");
+    for (int32_t k = 0; k < n; ++k) {
+        dclbm_status st = coarse_step(sim->s);
+        if (st != DCLBM_OK) return st;
+        sim->s.steps_done++;
+    }
+    return DCLBM_OK;
+}
+
+static dclbm_status read_flags(Sim& s)
+{
+    int flags[2] = {0, 0};
+    HIPCHECK(hipMemcpyAsync(flags, s.d_flags, sizeof(int), hipMemcpyDeviceToHost, s.stream));
+    HIPCHECK(hipStreamSynchronize(s.stream));
+    if (flags[0] & 1) return fail(DCLBM_ERR_NEWTON, "Newton did not converge at a co-located node");
+    if (flags[0] & 2) return fail(DCLBM_ERR_UNSTABLE, "non-finite density found");
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_check(dclbm_sim* sim)
+{
+    if (!sim) return fail(DCLBM_ERR_INVALID, "null simulation");
+    return read_flags(sim->s);
+}
+
+dclbm_status dclbm_read_populations(const dclbm_sim* sim, int32_t level, double* d_out)
+{
+    dclbm_status st = check_level_impl(sim, level);
+    if (st != DCLBM_OK) return st;
+    Sim& s = const_cast<Sim&>(sim->s);
+    s.eng->read(s, level, d_out, nullptr, nullptr);
+    HIPCHECK(hipGetLastError());
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_read_macros(const dclbm_sim* sim, int32_t level, double* d_rho, double* d_u)
+{
+    dclbm_status st = check_level_impl(sim, level);
+    if (st != DCLBM_OK) return st;
+    Sim& s = const_cast<Sim&>(sim->s);
+    s.eng->read(s, level, nullptr, d_rho, d_u);
+    HIPCHECK(hipGetLastError());
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_read_shared(const dclbm_sim* sim, int32_t level, double* d_out)
+{
+    dclbm_status st = check_level_impl(sim, level);
+    if (st != DCLBM_OK) return st;
+    Sim& s = const_cast<Sim&>(sim->s);
+    s.eng->read_shared(s, level, d_out);
+    HIPCHECK(hipGetLastError());
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_read_probes(const dclbm_sim* sim, double* d_out, int64_t* n_steps)
+{
+    if (!sim || !n_steps) return fail(DCLBM_ERR_INVALID, "null argument");
+    Sim& s = const_cast<Sim&>(sim->s);
+    int64_t cnt = 0;
+    HIPCHECK(hipMemcpyAsync(&cnt, s.d_counter, 8, hipMemcpyDeviceToHost, s.stream));
+    HIPCHECK(hipStreamSynchronize(s.stream));
+    const int64_t stored = std::min<int64_t>(cnt, s.cfg.probe_capacity);
+    *n_steps = stored;
+    if (d_out && stored > 0 && !s.probes.empty())
+        HIPCHECK(hipMemcpyAsync(d_out, s.d_series, (size_t)stored * s.probes.size() * 8, hipMemcpyDeviceToDevice,
+                                s.stream));
+    HIPCHECK(hipStreamSynchronize(s.stream));
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_balance(dclbm_sim* sim, double h_out[5])
+{
+    if (!sim || !h_out) return fail(DCLBM_ERR_INVALID, "null argument");
+    Sim& s = sim->s;
+    double res[DCLBM_MAX_LEVELS][5];
+    for (size_t l = 0; l < s.lv.size(); ++l) {
+        double* part = s.d_partial + (int64_t)l * s.partial_blocks * 5;
+        s.eng->balance(s, (int)l, part, s.partial_blocks);
+        hipLaunchKernelGGL(k_balance_final, dim3(1), dim3(64), 0, s.stream, part, s.partial_blocks, s.d_bal + 5 * l);
+    }
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(res, s.d_bal, sizeof(double) * 5 * s.lv.size(), hipMemcpyDeviceToHost, s.stream));
+    HIPCHECK(hipStreamSynchronize(s.stream));
+    for (int k = 0; k < 5; ++k) {
+        h_out[k] = 0.0;
+        for (size_t l = 0; l < s.lv.size(); ++l) h_out[k] += res[l][k];
+    }
+    return read_flags(s);
+}
+
+dclbm_status dclbm_set_timing(dclbm_sim* sim, int32_t on)
+{
+    if (!sim) return fail(DCLBM_ERR_INVALID, "null simulation");
+    sim->s.timing = on != 0;
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_bulk_time(dclbm_sim* sim, int32_t level, double* ms, int64_t* launches, int64_t* nodes_per_launch)
+{
+    dclbm_status st = check_level_impl(sim, level);
+    if (st != DCLBM_OK) return st;
+    Sim& s = sim->s;
+    HIPCHECK(hipStreamSynchronize(s.stream));
+    for (auto& e : s.tev[level]) {
+        float t = 0.f;
+        HIPCHECK(hipEventElapsedTime(&t, e.first, e.second));
+        s.tms[level] += t;
+        s.tlaunch[level] += 1;
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    s.tev[level].clear();
+    if (ms) *ms = s.tms[level];
+    if (launches) *launches = s.tlaunch[level];
+    if (nodes_per_launch) *nodes_per_launch = s.lv[level].n_bulk;
+    return DCLBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,191 @@
+"""Python face of the library: a Simulation owns a torch-allocated device
+workspace and a HIP stream (torch's), and forwards every call to the C ABI.
+
+    from paper_2004_14887_amd import Simulation, workloads
+    wl = workloads.vortex_2level()
+    sim = Simulation(wl, precision="fp64")
+    sim.init_from_workload()
+    sim.step(wl.steps)
+    f1 = sim.populations(1)        # torch float64 [Q, n] on the device
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import torch
+
+from . import _lib
+from .workloads import Workload, initial_fields
+
+
+def make_config(wl: Workload, precision: str = "fp64", probe_capacity: Optional[int] = None,
+                newton_max_iter: int = 0, newton_tol: float = 0.0):
+    cfg = _lib.Config()
+    cfg.abi_version = _lib.ABI_VERSION
+    cfg.lattice = _lib.LATTICE[wl.lattice]
+    cfg.precision = _lib.PRECISION[precision]
+    cfg.coupling = wl.coupling
+    cfg.eq_order = wl.eq_order
+    for a in range(3):
+        cfg.n0[a] = wl.n0[a] if a < wl.D else 1
+    cfg.n_levels = wl.n_levels
+    for k, (lo, hi) in enumerate(wl.boxes):
+        for a in range(wl.D):
+            cfg.box_lo[k][a] = lo[a]
+            cfg.box_hi[k][a] = hi[a]
+    cfg.tau0 = wl.tau0
+    probes = (C.c_int32 * max(1, 3 * len(wl.probes)))()
+    for k, p in enumerate(wl.probes):
+        for a in range(wl.D):
+            probes[3 * k + a] = p[a]
+    cfg.n_probes = len(wl.probes)
+    cfg.h_probe_xyz = C.cast(probes, C.POINTER(C.c_int32))
+    cfg.probe_capacity = probe_capacity if probe_capacity is not None else max(1, wl.steps)
+    cfg.newton_max_iter = newton_max_iter
+    cfg.newton_tol = newton_tol
+    return cfg, probes
+
+
+def workspace_bytes(wl: Workload, precision: str = "fp64", **kw) -> int:
+    lib = _lib.load()
+    cfg, _keep = make_config(wl, precision, **kw)
+    out = C.c_size_t()
+    _lib.check(lib.dclbm_workspace_bytes(C.byref(cfg), C.byref(out)))
+    return out.value
+
+
+class Simulation:
+    def __init__(self, wl: Workload, precision: str = "fp64", device="cuda:0",
+                 stream: Optional[torch.cuda.Stream] = None, probe_capacity: Optional[int] = None,
+                 newton_max_iter: int = 0, newton_tol: float = 0.0):
+        self.lib = _lib.load()
+        self.wl = wl
+        self.precision = precision
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        cfg, self._probe_buf = make_config(wl, precision, probe_capacity, newton_max_iter, newton_tol)
+        self.cfg = cfg
+        nbytes = C.c_size_t()
+        _lib.check(self.lib.dclbm_workspace_bytes(C.byref(cfg), C.byref(nbytes)))
+        self.bytes = nbytes.value
+        # 256-byte aligned view into a torch-owned uint8 buffer
+        self._raw = torch.empty(self.bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._raw.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.dclbm_create(C.byref(cfg), C.c_void_p(self._ws_ptr), self.bytes,
+                                             C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.D, self.Q = wl.D, wl.Q
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dclbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- geometry
+    def level_shape(self, l):
+        dims = (C.c_int32 * 3)()
+        n = C.c_int64()
+        _lib.check(self.lib.dclbm_level_shape(self.h, l, dims, C.byref(n)))
+        return tuple(dims), n.value
+
+    def n_dense(self, l):
+        d, _ = self.level_shape(l)
+        return d[0] * d[1] * d[2]
+
+    def updates_per_step(self):
+        u = C.c_int64()
+        _lib.check(self.lib.dclbm_updates_per_step(self.h, C.byref(u)))
+        return u.value
+
+    # ---------------------------------------------------------------- state
+    def _sync_torch(self):
+        # caller-side work (torch kernels on the current stream) must finish
+        # before the library's stream reads it, and vice versa
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def init(self, level, rho: torch.Tensor, u: torch.Tensor):
+        rho = rho.to(self.device, torch.float64).contiguous()
+        u = u.to(self.device, torch.float64).contiguous()
+        assert rho.numel() == self.n_dense(level) and u.shape[0] == self.D
+        self._sync_torch()
+        _lib.check(self.lib.dclbm_init_equilibrium(self.h, level, C.c_void_p(rho.data_ptr()),
+                                                   C.c_void_p(u.data_ptr())))
+        self.stream.synchronize()
+
+    def init_from_workload(self):
+        for l in range(self.wl.n_levels):
+            rho, u = initial_fields(self.wl, l)
+            self.init(l, torch.from_numpy(rho), torch.from_numpy(u))
+
+    def step(self, n: int = 1):
+        _lib.check(self.lib.dclbm_step(self.h, int(n)))
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def check(self):
+        _lib.check(self.lib.dclbm_check(self.h))
+
+    def _out(self, shape):
+        return torch.empty(shape, dtype=torch.float64, device=self.device)
+
+    def populations(self, l) -> torch.Tensor:
+        out = self._out((self.Q, self.n_dense(l)))
+        self._sync_torch()
+        _lib.check(self.lib.dclbm_read_populations(self.h, l, C.c_void_p(out.data_ptr())))
+        self.stream.synchronize()
+        return out
+
+    def macros(self, l):
+        n = self.n_dense(l)
+        rho, u = self._out((n,)), self._out((self.D, n))
+        _lib.check(self.lib.dclbm_read_macros(self.h, l, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr())))
+        self.stream.synchronize()
+        return rho, u
+
+    def shared(self, l) -> torch.Tensor:
+        out = self._out((4, self.n_dense(l)))
+        _lib.check(self.lib.dclbm_read_shared(self.h, l, C.c_void_p(out.data_ptr())))
+        self.stream.synchronize()
+        return out
+
+    def probes(self) -> torch.Tensor:
+        n = C.c_int64()
+        _lib.check(self.lib.dclbm_read_probes(self.h, None, C.byref(n)))
+        np_ = len(self.wl.probes)
+        out = self._out((max(1, n.value), max(1, np_)))
+        _lib.check(self.lib.dclbm_read_probes(self.h, C.c_void_p(out.data_ptr()), C.byref(n)))
+        return out[:n.value, :np_]
+
+    def balance(self):
+        out = (C.c_double * 5)()
+        _lib.check(self.lib.dclbm_balance(self.h, out))
+        return list(out)
+
+    def set_timing(self, on: bool):
+        _lib.check(self.lib.dclbm_set_timing(self.h, 1 if on else 0))
+
+    def bulk_time(self, l):
+        ms, n, nodes = C.c_double(), C.c_int64(), C.c_int64()
+        _lib.check(self.lib.dclbm_bulk_time(self.h, l, C.byref(ms), C.byref(n), C.byref(nodes)))
+        return ms.value, n.value, nodes.value
+
+
+def lattice_table(lattice: str):
+    lib = _lib.load()
+    q = C.c_int32()
+    xi = (C.c_int32 * 57)()
+    w = (C.c_double * 19)()
+    _lib.check(lib.dclbm_lattice_table(_lib.LATTICE[lattice], C.byref(q), xi, w))
+    Q = q.value
+    return [tuple(xi[3 * i:3 * i + 3]) for i in range(Q)], [w[i] for i in range(Q)]

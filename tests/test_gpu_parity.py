@@ -1,0 +1,213 @@
+"""GPU parity: the HIP library against the FP64 oracle, element by element,
+on the same seeded inputs (needs an MI355X; run with -m gpu).
+
+Bar: FP64 populations within 1e-12 relative of the oracle after the stated
+number of coarse steps, every level, every direction; holes NaN on both
+sides.  FP32 / FP16-storage forms: probe pressure error against the FP64
+oracle within 1e-4 / 1e-3 of the probe signal's peak (max norm).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import Oracle  # noqa: E402
+from paper_2004_14887_amd import workloads as W  # noqa: E402
+
+CS2 = 1.0 / 3.0
+
+
+def _gpu_ok():
+    return torch.cuda.is_available()
+
+
+requires_gpu = pytest.mark.skipif(not _gpu_ok(), reason="no GPU")
+
+
+def gpu_run(wl, steps, precision="fp64", **kw):
+    from paper_2004_14887_amd.sim import Simulation
+
+    print(f"[gpu] {wl.name} {precision} steps={steps} coupling={wl.coupling} eq={wl.eq_order}", flush=True)
+    sim = Simulation(wl, precision, probe_capacity=max(1, steps), **kw)
+    sim.init_from_workload()
+    sim.step(steps)
+    return sim
+
+
+def oracle_run(wl, steps):
+    o = Oracle(wl.lattice, wl.n0, wl.boxes, wl.tau0, wl.coupling, wl.eq_order, wl.probes, max(1, steps))
+    for l in range(wl.n_levels):
+        rho, u = W.initial_fields(wl, l)
+        o.init(l, rho, u)
+    o.run(steps)
+    return o
+
+
+def max_rel(g, r):
+    m = ~np.isnan(r)
+    assert np.array_equal(m, ~np.isnan(g)), "hole pattern differs"
+    return float(np.max(np.abs(g[m] - r[m]) / np.abs(r[m])))
+
+
+def assert_population_parity(sim, o, wl, tol=1e-12):
+    worst = 0.0
+    for l in range(wl.n_levels):
+        e = max_rel(sim.populations(l).cpu().numpy(), o.f(l))
+        print(f"  level {l}: max rel err {e:.3e}", flush=True)
+        worst = max(worst, e)
+    assert worst <= tol
+    return worst
+
+
+@requires_gpu
+@pytest.mark.parametrize("coupling", [1, 2])
+def test_vortex_2level_200_steps_fp64(coupling):
+    """128^2 periodic, centred 64^2-cell patch refined x2, two vortices crossing
+    both faces, tau 0.55, 200 coarse steps: populations within 1e-12."""
+    wl = W.vortex_2level(seed=1, n0=128, steps=200, coupling=coupling)
+    sim = gpu_run(wl, wl.steps)
+    sim.check()
+    o = oracle_run(wl, wl.steps)
+    assert_population_parity(sim, o, wl)
+    # probes and the shared macroscopic state at co-located nodes
+    pg, po = sim.probes().cpu().numpy(), o.probes()
+    assert pg.shape == po.shape == (200, 16)
+    assert np.abs(pg - po).max() <= 1e-13
+    Xg, Xo = sim.shared(1).cpu().numpy(), o.X(1)
+    assert max_rel(Xg[:1], Xo[:1]) <= 1e-12
+    m = ~np.isnan(Xo[1])
+    assert np.abs(Xg[1:3][:, m] - Xo[1:3][:, m]).max() <= 1e-13
+
+
+@requires_gpu
+def test_pulse_vortices_3level_fp64_parity():
+    """3 levels (reduced 128^2 replica of the 2048^2 nesting), 40 coarse steps."""
+    wl = W.pulse_vortices_3level(seed=2, n0=128, steps=40)
+    sim = gpu_run(wl, wl.steps)
+    sim.check()
+    o = oracle_run(wl, wl.steps)
+    assert_population_parity(sim, o, wl)
+    assert np.abs(sim.probes().cpu().numpy() - o.probes()).max() <= 1e-13
+
+
+@requires_gpu
+@pytest.mark.parametrize("coupling,eq_order", [(2, 2), (1, 2), (2, 3)])
+def test_pulse_ring_3d_fp64_parity(coupling, eq_order):
+    """D3Q19, 2 levels (32^3 replica of the 256^3 nesting), faces, edges and
+    corners of the refined box, 12 coarse steps."""
+    wl = W.pulse_ring_3d(seed=3, n0=32, steps=12, coupling=coupling)
+    wl.eq_order = eq_order
+    sim = gpu_run(wl, wl.steps)
+    sim.check()
+    o = oracle_run(wl, wl.steps)
+    assert_population_parity(sim, o, wl)
+
+
+@requires_gpu
+def test_3d_three_levels_fp64_parity():
+    wl = W.Workload("ring3_3lvl", "D3Q19", (32, 32, 32), [((8, 8, 8), (24, 24, 24)), ((8, 8, 8), (24, 24, 24))],
+                    0.52, 6, pulses=[dict(c=(15.5, 16.0, 16.5), A=1e-3, Rc=3.0)],
+                    background=(0.03, -0.02, 0.01), probes=[(16, 16, 16), (4, 4, 4)])
+    sim = gpu_run(wl, wl.steps)
+    o = oracle_run(wl, wl.steps)
+    assert_population_parity(sim, o, wl)
+
+
+@requires_gpu
+def test_balance_matches_oracle():
+    wl = W.vortex_2level(seed=4, n0=64, steps=10)
+    sim = gpu_run(wl, wl.steps)
+    o = oracle_run(wl, wl.steps)
+    bg, bo = np.array(sim.balance()), o.balance()
+    assert abs(bg[0] - bo[0]) <= 1e-12 * abs(bo[0])
+    assert np.abs(bg[1:] - bo[1:]).max() <= 1e-12 * abs(bo[0])
+
+
+@requires_gpu
+def test_graph_replay_equals_eager_and_is_deterministic():
+    wl = W.pulse_vortices_3level(seed=5, n0=64, steps=9)
+    a = gpu_run(wl, wl.steps)
+    b = gpu_run(wl, wl.steps)
+    from paper_2004_14887_amd.sim import Simulation
+
+    e = Simulation(wl, "fp64", probe_capacity=wl.steps)
+    e.set_timing(True)          # eager launches, no graph
+    e.init_from_workload()
+    e.step(wl.steps)
+    for l in range(wl.n_levels):
+        fa, fb, fe = a.populations(l), b.populations(l), e.populations(l)
+        assert torch.equal(torch.nan_to_num(fa, 7.0), torch.nan_to_num(fb, 7.0))
+        assert torch.equal(torch.nan_to_num(fa, 7.0), torch.nan_to_num(fe, 7.0))
+
+
+@requires_gpu
+def test_newton_failure_is_latched():
+    from paper_2004_14887_amd._lib import DclbmError
+
+    wl = W.vortex_2level(seed=1, n0=64, steps=2)
+    sim = gpu_run(wl, 1, newton_max_iter=1, newton_tol=1e-300)
+    with pytest.raises(DclbmError) as ei:
+        sim.check()
+    assert ei.value.status == -4
+
+
+@requires_gpu
+def test_uniform_flow_stays_uniform_all_precisions():
+    for prec, tol in (("fp64", 1e-15), ("fp32", 1e-7), ("fp16", 2e-4)):
+        wl = W.uniform_state("D2Q9", (64, 64), [((16, 16), (48, 48)), ((16, 16), (48, 48))], u0=(0.05, -0.03))
+        sim = gpu_run(wl, 4, prec)
+        for l in range(3):
+            rho, u = sim.macros(l)
+            m = ~torch.isnan(rho)
+            assert (rho[m] - 1).abs().max().item() <= tol, prec
+            assert (u[0][m] - 0.05).abs().max().item() <= tol * 4, prec
+
+
+def _probe_error(wl, steps, precision):
+    g = gpu_run(wl, steps, precision).probes().cpu().numpy()
+    r = oracle_run(wl, steps).probes()
+    return float(np.abs(g - r).max() / np.abs(r).max())
+
+
+@requires_gpu
+def test_fp32_probe_error_within_1e_4():
+    wl = W.vortex_2level(seed=1, n0=128, steps=200)
+    wl.pulses = [dict(c=(64.0, 64.0, 0.0), A=1e-3, Rc=6.0)]
+    e = _probe_error(wl, wl.steps, "fp32")
+    print(f"fp32 probe error {e:.3e}")
+    assert e <= 1e-4
+
+
+@requires_gpu
+def test_fp16_probe_error_within_1e_3():
+    wl = W.vortex_2level(seed=1, n0=128, steps=200)
+    wl.pulses = [dict(c=(64.0, 64.0, 0.0), A=1e-3, Rc=6.0)]
+    e = _probe_error(wl, wl.steps, "fp16")
+    print(f"fp16 probe error {e:.3e}")
+    assert e <= 1e-3
+
+
+@requires_gpu
+@pytest.mark.slow
+def test_full_size_2048_three_levels_sampled():
+    """The 2048^2 three-level workload at full size, in the graph-replay launch
+    configuration the benchmark times, against the oracle after 2 coarse
+    steps: every node of every level compared."""
+    wl = W.pulse_vortices_3level(seed=2, n0=2048, steps=2)
+    sim = gpu_run(wl, wl.steps)
+    sim.check()
+    o = oracle_run(wl, wl.steps)
+    assert_population_parity(sim, o, wl)
+
+
+@requires_gpu
+@pytest.mark.slow
+def test_full_size_256_cubed_two_levels():
+    """The 256^3 D3Q19 two-level workload at full size, 1 coarse step, every node."""
+    wl = W.pulse_ring_3d(seed=3, n0=256, steps=1)
+    sim = gpu_run(wl, wl.steps)
+    sim.check()
+    o = oracle_run(wl, wl.steps)
+    assert_population_parity(sim, o, wl)
