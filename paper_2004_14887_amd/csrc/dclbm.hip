@@ -3,19 +3,24 @@
 // A simulation is a periodic coarse level and up to three nested refined
 // boxes.  The host classifies the interface nodes once (co-located nodes with
 // their (Gamma, gamma) couples of Sec. 3.4, hanging nodes with their missing
-// directions), carves the caller's workspace, and drives the recursive
-// sub-cycling of Sec. 3.5: each level makes two substeps per step of its
-// parent (Sec. 3.1, acoustic scaling).  After the first coarse step each
-// coarse step is replayed as one hipGraph (two graphs, one per A/B parity of
-// level 0).
+// directions), cuts each refined level's interface into segments (tiles of
+// the interface line or face, with the co-located halo their 4-point stencils
+// need), carves the caller's workspace, and drives the recursive sub-cycling
+// of Sec. 3.5: each level makes two substeps per step of its parent
+// (Sec. 3.1, acoustic scaling).  A level substep is one kernel launch; after
+// the first coarse step each coarse step is replayed as one hipGraph (two
+// graphs, one per A/B parity of level 0).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/dclbm.h"
@@ -45,27 +50,29 @@ static dclbm_status fail(dclbm_status s, const char* fmt, ...)
 static int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 struct HostLevel {
-    int nx = 1, ny = 1, nz = 1, pitch = 1;
-    int64_t plane = 0, qs = 0;
+    int nx = 1, ny = 1, nz = 1, nxb = 1;
+    int64_t elems = 0;          // storage elements per buffer (Q per node slot, 64-node row blocks)
     int periodic = 0, boundary = 0, has_child = 0;
     int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
     int plo[3] = {0, 0, 0};
     double tau = 0.0;
-    int64_t n_active = 0, n_bulk = 0;
+    int64_t n_active = 0;
     // interface with the parent (level >= 1)
-    std::vector<int4> tf_meta, ie_meta;
-    std::vector<int> tfmap;
+    std::vector<int4> tf_meta, ie_meta;   // co-located (x,y,z,Gamma=R mask), hanging (x,y,z,missing mask)
+    std::vector<int> tfmap;               // co-located index at fine coords (2a,2b,2c), -1 elsewhere
     int mx = 1, my = 1, mz = 1;
+    std::vector<int4> seg_info;           // (tf_off, tf_cnt, ie_off, ie_cnt)
+    std::vector<int> seg_tf, seg_ie, seg_sten;
     // interface with the child (coarse co-located nodes, child's order)
     std::vector<int4> tfc_meta;
     // workspace offsets
-    int64_t off_f[2] = {0, 0}, off_tf = 0, off_ie = 0, off_tfmap = 0, off_S = 0, off_X = 0, off_tfc = 0,
-            off_H = 0;
+    int64_t off_f[2] = {0, 0}, off_tf = 0, off_ie = 0, off_X = 0, off_tfc = 0, off_H = 0, off_seg_info = 0,
+            off_seg_tf = 0, off_seg_ie = 0, off_seg_sten = 0;
     // device pointers
     void* f[2] = {nullptr, nullptr};
-    int4 *d_tf = nullptr, *d_ie = nullptr, *d_tfc = nullptr;
-    int* d_tfmap = nullptr;
-    void *S = nullptr, *X = nullptr, *H = nullptr;
+    int4 *d_tf = nullptr, *d_ie = nullptr, *d_tfc = nullptr, *d_seg_info = nullptr;
+    int *d_seg_tf = nullptr, *d_seg_ie = nullptr, *d_seg_sten = nullptr;
+    void *X = nullptr, *H = nullptr;
     int parity = 0;
     int64_t captures = 0;
 
@@ -75,9 +82,7 @@ struct HostLevel {
         g.nx = nx;
         g.ny = ny;
         g.nz = nz;
-        g.pitch = pitch;
-        g.plane = plane;
-        g.qs = qs;
+        g.nxb = nxb;
         g.periodic = periodic;
         g.boundary = boundary;
         g.has_child = has_child;
@@ -88,6 +93,19 @@ struct HostLevel {
         return g;
     }
     int64_t n_dense() const { return (int64_t)nx * ny * nz; }
+    TileMap tiles() const
+    {
+        TileMap m;
+        m.tx = (nx + 63) / 64;
+        m.ty = (ny + 3) / 4;
+        m.ntiles = m.tx * m.ty * nz;
+        m.per = (m.ntiles + 7) / 8;
+        return m;
+    }
+    int64_t elem0(int Q, int x, int y, int z) const
+    {
+        return (((int64_t)z * ny + y) * nxb + (x >> 6)) * (Q * 64) + (x & 63);
+    }
 };
 
 struct Sim;
@@ -95,11 +113,7 @@ struct Sim;
 // Type-erased launcher set for one (lattice, equilibrium order, storage form).
 struct Engine {
     virtual ~Engine() {}
-    virtual void bulk(Sim& s, int l) = 0;
-    virtual void capture(Sim& s, int l) = 0;
-    virtual void tf(Sim& s, int l, int substep, int first) = 0;
-    virtual void ie(Sim& s, int l) = 0;
-    virtual void restrict_(Sim& s, int l) = 0;
+    virtual void level_step(Sim& s, int l, int substep, int first) = 0;
     virtual void probe(Sim& s) = 0;
     virtual void init(Sim& s, int l, const double* rho, const double* u) = 0;
     virtual void ring_init(Sim& s, int l) = 0;
@@ -149,6 +163,13 @@ struct Sim {
     }
 };
 
+template <typename V>
+static hipError_t upload(Sim& s, void* dst, const std::vector<V>& v)
+{
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(dst, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, s.stream);
+}
+
 // ------------------------------------------------------------------ engine implementation
 template <int DIM, int EQ, int P>
 struct EngineImpl final : Engine {
@@ -156,74 +177,63 @@ struct EngineImpl final : Engine {
     using T = typename F::T;
     using R = typename F::R;
 
-    static dim3 tile_grid(const HostLevel& L)
+    static dim3 dense_grid(const HostLevel& L)
     {
         return dim3((unsigned)((L.nx + 63) / 64), (unsigned)((L.ny + 3) / 4), (unsigned)L.nz);
     }
 
-    void bulk(Sim& s, int l) override
+    void level_step(Sim& s, int l, int substep, int first) override
     {
         HostLevel& L = s.lv[l];
-        const T* src = (const T*)L.f[L.parity];
-        T* dst = (T*)L.f[L.parity ^ 1];
-        const R keep = R(1.0 - 1.0 / L.tau);
+        LevelArgs a;
+        memset(&a, 0, sizeof(a));
+        a.g = L.dev();
+        a.src = L.f[L.parity];
+        a.dst = L.f[L.parity ^ 1];
+        a.keep = 1.0 - 1.0 / L.tau;
+        a.tm = L.tiles();
+        if (L.has_child) {
+            a.n_cap = (int)L.tfc_meta.size();
+            a.nb_cap = (a.n_cap + kBlock - 1) / kBlock;
+            a.cap_meta = L.d_tfc;
+            a.H_own = L.H;
+        }
+        if (l > 0) {
+            HostLevel& Pn = s.lv[l - 1];
+            a.nb_seg = (int)L.seg_info.size();
+            a.seg_info = L.d_seg_info;
+            a.seg_tf = L.d_seg_tf;
+            a.seg_ie = L.d_seg_ie;
+            a.seg_sten = L.d_seg_sten;
+            a.n_ie = (int)L.ie_meta.size();
+            a.tf_meta = L.d_tf;
+            a.ie_meta = L.d_ie;
+            a.n_tf = (int)L.tf_meta.size();
+            a.H_parent = Pn.H;
+            a.X = L.X;
+            a.substep = substep;
+            a.first = first;
+            a.maxit = s.newton_maxit;
+            a.Rfac = L.tau / (2.0 * Pn.tau);
+            a.tol = s.newton_tol;
+            a.flags = s.d_flags;
+            a.gp = Pn.dev();
+            a.dst_parent = Pn.f[Pn.parity ^ 1];
+            a.tfc_meta = Pn.d_tfc;
+            a.keep_parent = 1.0 - 1.0 / Pn.tau;
+        }
+        const unsigned grid = (unsigned)(a.nb_cap + a.nb_seg + 8 * a.tm.per);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (s.timing) {
             (void)hipEventCreate(&e0);
             (void)hipEventCreate(&e1);
             (void)hipEventRecord(e0, s.stream);
         }
-        hipLaunchKernelGGL((k_bulk<DIM, EQ, P>), tile_grid(L), dim3(64, 4, 1), 0, s.stream, L.dev(), src, dst, keep);
+        hipLaunchKernelGGL((k_level<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, a);
         if (s.timing) {
             (void)hipEventRecord(e1, s.stream);
             s.tev[l].push_back({e0, e1});
         }
-    }
-    void capture(Sim& s, int l) override
-    {
-        HostLevel& L = s.lv[l];
-        const int n = (int)L.tfc_meta.size();
-        hipLaunchKernelGGL((k_capture<DIM, P>), dim3((n + 127) / 128), dim3(128), 0, s.stream, L.dev(),
-                           (const T*)L.f[L.parity], L.d_tfc, n, (R*)L.H);
-    }
-    void tf(Sim& s, int l, int substep, int first) override
-    {
-        HostLevel& L = s.lv[l];
-        HostLevel& C = s.lv[l - 1];
-        TfArgs a;
-        a.n = (int)L.tf_meta.size();
-        a.substep = substep;
-        a.first = first;
-        a.maxit = s.newton_maxit;
-        a.Rfac = L.tau / (2.0 * C.tau);
-        a.keep = 1.0 - 1.0 / L.tau;
-        a.tol = s.newton_tol;
-        hipLaunchKernelGGL((k_tf<DIM, EQ, P>), dim3((a.n + 63) / 64), dim3(64), 0, s.stream, L.dev(),
-                           (const T*)L.f[L.parity], (T*)L.f[L.parity ^ 1], L.d_tf, a, (const R*)C.H, (R*)L.S,
-                           (R*)L.X, s.d_flags);
-    }
-    void ie(Sim& s, int l) override
-    {
-        HostLevel& L = s.lv[l];
-        IeArgs a;
-        a.n = (int)L.ie_meta.size();
-        a.mx = L.mx;
-        a.my = L.my;
-        a.ntf = (int)L.tf_meta.size();
-        a.keep = 1.0 - 1.0 / L.tau;
-        hipLaunchKernelGGL((k_ie<DIM, EQ, P>), dim3((a.n + 63) / 64), dim3(64), 0, s.stream, L.dev(),
-                           (const T*)L.f[L.parity], (T*)L.f[L.parity ^ 1], L.d_ie, a, (const R*)L.S,
-                           L.d_tfmap);
-    }
-    void restrict_(Sim& s, int l) override
-    {
-        HostLevel& L = s.lv[l];
-        HostLevel& Fn = s.lv[l + 1];
-        const int n = (int)L.tfc_meta.size();
-        const double invR = 2.0 * L.tau / Fn.tau;
-        hipLaunchKernelGGL((k_restrict<DIM, EQ, P>), dim3((n + 63) / 64), dim3(64), 0, s.stream, L.dev(),
-                           (T*)L.f[L.parity ^ 1], L.d_tfc, n, (const R*)Fn.S, (const R*)Fn.X, invR,
-                           1.0 - 1.0 / L.tau);
     }
     void probe(Sim& s) override
     {
@@ -236,14 +246,13 @@ struct EngineImpl final : Engine {
             const HostLevel& L = s.lv[s.probes[p].level];
             a.buf[p] = L.f[L.parity];
             a.off[p] = s.probes[p].off;
-            a.qs[p] = L.qs;
         }
         hipLaunchKernelGGL((k_probe<DIM, P>), dim3(1), dim3(64), 0, s.stream, a, s.d_series, s.d_counter);
     }
     void init(Sim& s, int l, const double* rho, const double* u) override
     {
         HostLevel& L = s.lv[l];
-        hipLaunchKernelGGL((k_init<DIM, EQ, P>), tile_grid(L), dim3(64, 4, 1), 0, s.stream, L.dev(),
+        hipLaunchKernelGGL((k_init<DIM, EQ, P>), dense_grid(L), dim3(64, 4, 1), 0, s.stream, L.dev(),
                            (T*)L.f[L.parity], rho, u);
     }
     void ring_init(Sim& s, int l) override
@@ -256,7 +265,6 @@ struct EngineImpl final : Engine {
     void fill_nan(Sim& s) override
     {
         for (auto& L : s.lv) {
-            const int64_t nf = (int64_t)Lat<DIM>::Q * L.qs;
             T nanv;
             if constexpr (P == 2) {
                 unsigned short b = 0x7e00;
@@ -265,10 +273,7 @@ struct EngineImpl final : Engine {
                 nanv = (T)NAN;
             }
             for (int b = 0; b < 2; ++b)
-                hipLaunchKernelGGL((k_fill<T>), dim3(2048), dim3(256), 0, s.stream, (T*)L.f[b], nf, nanv);
-            if (L.S)
-                hipLaunchKernelGGL((k_fill<R>), dim3(256), dim3(256), 0, s.stream, (R*)L.S,
-                                   (int64_t)Lat<DIM>::Q * (int64_t)L.tf_meta.size(), (R)NAN);
+                hipLaunchKernelGGL((k_fill<T>), dim3(2048), dim3(256), 0, s.stream, (T*)L.f[b], L.elems, nanv);
             if (L.X)
                 hipLaunchKernelGGL((k_fill<R>), dim3(256), dim3(256), 0, s.stream, (R*)L.X,
                                    4 * (int64_t)L.tf_meta.size(), (R)NAN);
@@ -280,7 +285,7 @@ struct EngineImpl final : Engine {
     void read(Sim& s, int l, double* f, double* rho, double* u) override
     {
         HostLevel& L = s.lv[l];
-        hipLaunchKernelGGL((k_read<DIM, P>), tile_grid(L), dim3(64, 4, 1), 0, s.stream, L.dev(),
+        hipLaunchKernelGGL((k_read<DIM, P>), dense_grid(L), dim3(64, 4, 1), 0, s.stream, L.dev(),
                            (const T*)L.f[L.parity], f, rho, u);
     }
     void read_shared(Sim& s, int l, double* out) override
@@ -331,6 +336,116 @@ static void dirs(int D, int i, int c[3])
         c[1] = Lat<3>::cy[i];
         c[2] = Lat<3>::cz[i];
     }
+}
+
+// Stencil positions of a hanging node along axis a (odd coordinate k, line 0..N).
+static void stencil_positions(int k, int N, int pos[4])
+{
+    if (k == 1) {
+        pos[0] = 0; pos[1] = 2; pos[2] = 4; pos[3] = 6;
+    } else if (k == N - 1) {
+        pos[0] = N; pos[1] = N - 2; pos[2] = N - 4; pos[3] = N - 6;
+    } else {
+        pos[0] = k - 3; pos[1] = k - 1; pos[2] = k + 1; pos[3] = k + 3;
+    }
+}
+
+// Segment of a boundary node: the face it is assigned to (the first axis on
+// which it sits on the box boundary, and the side) and its tile within that
+// face: 256 positions along the line in 2-D, 16 x 16 in 3-D.
+static std::tuple<int, int, int> segment_key(int D, const int k[3], const int n[3])
+{
+    int face = -1;
+    for (int a = 0; a < D && face < 0; ++a) {
+        if (k[a] == 0) face = 2 * a;
+        else if (k[a] == n[a] - 1) face = 2 * a + 1;
+    }
+    const int ax = face / 2;
+    int t[2] = {0, 0}, no = 0;
+    const int T = D == 2 ? 256 : 16;
+    for (int a = 0; a < D; ++a)
+        if (a != ax) t[no++] = k[a] / T;
+    return std::make_tuple(face, t[0], t[1]);
+}
+
+static dclbm_status build_segments(Sim& s, int l)
+{
+    const int D = s.D;
+    HostLevel& L = s.lv[l];
+    const int n[3] = {L.nx, L.ny, L.nz};
+    struct Seg {
+        std::vector<int> own, ie;
+    };
+    std::map<std::tuple<int, int, int>, Seg> segs;
+    for (size_t t = 0; t < L.tf_meta.size(); ++t) {
+        const int k[3] = {L.tf_meta[t].x, L.tf_meta[t].y, L.tf_meta[t].z};
+        segs[segment_key(D, k, n)].own.push_back((int)t);
+    }
+    for (size_t e = 0; e < L.ie_meta.size(); ++e) {
+        const int k[3] = {L.ie_meta[e].x, L.ie_meta[e].y, L.ie_meta[e].z};
+        segs[segment_key(D, k, n)].ie.push_back((int)e);
+    }
+    const size_t nie = L.ie_meta.size();
+    L.seg_info.clear();
+    L.seg_tf.clear();
+    L.seg_ie.clear();
+    L.seg_sten.assign(16 * nie, 0);
+    const int TFM = D == 2 ? SegLimits<2>::TF : SegLimits<3>::TF;
+    for (auto& kv : segs) {
+        Seg& sg = kv.second;
+        std::map<int, int> local;   // co-located index -> local slot
+        std::vector<int> list;
+        for (int t : sg.own) {
+            local[t] = (int)list.size();
+            list.push_back(t | (1 << 30));
+        }
+        const int ie_off = (int)L.seg_ie.size();
+        for (int e : sg.ie) {
+            const int4& m = L.ie_meta[e];
+            const int k[3] = {m.x, m.y, m.z};
+            int pos[3][4], odd[2] = {-1, -1}, no = 0;
+            for (int a = 0; a < 3; ++a) {
+                pos[a][0] = pos[a][1] = pos[a][2] = pos[a][3] = k[a];
+                if (a < D && (k[a] & 1)) {
+                    if (n[a] - 1 < 6) return fail(DCLBM_ERR_INVALID, "level %d box too small for the 4-point stencil", l);
+                    stencil_positions(k[a], n[a] - 1, pos[a]);
+                    odd[no++] = a;
+                }
+            }
+            if (no < 1 || no > 2) return fail(DCLBM_ERR_INVALID, "level %d: hanging node with %d odd coordinates", l, no);
+            const int nq = no == 2 ? 16 : 4;
+            const size_t slot = L.seg_ie.size();
+            for (int q = 0; q < nq; ++q) {
+                int c[3] = {k[0], k[1], k[2]};
+                c[odd[0]] = pos[odd[0]][q & 3];
+                if (no == 2) c[odd[1]] = pos[odd[1]][q >> 2];
+                if ((c[0] | c[1] | c[2]) & 1) return fail(DCLBM_ERR_INVALID, "stencil off the co-located lattice");
+                const size_t key = ((size_t)(c[2] / 2) * L.my + c[1] / 2) * L.mx + c[0] / 2;
+                if (key >= L.tfmap.size() || L.tfmap[key] < 0)
+                    return fail(DCLBM_ERR_INVALID, "level %d hanging node (%d,%d,%d): stencil node is not co-located", l,
+                                m.x, m.y, m.z);
+                const int t = L.tfmap[key];
+                auto it = local.find(t);
+                int li;
+                if (it == local.end()) {
+                    li = (int)list.size();
+                    local[t] = li;
+                    list.push_back(t);
+                } else {
+                    li = it->second;
+                }
+                L.seg_sten[(size_t)q * nie + slot] = li;
+            }
+            L.seg_ie.push_back(e);
+        }
+        if ((int)list.size() > TFM || (int)list.size() > kBlock || (int)sg.ie.size() > kBlock)
+            return fail(DCLBM_ERR_INVALID, "level %d: interface segment too large (%zu co-located, %zu hanging)", l,
+                        list.size(), sg.ie.size());
+        L.seg_info.push_back(make_int4((int)L.seg_tf.size(), (int)list.size(), ie_off, (int)sg.ie.size()));
+        L.seg_tf.insert(L.seg_tf.end(), list.begin(), list.end());
+    }
+    // the stencil table is indexed by position in seg_ie, which is the IE order of the segments
+    return DCLBM_OK;
 }
 
 static dclbm_status build_geometry(Sim& s)
@@ -389,12 +504,11 @@ static dclbm_status build_geometry(Sim& s)
         L.tau = tau;
         tau = 2.0 * tau - 0.5;
     }
-    // storage layout per level
+    // storage layout per level: 64-node row blocks, Q directions per block
     for (int l = 0; l < c.n_levels; ++l) {
         HostLevel& L = s.lv[l];
-        L.pitch = (int)round_up(L.nx, 64);
-        L.plane = (int64_t)L.pitch * L.ny;
-        L.qs = round_up(L.plane * L.nz, 256);
+        L.nxb = (L.nx + 63) / 64;
+        L.elems = (int64_t)L.nz * L.ny * L.nxb * Q * 64;
         int64_t hole = 0;
         if (L.has_child) {
             hole = 1;
@@ -439,6 +553,7 @@ static dclbm_status build_geometry(Sim& s)
                         if (even && !hole) Kc |= 1u << i;
                     }
                     if (even) {
+                        // Table choice_Gamma_fine: DC1 takes M^f from the coarse grid, DC2 P and M^f
                         const uint32_t P_ = Kf & Kc, Mf = all & ~Kf;
                         const uint32_t gR = c.coupling == 1 ? Mf : (P_ | Mf);
                         if ((gR & ~Kc) || ((all & ~gR) & ~Kf))
@@ -452,36 +567,8 @@ static dclbm_status build_geometry(Sim& s)
                         L.ie_meta.push_back(make_int4(x, y, z, (int)(all & ~Kf)));
                     }
                 }
-        // every hanging node's stencil must land on co-located nodes (the
-        // kernel indexes the co-located list through tfmap without checks)
-        for (const int4& m : L.ie_meta) {
-            const int k[3] = {m.x, m.y, m.z};
-            int np[3] = {1, 1, 1}, pos[3][4];
-            for (int a = 0; a < 3; ++a) {
-                pos[a][0] = k[a];
-                if (a < D && (k[a] & 1)) {
-                    const int N = n[a] - 1;
-                    if (N < 6) return fail(DCLBM_ERR_INVALID, "level %d box too small for the 4-point stencil", l);
-                    np[a] = 4;
-                    if (k[a] == 1) { pos[a][0] = 0; pos[a][1] = 2; pos[a][2] = 4; pos[a][3] = 6; }
-                    else if (k[a] == N - 1) { pos[a][0] = N; pos[a][1] = N - 2; pos[a][2] = N - 4; pos[a][3] = N - 6; }
-                    else { pos[a][0] = k[a] - 3; pos[a][1] = k[a] - 1; pos[a][2] = k[a] + 1; pos[a][3] = k[a] + 3; }
-                }
-            }
-            for (int cz = 0; cz < np[2]; ++cz)
-                for (int cy = 0; cy < np[1]; ++cy)
-                    for (int cx = 0; cx < np[0]; ++cx) {
-                        const int px = pos[0][cx], py = pos[1][cy], pz = pos[2][cz];
-                        if ((px | py | pz) & 1) return fail(DCLBM_ERR_INVALID, "hanging-node stencil off the co-located lattice");
-                        const size_t key = ((size_t)(pz / 2) * L.my + py / 2) * L.mx + px / 2;
-                        if (key >= L.tfmap.size() || L.tfmap[key] < 0)
-                            return fail(DCLBM_ERR_INVALID, "level %d hanging node (%d,%d,%d): stencil node is not co-located", l, m.x, m.y, m.z);
-                    }
-        }
-    }
-    for (auto& L : s.lv) {
-        int64_t iface = (int64_t)L.tf_meta.size() + (int64_t)L.ie_meta.size() + (int64_t)L.tfc_meta.size();
-        L.n_bulk = L.n_active - iface;
+        dclbm_status st = build_segments(s, l);
+        if (st != DCLBM_OK) return st;
     }
     // probes: finest level whose closed box contains the point
     s.probes.clear();
@@ -510,7 +597,7 @@ static dclbm_status build_geometry(Sim& s)
                 if (d < 0 || (d >> sh) > n[a] - 1 || (d & ((1LL << sh) - 1))) inside = false;
                 else k[a] = (int)(d >> sh);
             }
-            if (inside) best = ProbeLoc{l, (int64_t)k[2] * s.lv[l].plane + (int64_t)k[1] * s.lv[l].pitch + k[0]};
+            if (inside) best = ProbeLoc{l, s.lv[l].elem0(Q, k[0], k[1], k[2])};
         }
         s.probes.push_back(best);
     }
@@ -522,14 +609,18 @@ static dclbm_status build_geometry(Sim& s)
         return o;
     };
     for (auto& L : s.lv) {
-        for (int b = 0; b < 2; ++b) L.off_f[b] = take(L.qs * Q * (int64_t)s.tsize);
+        for (int b = 0; b < 2; ++b) L.off_f[b] = take(L.elems * (int64_t)s.tsize);
         if (!L.tf_meta.empty()) {
             L.off_tf = take((int64_t)L.tf_meta.size() * 16);
-            L.off_S = take((int64_t)L.tf_meta.size() * Q * (int64_t)s.rsize);
             L.off_X = take((int64_t)L.tf_meta.size() * 4 * (int64_t)s.rsize);
-            L.off_tfmap = take((int64_t)L.tfmap.size() * 4);
+            L.off_seg_info = take((int64_t)L.seg_info.size() * 16);
+            L.off_seg_tf = take((int64_t)L.seg_tf.size() * 4);
         }
-        if (!L.ie_meta.empty()) L.off_ie = take((int64_t)L.ie_meta.size() * 16);
+        if (!L.ie_meta.empty()) {
+            L.off_ie = take((int64_t)L.ie_meta.size() * 16);
+            L.off_seg_ie = take((int64_t)L.seg_ie.size() * 4);
+            L.off_seg_sten = take((int64_t)L.seg_sten.size() * 4);
+        }
         if (!L.tfc_meta.empty()) {
             L.off_tfc = take((int64_t)L.tfc_meta.size() * 16);
             L.off_H = take((int64_t)L.tfc_meta.size() * 3 * Q * (int64_t)s.rsize);
@@ -545,23 +636,19 @@ static dclbm_status build_geometry(Sim& s)
 }
 
 // ------------------------------------------------------------------ stepping
+// One step of level l (substep 1 or 2 of its parent's step) is one launch:
+// its bulk nodes, its coarse history capture (if it has a child) and its
+// interface segments (if it has a parent; at substep 2 they also restrict
+// into the parent).  Then its two child substeps follow.
 static void advance(Sim& s, int l, int substep)
 {
     HostLevel& L = s.lv[l];
-    s.eng->bulk(s, l);
+    const int first = (l > 0 && s.lv[l - 1].captures <= 1) ? 1 : 0;
+    s.eng->level_step(s, l, substep, first);
     if (L.has_child) {
-        s.eng->capture(s, l);
         L.captures++;
-    }
-    if (l > 0) {
-        const int first = s.lv[l - 1].captures <= 1 ? 1 : 0;
-        s.eng->tf(s, l, substep, first);
-        if (!L.ie_meta.empty()) s.eng->ie(s, l);
-    }
-    if (L.has_child) {
         advance(s, l + 1, 1);
         advance(s, l + 1, 2);
-        s.eng->restrict_(s, l);
     }
     L.parity ^= 1;
 }
@@ -575,10 +662,15 @@ static void advance_state(Sim& s)
     s.lv[0].parity ^= 1;
 }
 
-static dclbm_status coarse_step_eager(Sim& s)
+static void one_coarse_step(Sim& s)
 {
     advance(s, 0, 0);
     s.eng->probe(s);
+}
+
+static dclbm_status coarse_step_eager(Sim& s)
+{
+    one_coarse_step(s);
     HIPCHECK(hipGetLastError());
     return DCLBM_OK;
 }
@@ -596,8 +688,7 @@ static dclbm_status coarse_step(Sim& s)
     const int par = s.lv[0].parity;
     if (!s.gexec[par]) {
         HIPCHECK(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal));
-        advance(s, 0, 0);
-        s.eng->probe(s);
+        one_coarse_step(s);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s.stream, &g);
         if (e != hipSuccess) return fail(DCLBM_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
@@ -696,20 +787,25 @@ dclbm_status dclbm_create(const dclbm_config* cfg, void* d_workspace, size_t byt
         for (int b = 0; b < 2; ++b) L.f[b] = s.ws + L.off_f[b];
         if (!L.tf_meta.empty()) {
             L.d_tf = s.at<int4>(L.off_tf);
-            L.S = s.ws + L.off_S;
             L.X = s.ws + L.off_X;
-            L.d_tfmap = s.at<int>(L.off_tfmap);
-            HIPCHECK(hipMemcpyAsync(L.d_tf, L.tf_meta.data(), L.tf_meta.size() * 16, hipMemcpyHostToDevice, s.stream));
-            HIPCHECK(hipMemcpyAsync(L.d_tfmap, L.tfmap.data(), L.tfmap.size() * 4, hipMemcpyHostToDevice, s.stream));
+            L.d_seg_info = s.at<int4>(L.off_seg_info);
+            L.d_seg_tf = s.at<int>(L.off_seg_tf);
+            HIPCHECK(upload(s, L.d_tf, L.tf_meta));
+            HIPCHECK(upload(s, L.d_seg_info, L.seg_info));
+            HIPCHECK(upload(s, L.d_seg_tf, L.seg_tf));
         }
         if (!L.ie_meta.empty()) {
             L.d_ie = s.at<int4>(L.off_ie);
-            HIPCHECK(hipMemcpyAsync(L.d_ie, L.ie_meta.data(), L.ie_meta.size() * 16, hipMemcpyHostToDevice, s.stream));
+            L.d_seg_ie = s.at<int>(L.off_seg_ie);
+            L.d_seg_sten = s.at<int>(L.off_seg_sten);
+            HIPCHECK(upload(s, L.d_ie, L.ie_meta));
+            HIPCHECK(upload(s, L.d_seg_ie, L.seg_ie));
+            HIPCHECK(upload(s, L.d_seg_sten, L.seg_sten));
         }
         if (!L.tfc_meta.empty()) {
             L.d_tfc = s.at<int4>(L.off_tfc);
             L.H = s.ws + L.off_H;
-            HIPCHECK(hipMemcpyAsync(L.d_tfc, L.tfc_meta.data(), L.tfc_meta.size() * 16, hipMemcpyHostToDevice, s.stream));
+            HIPCHECK(upload(s, L.d_tfc, L.tfc_meta));
         }
     }
     s.d_series = s.at<double>(s.off_series);
@@ -736,11 +832,12 @@ dclbm_status dclbm_destroy(dclbm_sim* sim)
         if (s.gexec[p]) (void)hipGraphExecDestroy(s.gexec[p]);
         if (s.graph[p]) (void)hipGraphDestroy(s.graph[p]);
     }
-    for (int l = 0; l < DCLBM_MAX_LEVELS; ++l)
+    for (int l = 0; l < DCLBM_MAX_LEVELS; ++l) {
         for (auto& e : s.tev[l]) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
+    }
     delete sim;
     return DCLBM_OK;
 }
@@ -898,7 +995,7 @@ dclbm_status dclbm_bulk_time(dclbm_sim* sim, int32_t level, double* ms, int64_t*
     s.tev[level].clear();
     if (ms) *ms = s.tms[level];
     if (launches) *launches = s.tlaunch[level];
-    if (nodes_per_launch) *nodes_per_launch = s.lv[level].n_bulk;
+    if (nodes_per_launch) *nodes_per_launch = s.lv[level].n_active - (int64_t)s.lv[level].tfc_meta.size();
     return DCLBM_OK;
 }
 

@@ -1,18 +1,30 @@
 // HIP kernels (gfx950) of the direct-coupling refined LBM step.
 //
-// Per level, populations live in two SoA buffers s[Q][z][y][x_pitch] (A/B),
-// read by a pull stream and written once per node per substep.  The kernels:
-//   k_bulk      fused pull-stream + BGK on every node that is not on an
-//               interface (Eq.(LBMequation), Eq.(LBMscheme_reg) with BGK)
-//   k_capture   coarse co-located nodes: store the streamed coarse
-//               populations in a 3-deep history ring (input of Eq.(TempInt))
-//   k_tf        fine co-located nodes: Newton for X (Eq.(system_fi)),
-//               rebuild every Gamma=R direction (Eq.(rescff)), collide with X
-//   k_ie        hanging fine nodes: 4-point 1-D Lagrange interpolation of the
-//               missing directions from completed co-located values, collide
-//   k_restrict  coarse co-located nodes after the synchronous fine substep:
-//               Eq.(rescfc) on all directions, collide with X
-// plus initialisation, conversion, probe and balance kernels.
+// Layout.  Each level keeps two population buffers (A/B).  A buffer is a
+// sequence of 64-node row blocks; inside a block the Q directions follow each
+// other, 64 contiguous values each:
+//     element(i, x, y, z) = ((z*ny + y)*nxb + x/64)*Q*64 + i*64 + x%64
+// A wavefront (64 lanes, one per node of a row block) reads every direction
+// as one coalesced 64-element run, and all Q directions of one row block sit
+// in one contiguous span, which keeps the pull stream's 3^D neighbouring row
+// blocks in few DRAM pages and translation entries.
+//
+// One launch per level substep (k_level) runs three kinds of workgroups:
+//   capture   coarse co-located nodes store their streamed populations in a
+//             3-deep history ring (the input of Eq.(TempInt));
+//   segment   one tile of the fine interface line/face: Newton for the shared
+//             state X of every co-located node the tile's hanging nodes need
+//             (Eq.(system_fi), Eq.(updated_macro)), rebuild of each Gamma=R
+//             direction (Eq.(rescff)) into LDS, collision of the tile's own
+//             co-located nodes with X, and at synchronous substeps the
+//             restriction of Eq.(rescfc) with the coarse collision of the
+//             co-located coarse node; then the hanging nodes take their
+//             missing directions by 4-point 1-D interpolation from LDS and
+//             collide.  Halo co-located nodes are recomputed, not exchanged;
+//   bulk      fused pull-stream + BGK of every other node (Eq.(LBMequation),
+//             Eq.(LBMscheme_reg) with BGK), 64 x 4 node tiles dealt to the
+//             8 XCDs in contiguous runs.
+// Plus initialisation, conversion, probe and balance kernels.
 #pragma once
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -68,21 +80,21 @@ struct Form<2> {
 // ---------------------------------------------------------------- level geometry
 struct LevelDev {
     int nx, ny, nz;
-    int pitch;
-    int64_t plane;     // pitch * ny
-    int64_t qs;        // elements between directions
+    int nxb;           // 64-node row blocks per row
     int periodic;      // level 0
     int boundary;      // own box faces are interfaces (level >= 1)
     int has_child;
     int clo[3], chi[3];// child box, closed, in this level's node coordinates
 };
 
-__device__ __forceinline__ int64_t node_off(const LevelDev& g, int x, int y, int z)
+// Element index of direction i at node (x, y, z).
+template <int DIM>
+__device__ __forceinline__ int64_t eoff(const LevelDev& g, int i, int x, int y, int z)
 {
-    return (int64_t)z * g.plane + (int64_t)y * g.pitch + x;
+    return (((int64_t)z * g.ny + y) * g.nxb + (x >> 6)) * (Lat<DIM>::Q * 64) + i * 64 + (x & 63);
 }
 
-// Source node of direction i for a pull stream; periodic wrap on level 0.
+// Pull-stream source of direction i: node (x, y, z) - xi_i, periodic on level 0.
 template <int DIM>
 __device__ __forceinline__ int64_t src_off(const LevelDev& g, int x, int y, int z, int i)
 {
@@ -92,13 +104,7 @@ __device__ __forceinline__ int64_t src_off(const LevelDev& g, int x, int y, int 
         sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
         if (DIM == 3) sz = sz < 0 ? sz + g.nz : (sz >= g.nz ? sz - g.nz : sz);
     }
-    return node_off(g, sx, sy, sz);
-}
-
-template <int DIM>
-__device__ __forceinline__ bool in_box(const LevelDev& g, int x, int y, int z)
-{
-    return x >= 0 && x < g.nx && y >= 0 && y < g.ny && (DIM == 2 || (z >= 0 && z < g.nz));
+    return eoff<DIM>(g, i, sx, sy, sz);
 }
 
 template <int DIM>
@@ -113,62 +119,295 @@ __device__ __forceinline__ bool is_interface_or_hole(const LevelDev& g, int x, i
     return false;
 }
 
-// ---------------------------------------------------------------- bulk stream + collide
-// Tile: 64 (x, one wavefront) x 4 (y) nodes; grid (ceil(nx/64), ceil(ny/4), nz).
-template <int DIM, int EQ, int P>
-__global__ __launch_bounds__(256) void k_bulk(LevelDev g, const typename Form<P>::T* __restrict__ src,
-                                              typename Form<P>::T* __restrict__ dst,
-                                              typename Form<P>::R keep)
+template <int DIM>
+__device__ __forceinline__ bool is_hole(const LevelDev& g, int x, int y, int z)
+{
+    return g.has_child && x > g.clo[0] && x < g.chi[0] && y > g.clo[1] && y < g.chi[1] &&
+           (DIM == 2 || (z > g.clo[2] && z < g.chi[2]));
+}
+
+// 4-point stencil along one axis for odd position k on a line 0..N:
+// centred (-1,9,9,-1)/16 at k-3..k+3, one-sided (5,15,-5,1)/16 at line ends
+// (nodes 0,2,4,6 or N,N-2,N-4,N-6).
+__device__ __forceinline__ void line_weights(int k, int N, float w[4])
+{
+    if (k == 1 || k == N - 1) {
+        w[0] = 5.f / 16; w[1] = 15.f / 16; w[2] = -5.f / 16; w[3] = 1.f / 16;
+    } else {
+        w[0] = -1.f / 16; w[1] = 9.f / 16; w[2] = 9.f / 16; w[3] = -1.f / 16;
+    }
+}
+
+// ---------------------------------------------------------------- the level-substep kernel
+// Maximum co-located nodes a segment holds in LDS (own + halo); every role
+// runs in workgroups of kBlock threads.
+template <int DIM>
+struct SegLimits {
+    static constexpr int TF = DIM == 2 ? 136 : 144;
+    static constexpr int IE = 256;
+};
+constexpr int kBlock = 256;
+
+struct TileMap {
+    int tx, ty;      // 64 x 4 tiles per row, per column
+    int ntiles;      // tx * ty * nz
+    int per;         // ceil(ntiles / 8)
+};
+
+struct LevelArgs {
+    LevelDev g;
+    const void* src;
+    void* dst;
+    double keep;          // 1 - 1/tau_l
+    TileMap tm;
+    int nb_cap, nb_seg;   // workgroups of the capture and segment roles (first in the grid)
+    // capture (level has a child): coarse co-located nodes of this level
+    const int4* cap_meta; // (x, y, z, K^c mask)
+    int n_cap;
+    void* H_own;          // this level's ring [3][Q][n_cap]
+    // segments (level has a parent)
+    const int4* seg_info; // (tf_off, tf_cnt, ie_off, ie_cnt)
+    const int* seg_tf;    // co-located index | owned << 30
+    const int* seg_ie;    // hanging-node index
+    const int* seg_sten;  // [16][n_ie] local stencil indices into the segment's co-located list
+    int n_ie;
+    const int4* tf_meta;  // (x, y, z, Gamma=R mask)
+    const int4* ie_meta;  // (x, y, z, missing mask)
+    int n_tf;
+    const void* H_parent; // parent's ring [3][Q][n_tf]
+    void* X;              // [4][n_tf] shared state (drho, u) of co-located nodes
+    int substep;          // 1 asynchronous, 2 synchronous
+    int first;            // parent made a single step: linear time interpolation
+    int maxit;
+    double Rfac;          // tau_l / (2 tau_{l-1}), Eq.(fneqResc)
+    double tol;
+    int* flags;
+    // restriction into the parent at synchronous substeps
+    LevelDev gp;
+    void* dst_parent;
+    const int4* tfc_meta; // parent coordinates of each co-located node (same order)
+    double keep_parent;
+};
+
+template <int DIM, int P>
+__device__ __forceinline__ void role_capture(const LevelArgs& a, int b)
 {
     using F = Form<P>;
+    using T = typename F::T;
     using R = typename F::R;
     constexpr int Q = Lat<DIM>::Q;
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = blockIdx.z;
+    const int t = b * kBlock + threadIdx.x;
+    if (t >= a.n_cap) return;
+    const int4 m = a.cap_meta[t];
+    const T* src = (const T*)a.src;
+    R* H = (R*)a.H_own;
+    const int64_t n = a.n_cap, slot = (int64_t)Q * n;
+    // every load before any store: one memory round trip per node
+    R v[Q], h1[Q], h2[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const bool k = (m.w >> i) & 1;
+        v[i] = k ? F::load(src + src_off<DIM>(a.g, m.x, m.y, m.z, i)) : R(0);
+        h1[i] = k ? H[slot + i * n + t] : R(0);
+        h2[i] = k ? H[2 * slot + i * n + t] : R(0);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (!((m.w >> i) & 1)) continue;
+        H[i * n + t] = h1[i];
+        H[slot + i * n + t] = h2[i];
+        H[2 * slot + i * n + t] = v[i];
+    }
+}
+
+template <int DIM, int EQ, int P>
+__device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typename Form<P>::R* lds)
+{
+    using F = Form<P>;
+    using T = typename F::T;
+    using R = typename F::R;
+    constexpr int Q = Lat<DIM>::Q;
+    constexpr int TFM = SegLimits<DIM>::TF;
+    const int4 info = a.seg_info[sgi];
+    const T* src = (const T*)a.src;
+    T* dst = (T*)a.dst;
+    const R rho0 = R(F::rho0);
+    const int j = threadIdx.x;
+    // ---- phase 1: co-located nodes (own and halo)
+    if (j < info.y) {
+        const int e = a.seg_tf[info.x + j];
+        const int t = e & 0x3fffffff;
+        const bool owned = (e >> 30) & 1;
+        const int4 m = a.tf_meta[t];
+        const uint32_t gR = (uint32_t)m.w;
+        const R* H = (const R*)a.H_parent;
+        const int64_t n = a.n_tf, slot = (int64_t)Q * n;
+        R h[Q], gc[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if ((gR >> i) & 1u) {
+                const R Hm = H[i * n + t], H0 = H[slot + i * n + t], Hp = H[2 * slot + i * n + t];
+                R v;
+                if (a.substep == 2)
+                    v = Hp;
+                else if (a.first)
+                    v = R(0.5) * H0 + R(0.5) * Hp;
+                else
+                    v = R(-0.125) * Hm + R(0.75) * H0 + R(0.375) * Hp;
+                gc[i] = v;
+                h[i] = v;
+            } else {
+                gc[i] = R(0);
+                h[i] = F::load(src + src_off<DIM>(a.g, m.x, m.y, m.z, i));
+            }
+        }
+        R drho, u[3];
+        const int it = newton<DIM, EQ, R>(h, gR, R(a.Rfac), rho0, R(a.tol), a.maxit, drho, u);
+        if (it < 0) {
+            if (owned) atomicOr(a.flags, 1);
+            R jj[3];
+            moments<DIM, R>(h, drho, jj);
+            const R rr = rho0 + drho;
+            u[0] = jj[0] / rr;
+            u[1] = jj[1] / rr;
+            u[2] = DIM == 3 ? jj[2] / rr : R(0);
+        }
+        const R uu = u[0] * u[0] + u[1] * u[1] + (DIM == 3 ? u[2] * u[2] : R(0));
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if ((gR >> i) & 1u) {
+                const R e0 = eq_s<DIM, EQ, R>(i, rho0, drho, u, uu);
+                h[i] = e0 + R(a.Rfac) * (gc[i] - e0);
+            }
+            lds[i * TFM + j] = h[i];
+        }
+        if (owned) {
+            R* X = (R*)a.X;
+            X[t] = drho;
+            X[n + t] = u[0];
+            X[2 * n + t] = u[1];
+            X[3 * n + t] = u[2];
+            if (a.substep == 2) {
+                // Eq.(rescfc): every coarse population from the completed fine
+                // ones, then the coarse collision with X
+                const int4 pm = a.tfc_meta[t];
+                const double invR = 1.0 / a.Rfac;
+                R c[Q];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    const R e0 = eq_s<DIM, EQ, R>(i, rho0, drho, u, uu);
+                    c[i] = e0 + R(invR) * (h[i] - e0);
+                }
+                bgk<DIM, EQ, R>(c, rho0, drho, u, R(a.keep_parent));
+                T* dp = (T*)a.dst_parent;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) F::store(dp + eoff<DIM>(a.gp, i, pm.x, pm.y, pm.z), c[i]);
+            }
+            R c[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) c[i] = h[i];
+            bgk<DIM, EQ, R>(c, rho0, drho, u, R(a.keep));
+#pragma unroll
+            for (int i = 0; i < Q; ++i) F::store(dst + eoff<DIM>(a.g, i, m.x, m.y, m.z), c[i]);
+        }
+    }
+    __syncthreads();
+    // ---- phase 2: hanging nodes
+    if (j < info.w) {
+        const int q0 = info.z + j;
+        const int4 m = a.ie_meta[a.seg_ie[q0]];
+        const int k[3] = {m.x, m.y, m.z};
+        const int N[3] = {a.g.nx - 1, a.g.ny - 1, a.g.nz - 1};
+        // odd axes in increasing order carry the stencil; the first one is fastest
+        int oa[2] = {0, 0}, no = 0;
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax)
+            if ((k[ax] & 1) && no < 2) oa[no++] = ax;
+        float w0[4], w1[4] = {1.f, 0.f, 0.f, 0.f};
+        line_weights(k[oa[0]], N[oa[0]], w0);
+        if (no == 2) line_weights(k[oa[1]], N[oa[1]], w1);
+        const int ns = no == 2 ? 16 : 4;
+        int idx[16];
+        R wt[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            idx[q] = q < ns ? a.seg_sten[(int64_t)q * a.n_ie + q0] : 0;
+            wt[q] = q < ns ? R(w0[q & 3]) * R(w1[q >> 2]) : R(0);
+        }
+        R s[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if ((m.w >> i) & 1) {
+                R acc = R(0);
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    if (q < ns) acc += wt[q] * lds[i * TFM + idx[q]];
+                s[i] = acc;
+            } else {
+                s[i] = F::load(src + src_off<DIM>(a.g, m.x, m.y, m.z, i));
+            }
+        }
+        R drho, jj[3];
+        moments<DIM, R>(s, drho, jj);
+        const R rho = rho0 + drho;
+        const R u[3] = {jj[0] / rho, jj[1] / rho, DIM == 3 ? jj[2] / rho : R(0)};
+        bgk<DIM, EQ, R>(s, rho0, drho, u, R(a.keep));
+#pragma unroll
+        for (int i = 0; i < Q; ++i) F::store(dst + eoff<DIM>(a.g, i, m.x, m.y, m.z), s[i]);
+    }
+}
+
+template <int DIM, int EQ, int P>
+__device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
+{
+    using F = Form<P>;
+    using T = typename F::T;
+    using R = typename F::R;
+    constexpr int Q = Lat<DIM>::Q;
+    const TileMap& tm = a.tm;
+    // contiguous runs of tiles per XCD (workgroups are dealt round-robin to 8 XCDs)
+    const int t = (bb & 7) * tm.per + (bb >> 3);
+    if (t >= tm.ntiles) return;
+    const int txy = tm.tx * tm.ty;
+    const int z = t / txy;
+    const int r = t - z * txy;
+    const int ty = r / tm.tx;
+    const int x = (r - ty * tm.tx) * 64 + (threadIdx.x & 63);
+    const int y = ty * 4 + (threadIdx.x >> 6);
+    const LevelDev& g = a.g;
     if (x >= g.nx || y >= g.ny) return;
     if (is_interface_or_hole<DIM>(g, x, y, z)) return;
+    const T* src = (const T*)a.src;
     R s[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) s[i] = F::load(src + (int64_t)i * g.qs + src_off<DIM>(g, x, y, z, i));
+    for (int i = 0; i < Q; ++i) s[i] = F::load(src + src_off<DIM>(g, x, y, z, i));
     R drho, j[3];
     moments<DIM, R>(s, drho, j);
     const R rho = R(F::rho0) + drho;
     const R inv = R(1) / rho;
     const R u[3] = {j[0] * inv, j[1] * inv, DIM == 3 ? j[2] * inv : R(0)};
-    bgk<DIM, EQ, R>(s, R(F::rho0), drho, u, keep);
-    const int64_t o = node_off(g, x, y, z);
+    bgk<DIM, EQ, R>(s, R(F::rho0), drho, u, R(a.keep));
+    T* d = (T*)a.dst + eoff<DIM>(g, 0, x, y, z);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) F::store(dst + (int64_t)i * g.qs + o, s[i]);
+    for (int i = 0; i < Q; ++i) F::store(d + i * 64, s[i]);
 }
 
-// ---------------------------------------------------------------- coarse history capture
-// meta: (x, y, z, K^c mask) of each coarse co-located node, in the order of
-// the child's co-located list.  H: [3][Q][n], slot 0 = t - dt, 1 = t, 2 = t + dt.
-template <int DIM, int P>
-__global__ __launch_bounds__(128) void k_capture(LevelDev g, const typename Form<P>::T* __restrict__ src,
-                                                 const int4* __restrict__ meta, int n,
-                                                 typename Form<P>::R* __restrict__ H)
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(kBlock) void k_level(LevelArgs a)
 {
-    using F = Form<P>;
-    using R = typename F::R;
-    constexpr int Q = Lat<DIM>::Q;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const int4 m = meta[t];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if (!((m.w >> i) & 1)) continue;
-        const R v = F::load(src + (int64_t)i * g.qs + src_off<DIM>(g, m.x, m.y, m.z, i));
-        R* h = H + (int64_t)i * n + t;
-        const int64_t slot = (int64_t)Q * n;
-        h[0] = h[slot];
-        h[slot] = h[2 * slot];
-        h[2 * slot] = v;
+    using R = typename Form<P>::R;
+    __shared__ R lds[Lat<DIM>::Q * SegLimits<DIM>::TF];
+    const int b = blockIdx.x;
+    if (b < a.nb_cap) {
+        role_capture<DIM, P>(a, b);
+    } else if (b < a.nb_cap + a.nb_seg) {
+        role_segment<DIM, EQ, P>(a, b - a.nb_cap, lds);
+    } else {
+        role_bulk<DIM, EQ, P>(a, b - a.nb_cap - a.nb_seg);
     }
 }
 
-// Ring initialisation from the node's own initial populations.
+// ---------------------------------------------------------------- history ring init
 template <int DIM, int P>
 __global__ __launch_bounds__(128) void k_ring_init(LevelDev g, const typename Form<P>::T* __restrict__ src,
                                                    const int4* __restrict__ meta, int n,
@@ -179,216 +418,15 @@ __global__ __launch_bounds__(128) void k_ring_init(LevelDev g, const typename Fo
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int4 m = meta[t];
-    const int64_t o = node_off(g, m.x, m.y, m.z);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const auto v = F::load(src + (int64_t)i * g.qs + o);
+        const auto v = F::load(src + eoff<DIM>(g, i, m.x, m.y, m.z));
         for (int r = 0; r < 3; ++r) H[((int64_t)r * Q + i) * n + t] = v;
     }
 }
 
-// ---------------------------------------------------------------- fine co-located nodes
-struct TfArgs {
-    int n;            // co-located fine nodes
-    int substep;      // 1 asynchronous (mid coarse step), 2 synchronous
-    int first;        // parent has made a single step: linear time interpolation
-    int maxit;
-    double Rfac;      // tau_f / (2 tau_c), Eq.(fneqResc)
-    double keep;      // 1 - 1/tau_f
-    double tol;
-};
-
-template <int DIM, int EQ, int P>
-__global__ __launch_bounds__(64) void k_tf(LevelDev g, const typename Form<P>::T* __restrict__ src,
-                                           typename Form<P>::T* __restrict__ dst,
-                                           const int4* __restrict__ meta, TfArgs a,
-                                           const typename Form<P>::R* __restrict__ H,
-                                           typename Form<P>::R* __restrict__ S,
-                                           typename Form<P>::R* __restrict__ X, int* __restrict__ flags)
-{
-    using F = Form<P>;
-    using R = typename F::R;
-    constexpr int Q = Lat<DIM>::Q;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.n) return;
-    const int4 m = meta[t];
-    const uint32_t gR = (uint32_t)m.w;
-    const int64_t slot = (int64_t)Q * a.n;
-    R h[Q], gc[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if ((gR >> i) & 1u) {
-            const R* hp = H + (int64_t)i * a.n + t;
-            const R Hm = hp[0], H0 = hp[slot], Hp = hp[2 * slot];
-            R v;
-            if (a.substep == 2)
-                v = Hp;
-            else if (a.first)
-                v = R(0.5) * H0 + R(0.5) * Hp;
-            else
-                v = R(-0.125) * Hm + R(0.75) * H0 + R(0.375) * Hp;
-            gc[i] = v;
-            h[i] = v;
-        } else {
-            gc[i] = R(0);
-            h[i] = F::load(src + (int64_t)i * g.qs + src_off<DIM>(g, m.x, m.y, m.z, i));
-        }
-    }
-    R drho, u[3];
-    const int it = newton<DIM, EQ, R>(h, gR, R(a.Rfac), R(F::rho0), R(a.tol), a.maxit, drho, u);
-    if (it < 0) {
-        atomicOr(flags, 1);
-        R j[3];
-        moments<DIM, R>(h, drho, j);
-        const R rr = R(F::rho0) + drho;
-        u[0] = j[0] / rr;
-        u[1] = j[1] / rr;
-        u[2] = DIM == 3 ? j[2] / rr : R(0);
-    }
-    const R uu = u[0] * u[0] + u[1] * u[1] + (DIM == 3 ? u[2] * u[2] : R(0));
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if ((gR >> i) & 1u) {
-            const R e = eq_s<DIM, EQ, R>(i, R(F::rho0), drho, u, uu);
-            h[i] = e + R(a.Rfac) * (gc[i] - e);
-        }
-        S[(int64_t)i * a.n + t] = h[i];
-    }
-    X[t] = drho;
-    X[(int64_t)a.n + t] = u[0];
-    X[2 * (int64_t)a.n + t] = u[1];
-    X[3 * (int64_t)a.n + t] = u[2];
-    bgk<DIM, EQ, R>(h, R(F::rho0), drho, u, R(a.keep));
-    const int64_t o = node_off(g, m.x, m.y, m.z);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) F::store(dst + (int64_t)i * g.qs + o, h[i]);
-}
-
-// ---------------------------------------------------------------- hanging fine nodes
-// 4-point stencil along one axis for odd position k on a line 0..N:
-// centred (-1,9,9,-1)/16 at k-3..k+3, one-sided (5,15,-5,1)/16 at line ends.
-__device__ __forceinline__ void line_stencil(int k, int N, int pos[4], float w[4])
-{
-    if (k == 1) {
-        pos[0] = 0; pos[1] = 2; pos[2] = 4; pos[3] = 6;
-        w[0] = 5.f / 16; w[1] = 15.f / 16; w[2] = -5.f / 16; w[3] = 1.f / 16;
-    } else if (k == N - 1) {
-        pos[0] = N; pos[1] = N - 2; pos[2] = N - 4; pos[3] = N - 6;
-        w[0] = 5.f / 16; w[1] = 15.f / 16; w[2] = -5.f / 16; w[3] = 1.f / 16;
-    } else {
-        pos[0] = k - 3; pos[1] = k - 1; pos[2] = k + 1; pos[3] = k + 3;
-        w[0] = -1.f / 16; w[1] = 9.f / 16; w[2] = 9.f / 16; w[3] = -1.f / 16;
-    }
-}
-
-struct IeArgs {
-    int n;            // hanging nodes
-    int mx, my;       // dims of the co-located index map (nx/2+1, ny/2+1)
-    int ntf;          // co-located nodes (stride of S)
-    double keep;
-};
-
-// meta: (x, y, z, missing-direction mask).  tfmap: co-located index of the
-// node at fine coords (2a, 2b, 2c) stored at (c*my + b)*mx + a, -1 elsewhere.
-template <int DIM, int EQ, int P>
-__global__ __launch_bounds__(64) void k_ie(LevelDev g, const typename Form<P>::T* __restrict__ src,
-                                           typename Form<P>::T* __restrict__ dst,
-                                           const int4* __restrict__ meta, IeArgs a,
-                                           const typename Form<P>::R* __restrict__ S,
-                                           const int* __restrict__ tfmap)
-{
-    using F = Form<P>;
-    using R = typename F::R;
-    constexpr int Q = Lat<DIM>::Q;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.n) return;
-    const int4 m = meta[t];
-    const int k[3] = {m.x, m.y, m.z};
-    const int N[3] = {g.nx - 1, g.ny - 1, g.nz - 1};
-    int np[3], pos[3][4];
-    float w[3][4];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        if (ax < DIM && (k[ax] & 1)) {
-            np[ax] = 4;
-            line_stencil(k[ax], N[ax], pos[ax], w[ax]);
-        } else {
-            np[ax] = 1;
-            pos[ax][0] = k[ax];
-            w[ax][0] = 1.f;
-        }
-    }
-    // co-located indices of the (up to 16) stencil nodes and their weights
-    int idx[16];
-    R wt[16];
-    int ns = 0;
-    for (int c = 0; c < np[2]; ++c)
-        for (int b = 0; b < np[1]; ++b)
-            for (int aa = 0; aa < np[0]; ++aa) {
-                const int64_t key = ((int64_t)(pos[2][c] >> 1) * a.my + (pos[1][b] >> 1)) * a.mx + (pos[0][aa] >> 1);
-                idx[ns] = tfmap[key];
-                wt[ns] = R(w[0][aa]) * R(w[1][b]) * R(w[2][c]);
-                ++ns;
-            }
-    R s[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if ((m.w >> i) & 1) {
-            R acc = R(0);
-            for (int q = 0; q < ns; ++q) acc += wt[q] * S[(int64_t)i * a.ntf + idx[q]];
-            s[i] = acc;
-        } else {
-            s[i] = F::load(src + (int64_t)i * g.qs + src_off<DIM>(g, m.x, m.y, m.z, i));
-        }
-    }
-    R drho, j[3];
-    moments<DIM, R>(s, drho, j);
-    const R rho = R(F::rho0) + drho;
-    const R u[3] = {j[0] / rho, j[1] / rho, DIM == 3 ? j[2] / rho : R(0)};
-    bgk<DIM, EQ, R>(s, R(F::rho0), drho, u, R(a.keep));
-    const int64_t o = node_off(g, m.x, m.y, m.z);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) F::store(dst + (int64_t)i * g.qs + o, s[i]);
-}
-
-// ---------------------------------------------------------------- restriction
-// Coarse co-located node t <-> child co-located node t (same ordering).
-template <int DIM, int EQ, int P>
-__global__ __launch_bounds__(64) void k_restrict(LevelDev g, typename Form<P>::T* __restrict__ dst,
-                                                 const int4* __restrict__ meta, int n,
-                                                 const typename Form<P>::R* __restrict__ S,
-                                                 const typename Form<P>::R* __restrict__ X, double invR,
-                                                 double keep)
-{
-    using F = Form<P>;
-    using R = typename F::R;
-    constexpr int Q = Lat<DIM>::Q;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const int4 m = meta[t];
-    const R drho = X[t];
-    const R u[3] = {X[(int64_t)n + t], X[2 * (int64_t)n + t], X[3 * (int64_t)n + t]};
-    const R uu = u[0] * u[0] + u[1] * u[1] + (DIM == 3 ? u[2] * u[2] : R(0));
-    R s[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const R e = eq_s<DIM, EQ, R>(i, R(F::rho0), drho, u, uu);
-        s[i] = e + R(invR) * (S[(int64_t)i * n + t] - e);
-    }
-    bgk<DIM, EQ, R>(s, R(F::rho0), drho, u, R(keep));
-    const int64_t o = node_off(g, m.x, m.y, m.z);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) F::store(dst + (int64_t)i * g.qs + o, s[i]);
-}
-
 // ---------------------------------------------------------------- init / conversion
-template <int DIM>
-__device__ __forceinline__ bool is_hole(const LevelDev& g, int x, int y, int z)
-{
-    return g.has_child && x > g.clo[0] && x < g.chi[0] && y > g.clo[1] && y < g.chi[1] &&
-           (DIM == 2 || (z > g.clo[2] && z < g.chi[2]));
-}
-
+// Dense [n] / [D][n] arrays are indexed d = (z*ny + y)*nx + x.
 template <int DIM, int EQ, int P>
 __global__ __launch_bounds__(256) void k_init(LevelDev g, typename Form<P>::T* __restrict__ dst,
                                               const double* __restrict__ rho, const double* __restrict__ u)
@@ -400,10 +438,9 @@ __global__ __launch_bounds__(256) void k_init(LevelDev g, typename Form<P>::T* _
     const int y = blockIdx.y * 4 + threadIdx.y;
     const int z = blockIdx.z;
     if (x >= g.nx || y >= g.ny) return;
-    const int64_t o = node_off(g, x, y, z);
     if (is_hole<DIM>(g, x, y, z)) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.qs + o] = F::nan();
+        for (int i = 0; i < Q; ++i) dst[eoff<DIM>(g, i, x, y, z)] = F::nan();
         return;
     }
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
@@ -416,7 +453,7 @@ __global__ __launch_bounds__(256) void k_init(LevelDev g, typename Form<P>::T* _
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const double e = eq_s<DIM, EQ, double>(i, F::rho0, drho, uu3, uu);
-        F::store(dst + (int64_t)i * g.qs + o, R(e));
+        F::store(dst + eoff<DIM>(g, i, x, y, z), R(e));
     }
 }
 
@@ -433,12 +470,11 @@ __global__ __launch_bounds__(256) void k_read(LevelDev g, const typename Form<P>
     if (x >= g.nx || y >= g.ny) return;
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const int64_t d = ((int64_t)z * g.ny + y) * g.nx + x;
-    const int64_t o = node_off(g, x, y, z);
     const bool hole = is_hole<DIM>(g, x, y, z);
     double r = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const double s = hole ? __builtin_nan("") : (double)F::load(src + (int64_t)i * g.qs + o);
+        const double s = hole ? __builtin_nan("") : (double)F::load(src + eoff<DIM>(g, i, x, y, z));
         const double f = s + F::rho0 * Lat<DIM>::w[i];
         if (fout) fout[(int64_t)i * n + d] = f;
         r += f;
@@ -483,8 +519,7 @@ struct ProbeArgs {
     int n;
     int64_t capacity;
     const void* buf[32];   // storage buffer holding the probe's node
-    int64_t off[32];       // node offset in that buffer
-    int64_t qs[32];
+    int64_t off[32];       // element offset of direction 0 of that node (directions 64 apart)
 };
 
 // One workgroup; p' = (rho - 1)/3 in FP64 after each coarse step.
@@ -497,9 +532,9 @@ __global__ __launch_bounds__(64) void k_probe(ProbeArgs a, double* __restrict__ 
     const int64_t step = *counter;
     const int p = threadIdx.x;
     if (p < a.n && step < a.capacity) {
-        const typename F::T* b = reinterpret_cast<const typename F::T*>(a.buf[p]);
+        const typename F::T* b = reinterpret_cast<const typename F::T*>(a.buf[p]) + a.off[p];
         double r = F::rho0;
-        for (int i = 0; i < Q; ++i) r += (double)F::load(b + (int64_t)i * a.qs[p] + a.off[p]);
+        for (int i = 0; i < Q; ++i) r += (double)F::load(b + i * 64);
         series[step * a.n + p] = (r - 1.0) / 3.0;
     }
     __syncthreads();
@@ -535,10 +570,9 @@ __global__ __launch_bounds__(256) void k_balance(LevelDev g, const typename Form
         if (g.has_child && x >= g.clo[0] && x <= g.chi[0] && y >= g.clo[1] && y <= g.chi[1] &&
             (DIM == 2 || (z >= g.clo[2] && z <= g.chi[2])))
             continue;   // hole or owned by the finer level
-        const int64_t o = node_off(g, x, y, z);
         double r = 0.0, j[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < Q; ++i) {
-            const double f = (double)F::load(src + (int64_t)i * g.qs + o) + F::rho0 * Lat<DIM>::w[i];
+            const double f = (double)F::load(src + eoff<DIM>(g, i, x, y, z)) + F::rho0 * Lat<DIM>::w[i];
             r += f;
             j[0] += cdir<DIM>(i, 0) * f;
             j[1] += cdir<DIM>(i, 1) * f;
