@@ -98,8 +98,8 @@ struct HostLevel {
         TileMap m;
         m.tx = (nx + 63) / 64;
         m.ty = (ny + 3) / 4;
-        m.ntiles = m.tx * m.ty * nz;
-        m.per = (m.ntiles + 7) / 8;
+        m.nrows = m.ty * nz;
+        m.per = m.tx * ((m.nrows + 7) / 8);
         return m;
     }
     int64_t elem0(int Q, int x, int y, int z) const

@@ -22,8 +22,8 @@
 //             missing directions by 4-point 1-D interpolation from LDS and
 //             collide.  Halo co-located nodes are recomputed, not exchanged;
 //   bulk      fused pull-stream + BGK of every other node (Eq.(LBMequation),
-//             Eq.(LBMscheme_reg) with BGK), 64 x 4 node tiles dealt to the
-//             8 XCDs in contiguous runs.
+//             Eq.(LBMscheme_reg) with BGK), 64 x 4 node tiles, whole tile
+//             rows per XCD, rows interleaved over the 8 XCDs.
 // Plus initialisation, conversion, probe and balance kernels.
 #pragma once
 #include <hip/hip_fp16.h>
@@ -148,10 +148,16 @@ struct SegLimits {
 };
 constexpr int kBlock = 256;
 
+// Bulk tiles are 64 x 4 nodes.  A tile row is the tx tiles sharing one
+// (4-row group, z).  Workgroups are dealt round-robin to the 8 XCDs, so
+// workgroup b = 8 m + c runs on XCD c; it takes tile m % tx of tile row
+// c + 8 (m / tx).  Each XCD walks whole tile rows (x neighbours, whose
+// shifted pulls share cache lines, stay in one L2) and the rows of all XCDs
+// interleave over the domain (holes do not leave some XCDs idle).
 struct TileMap {
-    int tx, ty;      // 64 x 4 tiles per row, per column
-    int ntiles;      // tx * ty * nz
-    int per;         // ceil(ntiles / 8)
+    int tx, ty;      // tiles per tile row, 4-row groups per plane
+    int nrows;       // tile rows: ty * nz
+    int per;         // workgroups per XCD: tx * ceil(nrows / 8)
 };
 
 struct LevelArgs {
@@ -365,14 +371,13 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
     using R = typename F::R;
     constexpr int Q = Lat<DIM>::Q;
     const TileMap& tm = a.tm;
-    // contiguous runs of tiles per XCD (workgroups are dealt round-robin to 8 XCDs)
-    const int t = (bb & 7) * tm.per + (bb >> 3);
-    if (t >= tm.ntiles) return;
-    const int txy = tm.tx * tm.ty;
-    const int z = t / txy;
-    const int r = t - z * txy;
-    const int ty = r / tm.tx;
-    const int x = (r - ty * tm.tx) * 64 + (threadIdx.x & 63);
+    const int m = bb >> 3;
+    const int rr = m / tm.tx;
+    const int row = (bb & 7) + 8 * rr;
+    if (row >= tm.nrows) return;
+    const int z = row / tm.ty;
+    const int ty = row - z * tm.ty;
+    const int x = (m - rr * tm.tx) * 64 + (threadIdx.x & 63);
     const int y = ty * 4 + (threadIdx.x >> 6);
     const LevelDev& g = a.g;
     if (x >= g.nx || y >= g.ny) return;
