@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP16 side runs")
+    ap.add_argument("--workload", default="pulse_vortices_3level", choices=["pulse_vortices_3level", "pulse_ring_3d"],
+                    help="3-level 2048^2 D2Q9 (default) or 2-level 256^3 D3Q19")
+    ap.add_argument("--copy-only", action="store_true", help="only run the plain copy kernel (counter calibration)")
     return ap.parse_args()
 
 
@@ -124,7 +127,7 @@ def roofline(form, Q):
             traffic = rec["bytes_per_launch"][key]
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": f"k_bulk level {best['level']}", "algorithmic_bytes_per_launch": algo,
+            "kernel": f"k_level (level {best['level']} substep)", "algorithmic_bytes_per_launch": algo,
             "avg_launch_ms": round(avg_ms, 5)}
 
 
@@ -162,7 +165,20 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
-    wl = W.pulse_vortices_3level(seed=2, n0=args.n0, steps=args.steps)
+    from paper_2004_14887_amd.sim import copy_calibration
+
+    copy_gbs, copy_ms = copy_calibration()
+    log(f"copy kernel: {copy_gbs:.1f} GB/s ({copy_ms:.4f} ms per 512 MiB copy)")
+    if args.copy_only:
+        print(json.dumps({"copy_gbs": round(copy_gbs, 1), "copy_ms": copy_ms}))
+        return
+    if args.workload == "pulse_ring_3d":
+        n0 = args.n0 if args.n0 != 2048 else 256
+        wl = W.pulse_ring_3d(seed=3, n0=n0, steps=args.steps)
+        mk = lambda steps: W.pulse_ring_3d(seed=3, n0=n0, steps=steps)
+    else:
+        wl = W.pulse_vortices_3level(seed=2, n0=args.n0, steps=args.steps)
+        mk = lambda steps: W.pulse_vortices_3level(seed=2, n0=args.n0, steps=steps)
     main_form = run_form(wl, args.precision, args.steps, args.warmup, args.latency_steps, args.timing_steps)
     side = {}
     if not args.no_compare:
@@ -186,7 +202,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(W.pulse_vortices_3level(seed=2, n0=args.n0, steps=args.cpu_steps), args.cpu_steps)
+        cpu = cpu_baseline(mk(args.cpu_steps), args.cpu_steps)
     Q = wl.Q
     rl = roofline(main_form, Q)
     bpv = bytes_per_value(args.precision)
@@ -206,9 +222,11 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f32 (f16 storage)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": wl.name, "lattice": wl.lattice, "levels": wl.n_levels, "n0": list(wl.n0),
+                   "steps_per_run": args.steps,
                    "boxes": [list(map(list, b)) for b in wl.boxes], "tau0": wl.tau0, "coupling": "DC2",
                    "precision": args.precision, "updates_per_step": main_form["updates_per_step"]},
         "hbm_roofline_frac_of_mlups": round(hbm_frac_mlups, 4),
+        "copy_kernel_gbs": round(copy_gbs, 1),
         "latency_ms": {"p50": round(main_form["p50"], 5), "p99": round(main_form["p99"], 5)},
         "roofline": rl,
         "cpu_baseline": cpu,

@@ -132,12 +132,22 @@ dclbm_status dclbm_read_probes(const dclbm_sim* sim, double* d_out, int64_t* n_s
  * Synchronises; also latches DCLBM_ERR_UNSTABLE on a non-finite density. */
 dclbm_status dclbm_balance(dclbm_sim* sim, double h_out[5]);
 
-/* Instrumentation: when on, steps run without graphs and HIP events bracket
- * every bulk stream-and-collide launch; dclbm_bulk_time returns the summed
- * milliseconds, launch count and active bulk nodes per launch of a level. */
+/* Instrumentation: when on, steps run without graphs and every level-substep
+ * launch carries start/stop events in its dispatch; dclbm_bulk_time returns
+ * the summed milliseconds, the launch count and the nodes one launch of that
+ * level updates (active nodes minus the coarse co-located nodes, which the
+ * child's synchronous substep updates). */
 dclbm_status dclbm_set_timing(dclbm_sim* sim, int32_t on);
 dclbm_status dclbm_bulk_time(dclbm_sim* sim, int32_t level, double* ms, int64_t* launches,
                              int64_t* nodes_per_launch);
+
+/* Bandwidth reference: copies `bytes` (multiple of 16, 16-byte aligned
+ * device buffers) from d_src to d_dst `repeats` times on the stream with a
+ * plain 16-byte-per-lane copy kernel and returns the mean milliseconds per
+ * copy (read + write of `bytes` each).  Used to state the achievable HBM
+ * bandwidth and to scale the HBM byte counters. */
+dclbm_status dclbm_copy_calibration(void* d_dst, const void* d_src, size_t bytes, void* stream, int32_t repeats,
+                                    double* ms_per_copy);
 
 /* Lattice table: Q, velocities [Q][3] and weights [Q] of a lattice. */
 dclbm_status dclbm_lattice_table(int32_t lattice, int32_t* q, int32_t* h_xi, double* h_w);

@@ -10,6 +10,7 @@
 // (Sec. 3.1, acoustic scaling).  A level substep is one kernel launch; after
 // the first coarse step each coarse step is replayed as one hipGraph (two
 // graphs, one per A/B parity of level 0).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -222,17 +223,21 @@ struct EngineImpl final : Engine {
             a.tfc_meta = Pn.d_tfc;
             a.keep_parent = 1.0 - 1.0 / Pn.tau;
         }
-        const unsigned grid = (unsigned)(a.nb_cap + a.nb_seg + 8 * a.tm.per);
-        hipEvent_t e0 = nullptr, e1 = nullptr;
+        // Segment workgroups go first: their latency-bound work then overlaps
+        // the bulk tiles that start behind them, and none of it lands in the
+        // launch's tail (spreading them over the grid measured slower).
+        a.seg_groups = (a.nb_seg + 7) / 8;
+        a.seg_period = 8;
+        const unsigned grid = (unsigned)(a.nb_cap + 8 * a.seg_groups + 8 * a.tm.per);
         if (s.timing) {
+            // start/stop events travel in the dispatch packet of the kernel itself
+            hipEvent_t e0 = nullptr, e1 = nullptr;
             (void)hipEventCreate(&e0);
             (void)hipEventCreate(&e1);
-            (void)hipEventRecord(e0, s.stream);
-        }
-        hipLaunchKernelGGL((k_level<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, a);
-        if (s.timing) {
-            (void)hipEventRecord(e1, s.stream);
+            hipExtLaunchKernelGGL((k_level<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, e0, e1, 0, a);
             s.tev[l].push_back({e0, e1});
+        } else {
+            hipLaunchKernelGGL((k_level<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, a);
         }
     }
     void probe(Sim& s) override
@@ -567,8 +572,41 @@ static dclbm_status build_geometry(Sim& s)
                         L.ie_meta.push_back(make_int4(x, y, z, (int)(all & ~Kf)));
                     }
                 }
+        // Renumber co-located and hanging nodes in segment order, so that one
+        // segment's ring entries, shared states and metadata are contiguous
+        // (its gathers then touch few cache lines), then build the final tables.
         dclbm_status st = build_segments(s, l);
         if (st != DCLBM_OK) return st;
+        {
+            std::vector<int> tf_order, ie_order = L.seg_ie;
+            for (size_t g = 0; g < L.seg_info.size(); ++g) {
+                const int4 info = L.seg_info[g];
+                for (int j = 0; j < info.y; ++j) {
+                    const int e = L.seg_tf[info.x + j];
+                    if ((e >> 30) & 1) tf_order.push_back(e & 0x3fffffff);
+                }
+            }
+            if (tf_order.size() != L.tf_meta.size() || ie_order.size() != L.ie_meta.size())
+                return fail(DCLBM_ERR_INVALID, "level %d: segment ownership does not cover the interface", l);
+            // the parent's co-located list was appended in this level's order, at its end
+            const size_t base = Pn.tfc_meta.size() - L.tf_meta.size();
+            std::vector<int4> tf2, tfc2, ie2;
+            for (int t : tf_order) {
+                tf2.push_back(L.tf_meta[t]);
+                tfc2.push_back(Pn.tfc_meta[base + t]);
+            }
+            for (int e : ie_order) ie2.push_back(L.ie_meta[e]);
+            L.tf_meta = tf2;
+            L.ie_meta = ie2;
+            std::copy(tfc2.begin(), tfc2.end(), Pn.tfc_meta.begin() + base);
+            std::fill(L.tfmap.begin(), L.tfmap.end(), -1);
+            for (size_t t = 0; t < L.tf_meta.size(); ++t) {
+                const int4& m = L.tf_meta[t];
+                L.tfmap[((size_t)(m.z / 2) * L.my + m.y / 2) * L.mx + m.x / 2] = (int)t;
+            }
+            st = build_segments(s, l);
+            if (st != DCLBM_OK) return st;
+        }
     }
     // probes: finest level whose closed box contains the point
     s.probes.clear();
@@ -969,6 +1007,32 @@ dclbm_status dclbm_balance(dclbm_sim* sim, double h_out[5])
         for (size_t l = 0; l < s.lv.size(); ++l) h_out[k] += res[l][k];
     }
     return read_flags(s);
+}
+
+dclbm_status dclbm_copy_calibration(void* d_dst, const void* d_src, size_t bytes, void* stream, int32_t repeats,
+                                    double* ms_per_copy)
+{
+    if (!d_dst || !d_src || bytes < 16 || (bytes & 15) || ((uintptr_t)d_dst & 15) || ((uintptr_t)d_src & 15) ||
+        repeats < 1)
+        return fail(DCLBM_ERR_INVALID, "copy calibration needs 16-byte aligned buffers, a multiple of 16 bytes");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = (int64_t)(bytes / 16);
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 1 << 20);
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, st, (const uint4*)d_src, (uint4*)d_dst, n);
+    HIPCHECK(hipEventRecord(e0, st));
+    for (int r = 0; r < repeats; ++r)
+        hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, st, (const uint4*)d_src, (uint4*)d_dst, n);
+    HIPCHECK(hipEventRecord(e1, st));
+    HIPCHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (ms_per_copy) *ms_per_copy = ms / repeats;
+    return DCLBM_OK;
 }
 
 dclbm_status dclbm_set_timing(dclbm_sim* sim, int32_t on)

@@ -166,7 +166,9 @@ struct LevelArgs {
     void* dst;
     double keep;          // 1 - 1/tau_l
     TileMap tm;
-    int nb_cap, nb_seg;   // workgroups of the capture and segment roles (first in the grid)
+    int nb_cap, nb_seg;   // workgroups of the capture and segment roles
+    int seg_groups;       // ceil(nb_seg / 8)
+    int seg_period;       // a group of 8 segment workgroups opens every seg_period workgroups
     // capture (level has a child): coarse co-located nodes of this level
     const int4* cap_meta; // (x, y, z, K^c mask)
     int n_cap;
@@ -208,21 +210,28 @@ __device__ __forceinline__ void role_capture(const LevelArgs& a, int b)
     const T* src = (const T*)a.src;
     R* H = (R*)a.H_own;
     const int64_t n = a.n_cap, slot = (int64_t)Q * n;
-    // every load before any store: one memory round trip per node
-    R v[Q], h1[Q], h2[Q];
+    // loads of a chunk of directions before its stores (the ring slots do not
+    // alias, but the compiler cannot know it); chunks bound the registers held
+    constexpr int CH = 7;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const bool k = (m.w >> i) & 1;
-        v[i] = k ? F::load(src + src_off<DIM>(a.g, m.x, m.y, m.z, i)) : R(0);
-        h1[i] = k ? H[slot + i * n + t] : R(0);
-        h2[i] = k ? H[2 * slot + i * n + t] : R(0);
-    }
+    for (int i0 = 0; i0 < Q; i0 += CH) {
+        R v[CH], h1[CH], h2[CH];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if (!((m.w >> i) & 1)) continue;
-        H[i * n + t] = h1[i];
-        H[slot + i * n + t] = h2[i];
-        H[2 * slot + i * n + t] = v[i];
+        for (int c = 0; c < CH; ++c) {
+            const int i = i0 + c;
+            const bool k = i < Q && ((m.w >> i) & 1);
+            v[c] = k ? F::load(src + src_off<DIM>(a.g, m.x, m.y, m.z, i)) : R(0);
+            h1[c] = k ? H[slot + i * n + t] : R(0);
+            h2[c] = k ? H[2 * slot + i * n + t] : R(0);
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int i = i0 + c;
+            if (i >= Q || !((m.w >> i) & 1)) continue;
+            H[i * n + t] = h1[c];
+            H[slot + i * n + t] = h2[c];
+            H[2 * slot + i * n + t] = v[c];
+        }
     }
 }
 
@@ -239,7 +248,9 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
     T* dst = (T*)a.dst;
     const R rho0 = R(F::rho0);
     const int j = threadIdx.x;
-    // ---- phase 1: co-located nodes (own and halo)
+    // ---- phase 1: co-located nodes (own and halo).  Column j of the LDS
+    // tile holds the node's h (fine value where Gamma = 1, time-interpolated
+    // coarse value where Gamma = R), then its completed populations.
     if (j < info.y) {
         const int e = a.seg_tf[info.x + j];
         const int t = e & 0x3fffffff;
@@ -248,44 +259,51 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
         const uint32_t gR = (uint32_t)m.w;
         const R* H = (const R*)a.H_parent;
         const int64_t n = a.n_tf, slot = (int64_t)Q * n;
-        R h[Q], gc[Q];
+        volatile R* col = lds + j;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
+            R v;
             if ((gR >> i) & 1u) {
                 const R Hm = H[i * n + t], H0 = H[slot + i * n + t], Hp = H[2 * slot + i * n + t];
-                R v;
                 if (a.substep == 2)
                     v = Hp;
                 else if (a.first)
                     v = R(0.5) * H0 + R(0.5) * Hp;
                 else
                     v = R(-0.125) * Hm + R(0.75) * H0 + R(0.375) * Hp;
-                gc[i] = v;
-                h[i] = v;
             } else {
-                gc[i] = R(0);
-                h[i] = F::load(src + src_off<DIM>(a.g, m.x, m.y, m.z, i));
+                v = F::load(src + src_off<DIM>(a.g, m.x, m.y, m.z, i));
             }
+            col[i * TFM] = v;
         }
+        auto hv = [&](int i) -> R { return col[i * TFM]; };
         R drho, u[3];
-        const int it = newton<DIM, EQ, R>(h, gR, R(a.Rfac), rho0, R(a.tol), a.maxit, drho, u);
+        const int it = newton_v<DIM, EQ, R>(hv, gR, R(a.Rfac), rho0, R(a.tol), a.maxit, drho, u);
         if (it < 0) {
             if (owned) atomicOr(a.flags, 1);
-            R jj[3];
-            moments<DIM, R>(h, drho, jj);
+            R jj[3] = {R(0), R(0), R(0)};
+            drho = R(0);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const R v = hv(i);
+                drho += v;
+                jj[0] += R(cdir<DIM>(i, 0)) * v;
+                jj[1] += R(cdir<DIM>(i, 1)) * v;
+                jj[2] += R(cdir<DIM>(i, 2)) * v;
+            }
             const R rr = rho0 + drho;
             u[0] = jj[0] / rr;
             u[1] = jj[1] / rr;
             u[2] = DIM == 3 ? jj[2] / rr : R(0);
         }
         const R uu = u[0] * u[0] + u[1] * u[1] + (DIM == 3 ? u[2] * u[2] : R(0));
+        // Eq.(rescff) on every coarse-coupled direction
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             if ((gR >> i) & 1u) {
                 const R e0 = eq_s<DIM, EQ, R>(i, rho0, drho, u, uu);
-                h[i] = e0 + R(a.Rfac) * (gc[i] - e0);
+                col[i * TFM] = e0 + R(a.Rfac) * (col[i * TFM] - e0);
             }
-            lds[i * TFM + j] = h[i];
         }
         if (owned) {
             R* X = (R*)a.X;
@@ -297,24 +315,21 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
                 // Eq.(rescfc): every coarse population from the completed fine
                 // ones, then the coarse collision with X
                 const int4 pm = a.tfc_meta[t];
-                const double invR = 1.0 / a.Rfac;
-                R c[Q];
+                const R invR = R(1.0 / a.Rfac), keepp = R(a.keep_parent);
+                T* dp = (T*)a.dst_parent;
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     const R e0 = eq_s<DIM, EQ, R>(i, rho0, drho, u, uu);
-                    c[i] = e0 + R(invR) * (h[i] - e0);
+                    const R c = e0 + invR * (col[i * TFM] - e0);
+                    F::store(dp + eoff<DIM>(a.gp, i, pm.x, pm.y, pm.z), e0 + keepp * (c - e0));
                 }
-                bgk<DIM, EQ, R>(c, rho0, drho, u, R(a.keep_parent));
-                T* dp = (T*)a.dst_parent;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) F::store(dp + eoff<DIM>(a.gp, i, pm.x, pm.y, pm.z), c[i]);
             }
-            R c[Q];
+            const R keep = R(a.keep);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) c[i] = h[i];
-            bgk<DIM, EQ, R>(c, rho0, drho, u, R(a.keep));
-#pragma unroll
-            for (int i = 0; i < Q; ++i) F::store(dst + eoff<DIM>(a.g, i, m.x, m.y, m.z), c[i]);
+            for (int i = 0; i < Q; ++i) {
+                const R e0 = eq_s<DIM, EQ, R>(i, rho0, drho, u, uu);
+                F::store(dst + eoff<DIM>(a.g, i, m.x, m.y, m.z), e0 + keep * (col[i * TFM] - e0));
+            }
         }
     }
     __syncthreads();
@@ -325,32 +340,38 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
         const int k[3] = {m.x, m.y, m.z};
         const int N[3] = {a.g.nx - 1, a.g.ny - 1, a.g.nz - 1};
         // odd axes in increasing order carry the stencil; the first one is fastest
-        int oa[2] = {0, 0}, no = 0;
+        // (picked with compile-time indices only, so nothing lands in scratch)
+        int ka = 0, Na = 0, kb = 0, Nb = 0, no = 0;
 #pragma unroll
-        for (int ax = 0; ax < DIM; ++ax)
-            if ((k[ax] & 1) && no < 2) oa[no++] = ax;
-        float w0[4], w1[4] = {1.f, 0.f, 0.f, 0.f};
-        line_weights(k[oa[0]], N[oa[0]], w0);
-        if (no == 2) line_weights(k[oa[1]], N[oa[1]], w1);
-        const int ns = no == 2 ? 16 : 4;
-        int idx[16];
-        R wt[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            idx[q] = q < ns ? a.seg_sten[(int64_t)q * a.n_ie + q0] : 0;
-            wt[q] = q < ns ? R(w0[q & 3]) * R(w1[q >> 2]) : R(0);
+        for (int ax = 0; ax < DIM; ++ax) {
+            if (k[ax] & 1) {
+                if (no == 0) {
+                    ka = k[ax];
+                    Na = N[ax];
+                } else {
+                    kb = k[ax];
+                    Nb = N[ax];
+                }
+                ++no;
+            }
         }
+        float w0[4], w1[4] = {1.f, 0.f, 0.f, 0.f};
+        line_weights(ka, Na, w0);
+        if (no == 2) line_weights(kb, Nb, w1);
+        const int ns = no == 2 ? 16 : 4;
+        const uint32_t miss = (uint32_t)m.w;
         R s[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            if ((m.w >> i) & 1) {
-                R acc = R(0);
+        for (int i = 0; i < Q; ++i)
+            s[i] = ((miss >> i) & 1u) ? R(0) : F::load(src + src_off<DIM>(a.g, m.x, m.y, m.z, i));
 #pragma unroll
-                for (int q = 0; q < 16; ++q)
-                    if (q < ns) acc += wt[q] * lds[i * TFM + idx[q]];
-                s[i] = acc;
-            } else {
-                s[i] = F::load(src + src_off<DIM>(a.g, m.x, m.y, m.z, i));
+        for (int q = 0; q < (DIM == 2 ? 4 : 16); ++q) {
+            if (q < ns) {
+                const int idx = a.seg_sten[(int64_t)q * a.n_ie + q0];
+                const R wq = R(w0[q & 3]) * R(w1[q >> 2]);
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    if ((miss >> i) & 1u) s[i] += wq * lds[i * TFM + idx];
             }
         }
         R drho, jj[3];
@@ -397,6 +418,11 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
     for (int i = 0; i < Q; ++i) F::store(d + i * 64, s[i]);
 }
 
+// Grid order: the capture workgroups first, then segment workgroups in
+// groups of 8 (one per XCD) every seg_period workgroups, bulk tiles in
+// between.  Segment work is latency-bound (Newton, gathers), bulk work is
+// bandwidth-bound, so spreading the segments over the launch overlaps the
+// two; groups of 8 keep bulk workgroup b' on XCD b' % 8 as TileMap assumes.
 template <int DIM, int EQ, int P>
 __global__ __launch_bounds__(kBlock) void k_level(LevelArgs a)
 {
@@ -405,11 +431,17 @@ __global__ __launch_bounds__(kBlock) void k_level(LevelArgs a)
     const int b = blockIdx.x;
     if (b < a.nb_cap) {
         role_capture<DIM, P>(a, b);
-    } else if (b < a.nb_cap + a.nb_seg) {
-        role_segment<DIM, EQ, P>(a, b - a.nb_cap, lds);
-    } else {
-        role_bulk<DIM, EQ, P>(a, b - a.nb_cap - a.nb_seg);
+        return;
     }
+    const int b2 = b - a.nb_cap;
+    const int j = b2 / a.seg_period, r = b2 - j * a.seg_period;
+    if (j < a.seg_groups && r < 8) {
+        const int sg = 8 * j + r;
+        if (sg < a.nb_seg) role_segment<DIM, EQ, P>(a, sg, lds);
+        return;
+    }
+    const int before = 8 * (j < a.seg_groups ? j + 1 : a.seg_groups);
+    role_bulk<DIM, EQ, P>(a, b2 - before);
 }
 
 // ---------------------------------------------------------------- history ring init
@@ -517,6 +549,14 @@ __global__ void k_fill(T* p, int64_t n, T v)
 {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
         p[k] = v;
+}
+
+// Plain 16-byte copy: the bandwidth and HBM-counter reference for the
+// population kernels (read n*16 bytes, write n*16 bytes).
+__global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        dst[k] = src[k];
 }
 
 // ---------------------------------------------------------------- probes

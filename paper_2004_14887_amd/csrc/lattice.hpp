@@ -255,4 +255,66 @@ __device__ __forceinline__ int newton(const R h[], uint32_t gamma_R_mask, R Rfac
     return -1;
 }
 
+// The same Newton iteration with h_i read through an accessor hv(i) (the
+// interface kernels keep h in LDS, so only X, F and J occupy registers).
+template <int DIM, int EQ, typename R, typename HV>
+__device__ __forceinline__ int newton_v(const HV& hv, uint32_t gamma_R_mask, R Rfac, R rho0, R tol, int maxit,
+                                        R& drho, R u[3])
+{
+    constexpr int Q = Lat<DIM>::Q;
+    constexpr int N = DIM + 1;
+    R j[3] = {R(0), R(0), R(0)};
+    drho = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const R v = hv(i);
+        drho += v;
+        if (cdir<DIM>(i, 0)) j[0] += R(cdir<DIM>(i, 0)) * v;
+        if (cdir<DIM>(i, 1)) j[1] += R(cdir<DIM>(i, 1)) * v;
+        if (DIM == 3 && cdir<DIM>(i, 2)) j[2] += R(cdir<DIM>(i, 2)) * v;
+    }
+    const R rho_init = rho0 + drho;
+    u[0] = j[0] / rho_init;
+    u[1] = j[1] / rho_init;
+    u[2] = DIM == 3 ? j[2] / rho_init : R(0);
+    for (int it = 1; it <= maxit; ++it) {
+        const R uu = u[0] * u[0] + u[1] * u[1] + (DIM == 3 ? u[2] * u[2] : R(0));
+        R F[4] = {R(0), R(0), R(0), R(0)};
+        R J[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) J[r][c] = R(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const R G = ((gamma_R_mask >> i) & 1u) ? Rfac : R(1);
+            const R e = eq_s<DIM, EQ, R>(i, rho0, drho, u, uu);
+            R g[4];
+            eq_s_grad<DIM, EQ, R>(i, rho0, drho, u, uu, g);
+            const R d = G * (hv(i) - e);
+            const R phi[4] = {R(1), R(cdir<DIM>(i, 0)), R(cdir<DIM>(i, 1)), R(cdir<DIM>(i, 2))};
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                if (phi[r] == R(0)) continue;
+                F[r] += phi[r] * d;
+#pragma unroll
+                for (int c = 0; c < N; ++c) J[r][c] -= G * phi[r] * g[c];
+            }
+        }
+        R rhs[4] = {-F[0], -F[1], -F[2], -F[3]};
+        R dX[4] = {R(0), R(0), R(0), R(0)};
+        if (!solve_small<N, R>(J, rhs, dX)) return -1;
+        drho += dX[0];
+        R nrm = fabs(dX[0]);
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            u[b] += dX[1 + b];
+            nrm = fmax(nrm, fabs(dX[1 + b]));
+        }
+        if (!(nrm == nrm)) return -1;
+        if (nrm < tol) return it;
+    }
+    return -1;
+}
+
 }  // namespace dclbm

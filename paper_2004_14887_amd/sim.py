@@ -189,3 +189,17 @@ def lattice_table(lattice: str):
     _lib.check(lib.dclbm_lattice_table(_lib.LATTICE[lattice], C.byref(q), xi, w))
     Q = q.value
     return [tuple(xi[3 * i:3 * i + 3]) for i in range(Q)], [w[i] for i in range(Q)]
+
+
+def copy_calibration(nbytes: int = 512 << 20, repeats: int = 20, device="cuda:0", stream=None):
+    """GB/s (read + write) of the library's plain 16-byte copy kernel."""
+    lib = _lib.load()
+    st = stream if stream is not None else torch.cuda.Stream(device=device)
+    a = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    b = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    a.zero_()
+    torch.cuda.synchronize(device)
+    ms = C.c_double()
+    _lib.check(lib.dclbm_copy_calibration(C.c_void_p(b.data_ptr()), C.c_void_p(a.data_ptr()), nbytes,
+                                          C.c_void_p(st.cuda_stream), repeats, C.byref(ms)))
+    return 2.0 * nbytes / (ms.value * 1e-3) / 1e9, ms.value
