@@ -110,7 +110,7 @@ def run_form(wl, prec, steps, warmup, latency_steps, timing_steps):
     return out
 
 
-def roofline(form, Q):
+def roofline(form, Q, workload):
     bpv = bytes_per_value(form["prec"])
     per_node = 2 * Q * bpv                      # read Q + write Q values (A/B pull)
     best = max(form["bulk"], key=lambda b: b["ms"])
@@ -121,14 +121,18 @@ def roofline(form, Q):
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tfile):
         rec = json.load(open(tfile))
-        key = f"{form['prec']}_level{best['level']}"
+        key = f"{workload}/{form['prec']}/level{best['level']}"
         src = open(os.path.join(ROOT, "paper_2004_14887_amd", "csrc", "kernels.hpp"), "rb").read()
         if rec.get("kernels_sha256") == hashlib.sha256(src).hexdigest() and key in rec.get("bytes_per_launch", {}):
             traffic = rec["bytes_per_launch"][key]
+    per_level = [{"level": b["level"], "launches": b["launches"], "nodes_per_launch": b["nodes_per_launch"],
+                  "avg_launch_ms": round(b["ms"] / max(1, b["launches"]), 5),
+                  "gbs": round(b["nodes_per_launch"] * per_node / (b["ms"] / max(1, b["launches"]) * 1e-3) / 1e9, 1)}
+                 for b in form["bulk"]]
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": f"k_level (level {best['level']} substep)", "algorithmic_bytes_per_launch": algo,
-            "avg_launch_ms": round(avg_ms, 5)}
+            "avg_launch_ms": round(avg_ms, 5), "per_level": per_level}
 
 
 def cpu_baseline(wl_full, steps):
@@ -204,7 +208,7 @@ def main():
         log("cpu baseline (oracle)")
         cpu = cpu_baseline(mk(args.cpu_steps), args.cpu_steps)
     Q = wl.Q
-    rl = roofline(main_form, Q)
+    rl = roofline(main_form, Q, wl.name)
     bpv = bytes_per_value(args.precision)
     mlups = main_form["mlups"]
     hbm_frac_mlups = mlups * 1e6 * 2 * Q * bpv / (HBM_PEAK_GBS * 1e9)

@@ -230,10 +230,12 @@ struct EngineImpl final : Engine {
         a.seg_period = 8;
         const unsigned grid = (unsigned)(a.nb_cap + 8 * a.seg_groups + 8 * a.tm.per);
         if (s.timing) {
-            // start/stop events travel in the dispatch packet of the kernel itself
+            // start/stop events travel in the dispatch packet of the kernel
+            // itself; without the system-scope fence the stop stamp is not
+            // delayed by a cache write-back the next launch does not need
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            (void)hipEventCreate(&e0);
-            (void)hipEventCreate(&e1);
+            (void)hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
+            (void)hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
             hipExtLaunchKernelGGL((k_level<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, e0, e1, 0, a);
             s.tev[l].push_back({e0, e1});
         } else {
