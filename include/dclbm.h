@@ -149,6 +149,86 @@ dclbm_status dclbm_bulk_time(dclbm_sim* sim, int32_t level, double* ms, int64_t*
 dclbm_status dclbm_copy_calibration(void* d_dst, const void* d_src, size_t bytes, void* stream, int32_t repeats,
                                     double* ms_per_copy);
 
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of many simulations of one class (lattice, precision,
+ * eq_order) on one GPU and one stream.  The caller owns the server's device
+ * workspace: fixed tables plus an arena from which every admitted request
+ * takes exactly dclbm_workspace_bytes of its configuration (first fit);
+ * admission waits for a free slot and a fitting block.  A tick retires
+ * finished requests, admits queued ones (arrival order; later requests may
+ * pass one that does not fit yet, a bounded number of times) and enqueues
+ * steps_per_tick coarse steps of every resident simulation as one hipGraph
+ * launch: one persistent launch per level substep of a max_levels mesh plus
+ * one for probes.  Each simulation advances exactly as dclbm_step would
+ * advance it alone (Sec. 3.5 sub-cycling; its own arguments, tables and
+ * state), so its result does not depend on the mix.  A request finishes
+ * after its own step count; its probe series then comes back to the host.
+ * submit may be called from another thread while a thread ticks. */
+typedef struct dclbm_server dclbm_server;
+
+typedef enum { DCLBM_REQ_QUEUED = 0, DCLBM_REQ_RUNNING = 1, DCLBM_REQ_DONE = 2, DCLBM_REQ_FAILED = 3 } dclbm_request_state;
+
+typedef struct {
+    int32_t abi_version;      /* DCLBM_ABI_VERSION */
+    int32_t lattice;          /* class of every request: lattice, precision, eq_order */
+    int32_t precision;
+    int32_t eq_order;
+    int32_t max_levels;       /* deepest mesh admitted, 1..DCLBM_MAX_LEVELS (sets the phases per step: 2^L - 1) */
+    int32_t max_slots;        /* simulations resident at once, 1..1024 */
+    int32_t steps_per_tick;   /* coarse steps per tick, 1..64 */
+    int32_t max_probes;       /* probes per request, 0..32 */
+    int64_t max_probe_steps;  /* largest step count of a request (its probe series is kept whole) */
+    int64_t max_level_nodes;  /* dense nodes of the largest level of any request (staging of initial fields) */
+    int32_t grid;             /* workgroups of each persistent launch (multiple of 8); 0: all resident at once */
+    int32_t max_inflight;     /* ticks enqueued ahead of the GPU before a tick waits; 0: 2 */
+} dclbm_server_config;
+
+typedef struct {
+    double t_submit, t_admit, t_done; /* seconds since the server was created (host clock) */
+    int64_t steps;            /* coarse steps requested */
+    int64_t updates;          /* node updates: steps * sum_l 2^l active_l */
+    int64_t workspace_bytes;  /* footprint taken from the arena while resident */
+    int32_t slot;             /* slot it ran in (-1 before admission) */
+    int32_t state;            /* dclbm_request_state */
+    int32_t status;           /* DCLBM_OK, or the latched error (DCLBM_ERR_NEWTON, DCLBM_ERR_UNSTABLE) */
+    int32_t n_probes;
+} dclbm_request_info;
+
+typedef struct {
+    int64_t ticks;            /* graph launches so far */
+    int32_t running, queued;  /* resident (including finishing) and waiting requests */
+    int64_t arena_bytes, arena_free, arena_largest_free;
+    int32_t grid;             /* workgroups of each persistent launch */
+    int32_t n_phases;         /* persistent launches per coarse step, before the probe launch */
+} dclbm_server_info;
+
+/* Device bytes of a server whose arena holds arena_bytes. */
+dclbm_status dclbm_server_workspace_bytes(const dclbm_server_config* cfg, size_t arena_bytes, size_t* total);
+/* Create a server in the caller's workspace (256-byte aligned) on a
+ * non-default stream (hipStream_t as void*); captures its tick graph. */
+dclbm_status dclbm_server_create(const dclbm_server_config* cfg, void* d_workspace, size_t bytes, void* stream,
+                                 dclbm_server** out);
+dclbm_status dclbm_server_destroy(dclbm_server* server);
+/* Queue a request: a configuration of the server's class (its probe_capacity
+ * is replaced by steps), `steps` coarse steps, and initial fields per level
+ * (h_rho[l]: [n_l] FP64, h_u[l]: [D][n_l] FP64, dense as for
+ * dclbm_init_equilibrium, host memory, copied before return).  The geometry
+ * is validated here (DCLBM_ERR_INVALID; DCLBM_ERR_NOMEM if it can never fit). */
+dclbm_status dclbm_server_submit(dclbm_server* server, const dclbm_config* cfg, int64_t steps,
+                                 const double* const* h_rho, const double* const* h_u, uint64_t* id);
+/* One scheduling round (see above).  Blocks only to keep at most
+ * max_inflight ticks queued on the stream. */
+dclbm_status dclbm_server_tick(dclbm_server* server, int32_t* n_running, int32_t* n_queued);
+dclbm_status dclbm_server_poll(dclbm_server* server, uint64_t id, int32_t* state);
+/* Probe series [steps][n_probes] FP64 of a finished request (h_probes may
+ * be NULL) and its record; DCLBM_ERR_BUSY while it has not finished, the
+ * latched error if it failed. */
+dclbm_status dclbm_server_result(dclbm_server* server, uint64_t id, double* h_probes, int64_t* n_steps,
+                                 dclbm_request_info* info);
+/* Forget a finished request. */
+dclbm_status dclbm_server_release(dclbm_server* server, uint64_t id);
+dclbm_status dclbm_server_stats(dclbm_server* server, dclbm_server_info* out);
+
 /* Lattice table: Q, velocities [Q][3] and weights [Q] of a lattice. */
 dclbm_status dclbm_lattice_table(int32_t lattice, int32_t* q, int32_t* h_xi, double* h_w);
 

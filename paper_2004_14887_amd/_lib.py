@@ -48,6 +48,53 @@ class Config(C.Structure):
     ]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32),
+        ("lattice", C.c_int32),
+        ("precision", C.c_int32),
+        ("eq_order", C.c_int32),
+        ("max_levels", C.c_int32),
+        ("max_slots", C.c_int32),
+        ("steps_per_tick", C.c_int32),
+        ("max_probes", C.c_int32),
+        ("max_probe_steps", C.c_int64),
+        ("max_level_nodes", C.c_int64),
+        ("grid", C.c_int32),
+        ("max_inflight", C.c_int32),
+    ]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [
+        ("t_submit", C.c_double),
+        ("t_admit", C.c_double),
+        ("t_done", C.c_double),
+        ("steps", C.c_int64),
+        ("updates", C.c_int64),
+        ("workspace_bytes", C.c_int64),
+        ("slot", C.c_int32),
+        ("state", C.c_int32),
+        ("status", C.c_int32),
+        ("n_probes", C.c_int32),
+    ]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [
+        ("ticks", C.c_int64),
+        ("running", C.c_int32),
+        ("queued", C.c_int32),
+        ("arena_bytes", C.c_int64),
+        ("arena_free", C.c_int64),
+        ("arena_largest_free", C.c_int64),
+        ("grid", C.c_int32),
+        ("n_phases", C.c_int32),
+    ]
+
+
+REQ_STATE = {0: "queued", 1: "running", 2: "done", 3: "failed"}
+
 _lock = threading.Lock()
 _lib = None
 
@@ -74,6 +121,18 @@ _SIGS = {
     "dclbm_lattice_table": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_double)]),
     "dclbm_last_error": (C.c_char_p, []),
+    "dclbm_server_workspace_bytes": (C.c_int, [C.POINTER(ServerConfig), C.c_size_t, C.POINTER(C.c_size_t)]),
+    "dclbm_server_create": (C.c_int, [C.POINTER(ServerConfig), C.c_void_p, C.c_size_t, C.c_void_p,
+                                      C.POINTER(C.c_void_p)]),
+    "dclbm_server_destroy": (C.c_int, [C.c_void_p]),
+    "dclbm_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Config), C.c_int64, C.POINTER(C.c_void_p),
+                                      C.POINTER(C.c_void_p), C.POINTER(C.c_uint64)]),
+    "dclbm_server_tick": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "dclbm_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)]),
+    "dclbm_server_result": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(C.c_int64),
+                                      C.POINTER(RequestInfo)]),
+    "dclbm_server_release": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "dclbm_server_stats": (C.c_int, [C.c_void_p, C.POINTER(ServerInfo)]),
 }
 
 

@@ -7,8 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdclbm.so")
-SOURCES = [os.path.join(HERE, "csrc", "dclbm.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "kernels.hpp"), os.path.join(HERE, "csrc", "lattice.hpp"),
+SOURCES = [os.path.join(HERE, "csrc", "dclbm.hip"), os.path.join(HERE, "csrc", "server.hip")]
+HEADERS = [os.path.join(HERE, "csrc", "kernels.hpp"), os.path.join(HERE, "csrc", "engine.hpp"), os.path.join(HERE, "csrc", "lattice.hpp"),
            os.path.join(ROOT, "include", "dclbm.h")]
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

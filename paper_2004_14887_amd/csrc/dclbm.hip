@@ -25,13 +25,13 @@
 #include <vector>
 
 #include "../../include/dclbm.h"
-#include "kernels.hpp"
+#include "engine.hpp"
 
 namespace dclbm {
 
-static thread_local std::string g_err;
+thread_local std::string g_err;
 
-static dclbm_status fail(dclbm_status s, const char* fmt, ...)
+dclbm_status fail(dclbm_status s, const char* fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -42,133 +42,68 @@ static dclbm_status fail(dclbm_status s, const char* fmt, ...)
     return s;
 }
 
-#define HIPCHECK(expr)                                                                         \
-    do {                                                                                       \
-        hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess) return fail(DCLBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-static int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
-
-struct HostLevel {
-    int nx = 1, ny = 1, nz = 1, nxb = 1;
-    int64_t elems = 0;          // storage elements per buffer (Q per node slot, 64-node row blocks)
-    int periodic = 0, boundary = 0, has_child = 0;
-    int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
-    int plo[3] = {0, 0, 0};
-    double tau = 0.0;
-    int64_t n_active = 0;
-    // interface with the parent (level >= 1)
-    std::vector<int4> tf_meta, ie_meta;   // co-located (x,y,z,Gamma=R mask), hanging (x,y,z,missing mask)
-    std::vector<int> tfmap;               // co-located index at fine coords (2a,2b,2c), -1 elsewhere
-    int mx = 1, my = 1, mz = 1;
-    std::vector<int4> seg_info;           // (tf_off, tf_cnt, ie_off, ie_cnt)
-    std::vector<int> seg_tf, seg_ie, seg_sten;
-    // interface with the child (coarse co-located nodes, child's order)
-    std::vector<int4> tfc_meta;
-    // workspace offsets
-    int64_t off_f[2] = {0, 0}, off_tf = 0, off_ie = 0, off_X = 0, off_tfc = 0, off_H = 0, off_seg_info = 0,
-            off_seg_tf = 0, off_seg_ie = 0, off_seg_sten = 0;
-    // device pointers
-    void* f[2] = {nullptr, nullptr};
-    int4 *d_tf = nullptr, *d_ie = nullptr, *d_tfc = nullptr, *d_seg_info = nullptr;
-    int *d_seg_tf = nullptr, *d_seg_ie = nullptr, *d_seg_sten = nullptr;
-    void *X = nullptr, *H = nullptr;
-    int parity = 0;
-    int64_t captures = 0;
-
-    LevelDev dev() const
-    {
-        LevelDev g;
-        g.nx = nx;
-        g.ny = ny;
-        g.nz = nz;
-        g.nxb = nxb;
-        g.periodic = periodic;
-        g.boundary = boundary;
-        g.has_child = has_child;
-        for (int a = 0; a < 3; ++a) {
-            g.clo[a] = clo[a];
-            g.chi[a] = chi[a];
-        }
-        return g;
-    }
-    int64_t n_dense() const { return (int64_t)nx * ny * nz; }
-    TileMap tiles() const
-    {
-        TileMap m;
-        m.tx = (nx + 63) / 64;
-        m.ty = (ny + 3) / 4;
-        m.nrows = m.ty * nz;
-        m.per = m.tx * ((m.nrows + 7) / 8);
-        return m;
-    }
-    int64_t elem0(int Q, int x, int y, int z) const
-    {
-        return (((int64_t)z * ny + y) * nxb + (x >> 6)) * (Q * 64) + (x & 63);
-    }
-};
-
-struct Sim;
-
-// Type-erased launcher set for one (lattice, equilibrium order, storage form).
-struct Engine {
-    virtual ~Engine() {}
-    virtual void level_step(Sim& s, int l, int substep, int first) = 0;
-    virtual void probe(Sim& s) = 0;
-    virtual void init(Sim& s, int l, const double* rho, const double* u) = 0;
-    virtual void ring_init(Sim& s, int l) = 0;
-    virtual void fill_nan(Sim& s) = 0;
-    virtual void read(Sim& s, int l, double* f, double* rho, double* u) = 0;
-    virtual void read_shared(Sim& s, int l, double* out) = 0;
-    virtual void balance(Sim& s, int l, double* partial, int nblocks) = 0;
-};
-
-struct ProbeLoc {
-    int level;
-    int64_t off;
-};
-
-struct Sim {
-    dclbm_config cfg;
-    int D = 2, Q = 9, P = 0, EQ = 2;
-    size_t tsize = 8, rsize = 8;   // storage and arithmetic element sizes
-    std::vector<HostLevel> lv;
-    std::vector<ProbeLoc> probes;
-    std::vector<int32_t> probe_xyz;
-    hipStream_t stream = nullptr;
-    char* ws = nullptr;
-    size_t ws_bytes = 0, need_bytes = 0;
-    int64_t off_series = 0, off_counter = 0, off_flags = 0, off_partial = 0, off_bal = 0;
-    double* d_series = nullptr;
-    int64_t* d_counter = nullptr;
-    int* d_flags = nullptr;
-    double* d_partial = nullptr;
-    double* d_bal = nullptr;
-    int partial_blocks = 1024;
-    std::unique_ptr<Engine> eng;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    int64_t steps_done = 0;
-    bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[DCLBM_MAX_LEVELS];
-    double tms[DCLBM_MAX_LEVELS] = {0, 0, 0, 0};
-    int64_t tlaunch[DCLBM_MAX_LEVELS] = {0, 0, 0, 0};
-    double newton_tol = 1e-12;
-    int newton_maxit = 20;
-
-    template <typename T>
-    T* at(int64_t off) const
-    {
-        return reinterpret_cast<T*>(ws + off);
-    }
-};
-
-template <typename V>
-static hipError_t upload(Sim& s, void* dst, const std::vector<V>& v)
+// ------------------------------------------------------------------ launch arguments
+LevelArgs level_args(const Sim& s, int l, int substep, int first, unsigned* grid)
 {
-    if (v.empty()) return hipSuccess;
-    return hipMemcpyAsync(dst, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, s.stream);
+    const HostLevel& L = s.lv[l];
+    LevelArgs a;
+    memset(&a, 0, sizeof(a));
+    a.g = L.dev();
+    a.src = L.f[L.parity];
+    a.dst = L.f[L.parity ^ 1];
+    a.keep = 1.0 - 1.0 / L.tau;
+    a.tm = L.tiles();
+    if (L.has_child) {
+        a.n_cap = (int)L.tfc_meta.size();
+        a.nb_cap = (a.n_cap + kBlock - 1) / kBlock;
+        a.cap_meta = L.d_tfc;
+        a.H_own = L.H;
+    }
+    if (l > 0) {
+        const HostLevel& Pn = s.lv[l - 1];
+        a.nb_seg = (int)L.seg_info.size();
+        a.seg_info = L.d_seg_info;
+        a.seg_tf = L.d_seg_tf;
+        a.seg_ie = L.d_seg_ie;
+        a.seg_sten = L.d_seg_sten;
+        a.n_ie = (int)L.ie_meta.size();
+        a.tf_meta = L.d_tf;
+        a.ie_meta = L.d_ie;
+        a.n_tf = (int)L.tf_meta.size();
+        a.H_parent = Pn.H;
+        a.X = L.X;
+        a.substep = substep;
+        a.first = first;
+        a.maxit = s.newton_maxit;
+        a.Rfac = L.tau / (2.0 * Pn.tau);
+        a.tol = s.newton_tol;
+        a.flags = s.d_flags;
+        a.gp = Pn.dev();
+        a.dst_parent = Pn.f[Pn.parity ^ 1];
+        a.tfc_meta = Pn.d_tfc;
+        a.keep_parent = 1.0 - 1.0 / Pn.tau;
+    }
+    // Segment workgroups go first: their latency-bound work then overlaps
+    // the bulk tiles that start behind them, and none of it lands in the
+    // launch's tail (spreading them over the grid measured slower).
+    a.seg_groups = (a.nb_seg + 7) / 8;
+    a.seg_period = 8;
+    *grid = (unsigned)(a.nb_cap + 8 * a.seg_groups + 8 * a.tm.per);
+    return a;
+}
+
+ProbeArgs probe_args(const Sim& s)
+{
+    ProbeArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = (int)s.probes.size();
+    a.capacity = s.cfg.probe_capacity;
+    for (int p = 0; p < a.n; ++p) {
+        const HostLevel& L = s.lv[s.probes[p].level];
+        a.buf[p] = L.f[L.parity];
+        a.off[p] = s.probes[p].off;
+    }
+    return a;
 }
 
 // ------------------------------------------------------------------ engine implementation
@@ -185,50 +120,8 @@ struct EngineImpl final : Engine {
 
     void level_step(Sim& s, int l, int substep, int first) override
     {
-        HostLevel& L = s.lv[l];
-        LevelArgs a;
-        memset(&a, 0, sizeof(a));
-        a.g = L.dev();
-        a.src = L.f[L.parity];
-        a.dst = L.f[L.parity ^ 1];
-        a.keep = 1.0 - 1.0 / L.tau;
-        a.tm = L.tiles();
-        if (L.has_child) {
-            a.n_cap = (int)L.tfc_meta.size();
-            a.nb_cap = (a.n_cap + kBlock - 1) / kBlock;
-            a.cap_meta = L.d_tfc;
-            a.H_own = L.H;
-        }
-        if (l > 0) {
-            HostLevel& Pn = s.lv[l - 1];
-            a.nb_seg = (int)L.seg_info.size();
-            a.seg_info = L.d_seg_info;
-            a.seg_tf = L.d_seg_tf;
-            a.seg_ie = L.d_seg_ie;
-            a.seg_sten = L.d_seg_sten;
-            a.n_ie = (int)L.ie_meta.size();
-            a.tf_meta = L.d_tf;
-            a.ie_meta = L.d_ie;
-            a.n_tf = (int)L.tf_meta.size();
-            a.H_parent = Pn.H;
-            a.X = L.X;
-            a.substep = substep;
-            a.first = first;
-            a.maxit = s.newton_maxit;
-            a.Rfac = L.tau / (2.0 * Pn.tau);
-            a.tol = s.newton_tol;
-            a.flags = s.d_flags;
-            a.gp = Pn.dev();
-            a.dst_parent = Pn.f[Pn.parity ^ 1];
-            a.tfc_meta = Pn.d_tfc;
-            a.keep_parent = 1.0 - 1.0 / Pn.tau;
-        }
-        // Segment workgroups go first: their latency-bound work then overlaps
-        // the bulk tiles that start behind them, and none of it lands in the
-        // launch's tail (spreading them over the grid measured slower).
-        a.seg_groups = (a.nb_seg + 7) / 8;
-        a.seg_period = 8;
-        const unsigned grid = (unsigned)(a.nb_cap + 8 * a.seg_groups + 8 * a.tm.per);
+        unsigned grid = 0;
+        const LevelArgs a = level_args(s, l, substep, first, &grid);
         if (s.timing) {
             // start/stop events travel in the dispatch packet of the kernel
             // itself; without the system-scope fence the stop stamp is not
@@ -245,15 +138,7 @@ struct EngineImpl final : Engine {
     void probe(Sim& s) override
     {
         if (s.probes.empty()) return;
-        ProbeArgs a;
-        memset(&a, 0, sizeof(a));
-        a.n = (int)s.probes.size();
-        a.capacity = s.cfg.probe_capacity;
-        for (int p = 0; p < a.n; ++p) {
-            const HostLevel& L = s.lv[s.probes[p].level];
-            a.buf[p] = L.f[L.parity];
-            a.off[p] = s.probes[p].off;
-        }
+        const ProbeArgs a = probe_args(s);
         hipLaunchKernelGGL((k_probe<DIM, P>), dim3(1), dim3(64), 0, s.stream, a, s.d_series, s.d_counter);
     }
     void init(Sim& s, int l, const double* rho, const double* u) override
@@ -312,6 +197,20 @@ struct EngineImpl final : Engine {
         hipLaunchKernelGGL((k_balance<DIM, P>), dim3(nblocks), dim3(256), 0, s.stream, L.dev(),
                            (const T*)L.f[L.parity], vol, partial, s.d_flags);
     }
+    void launch_multi(hipStream_t st, const MultiArgs& m, unsigned grid) override
+    {
+        hipLaunchKernelGGL((k_level_multi<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, st, m);
+    }
+    void launch_tail(hipStream_t st, const MultiArgs& m, unsigned grid) override
+    {
+        hipLaunchKernelGGL((k_server_tail<DIM, P>), dim3(grid), dim3(64), 0, st, m);
+    }
+    int multi_blocks_per_cu() override
+    {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_level_multi<DIM, EQ, P>, kBlock, 0) != hipSuccess) return 0;
+        return n;
+    }
 };
 
 template <int DIM, int EQ>
@@ -322,7 +221,7 @@ static Engine* make_engine_p(int P)
     return new EngineImpl<DIM, EQ, 2>();
 }
 
-static Engine* make_engine(int D, int EQ, int P)
+Engine* make_engine(int D, int EQ, int P)
 {
     if (D == 2) return EQ == 2 ? make_engine_p<2, 2>(P) : make_engine_p<2, 3>(P);
     return EQ == 2 ? make_engine_p<3, 2>(P) : make_engine_p<3, 3>(P);
@@ -455,7 +354,7 @@ static dclbm_status build_segments(Sim& s, int l)
     return DCLBM_OK;
 }
 
-static dclbm_status build_geometry(Sim& s)
+dclbm_status build_geometry(Sim& s)
 {
     const dclbm_config& c = s.cfg;
     if (c.abi_version != DCLBM_ABI_VERSION) return fail(DCLBM_ERR_INVALID, "abi_version %d != %d", c.abi_version, DCLBM_ABI_VERSION);
@@ -675,22 +574,85 @@ static dclbm_status build_geometry(Sim& s)
     return DCLBM_OK;
 }
 
+dclbm_status sim_attach(Sim& s, void* d_workspace, size_t bytes, hipStream_t stream)
+{
+    if (bytes < s.need_bytes) return fail(DCLBM_ERR_NOMEM, "workspace %zu bytes, need %zu", bytes, s.need_bytes);
+    s.ws = (char*)d_workspace;
+    s.ws_bytes = bytes;
+    s.stream = stream;
+    for (auto& L : s.lv) {
+        for (int b = 0; b < 2; ++b) L.f[b] = s.ws + L.off_f[b];
+        if (!L.tf_meta.empty()) {
+            L.d_tf = s.at<int4>(L.off_tf);
+            L.X = s.ws + L.off_X;
+            L.d_seg_info = s.at<int4>(L.off_seg_info);
+            L.d_seg_tf = s.at<int>(L.off_seg_tf);
+            HIPCHECK(upload(s, L.d_tf, L.tf_meta));
+            HIPCHECK(upload(s, L.d_seg_info, L.seg_info));
+            HIPCHECK(upload(s, L.d_seg_tf, L.seg_tf));
+        }
+        if (!L.ie_meta.empty()) {
+            L.d_ie = s.at<int4>(L.off_ie);
+            L.d_seg_ie = s.at<int>(L.off_seg_ie);
+            L.d_seg_sten = s.at<int>(L.off_seg_sten);
+            HIPCHECK(upload(s, L.d_ie, L.ie_meta));
+            HIPCHECK(upload(s, L.d_seg_ie, L.seg_ie));
+            HIPCHECK(upload(s, L.d_seg_sten, L.seg_sten));
+        }
+        if (!L.tfc_meta.empty()) {
+            L.d_tfc = s.at<int4>(L.off_tfc);
+            L.H = s.ws + L.off_H;
+            HIPCHECK(upload(s, L.d_tfc, L.tfc_meta));
+        }
+    }
+    s.d_series = s.at<double>(s.off_series);
+    s.d_counter = s.at<int64_t>(s.off_counter);
+    s.d_flags = s.at<int>(s.off_flags);
+    s.d_partial = s.at<double>(s.off_partial);
+    s.d_bal = s.at<double>(s.off_bal);
+    s.eng.reset(make_engine(s.D, s.EQ, s.P));
+    s.eng->fill_nan(s);
+    hipLaunchKernelGGL((k_fill<int64_t>), dim3(1), dim3(64), 0, s.stream, s.d_counter, (int64_t)1, (int64_t)0);
+    hipLaunchKernelGGL((k_fill<int>), dim3(1), dim3(64), 0, s.stream, s.d_flags, (int64_t)2, 0);
+    HIPCHECK(hipGetLastError());
+    return DCLBM_OK;
+}
+
 // ------------------------------------------------------------------ stepping
 // One step of level l (substep 1 or 2 of its parent's step) is one launch:
 // its bulk nodes, its coarse history capture (if it has a child) and its
 // interface segments (if it has a parent; at substep 2 they also restrict
 // into the parent).  Then its two child substeps follow.
-static void advance(Sim& s, int l, int substep)
+template <class Fn>
+static void walk(Sim& s, int l, int substep, Fn&& fn)
 {
     HostLevel& L = s.lv[l];
     const int first = (l > 0 && s.lv[l - 1].captures <= 1) ? 1 : 0;
-    s.eng->level_step(s, l, substep, first);
+    fn(l, substep, first);
     if (L.has_child) {
         L.captures++;
-        advance(s, l + 1, 1);
-        advance(s, l + 1, 2);
+        walk(s, l + 1, 1, fn);
+        walk(s, l + 1, 2, fn);
     }
     L.parity ^= 1;
+}
+
+static void advance(Sim& s, int l, int substep)
+{
+    walk(s, l, substep, [&](int lv, int sub, int first) { s.eng->level_step(s, lv, sub, first); });
+}
+
+void record_coarse_step(Sim& s, std::vector<StepRecord>& out, ProbeArgs& probe_after)
+{
+    out.clear();
+    walk(s, 0, 0, [&](int lv, int sub, int first) {
+        StepRecord r;
+        r.level = lv;
+        r.substep = sub;
+        r.args = level_args(s, lv, sub, first, &r.grid);
+        out.push_back(r);
+    });
+    probe_after = probe_args(s);
 }
 
 // Host-side state change of one coarse step, without launching anything.
@@ -819,45 +781,8 @@ dclbm_status dclbm_create(const dclbm_config* cfg, void* d_workspace, size_t byt
         s.off_partial = tmp.off_partial;
         s.off_bal = tmp.off_bal;
     }
-    if (bytes < s.need_bytes) return fail(DCLBM_ERR_NOMEM, "workspace %zu bytes, need %zu", bytes, s.need_bytes);
-    s.ws = (char*)d_workspace;
-    s.ws_bytes = bytes;
-    s.stream = (hipStream_t)stream;
-    for (auto& L : s.lv) {
-        for (int b = 0; b < 2; ++b) L.f[b] = s.ws + L.off_f[b];
-        if (!L.tf_meta.empty()) {
-            L.d_tf = s.at<int4>(L.off_tf);
-            L.X = s.ws + L.off_X;
-            L.d_seg_info = s.at<int4>(L.off_seg_info);
-            L.d_seg_tf = s.at<int>(L.off_seg_tf);
-            HIPCHECK(upload(s, L.d_tf, L.tf_meta));
-            HIPCHECK(upload(s, L.d_seg_info, L.seg_info));
-            HIPCHECK(upload(s, L.d_seg_tf, L.seg_tf));
-        }
-        if (!L.ie_meta.empty()) {
-            L.d_ie = s.at<int4>(L.off_ie);
-            L.d_seg_ie = s.at<int>(L.off_seg_ie);
-            L.d_seg_sten = s.at<int>(L.off_seg_sten);
-            HIPCHECK(upload(s, L.d_ie, L.ie_meta));
-            HIPCHECK(upload(s, L.d_seg_ie, L.seg_ie));
-            HIPCHECK(upload(s, L.d_seg_sten, L.seg_sten));
-        }
-        if (!L.tfc_meta.empty()) {
-            L.d_tfc = s.at<int4>(L.off_tfc);
-            L.H = s.ws + L.off_H;
-            HIPCHECK(upload(s, L.d_tfc, L.tfc_meta));
-        }
-    }
-    s.d_series = s.at<double>(s.off_series);
-    s.d_counter = s.at<int64_t>(s.off_counter);
-    s.d_flags = s.at<int>(s.off_flags);
-    s.d_partial = s.at<double>(s.off_partial);
-    s.d_bal = s.at<double>(s.off_bal);
-    s.eng.reset(make_engine(s.D, s.EQ, s.P));
-    s.eng->fill_nan(s);
-    hipLaunchKernelGGL((k_fill<int64_t>), dim3(1), dim3(64), 0, s.stream, s.d_counter, (int64_t)1, (int64_t)0);
-    hipLaunchKernelGGL((k_fill<int>), dim3(1), dim3(64), 0, s.stream, s.d_flags, (int64_t)2, 0);
-    HIPCHECK(hipGetLastError());
+    dclbm_status st = sim_attach(s, d_workspace, bytes, (hipStream_t)stream);
+    if (st != DCLBM_OK) return st;
     HIPCHECK(hipStreamSynchronize(s.stream));
     *out = h.release();
     return DCLBM_OK;

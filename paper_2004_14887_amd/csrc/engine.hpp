@@ -1,0 +1,176 @@
+// Host-side state of one simulation and the type-erased engine that launches
+// its kernels; shared by the single-simulation C ABI and the serving runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/dclbm.h"
+#include "kernels.hpp"
+
+namespace dclbm {
+
+extern thread_local std::string g_err;
+dclbm_status fail(dclbm_status s, const char* fmt, ...);
+
+#define HIPCHECK(expr)                                                                         \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(DCLBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+struct HostLevel {
+    int nx = 1, ny = 1, nz = 1, nxb = 1;
+    int64_t elems = 0;          // storage elements per buffer (Q per node slot, 64-node row blocks)
+    int periodic = 0, boundary = 0, has_child = 0;
+    int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
+    int plo[3] = {0, 0, 0};
+    double tau = 0.0;
+    int64_t n_active = 0;
+    // interface with the parent (level >= 1)
+    std::vector<int4> tf_meta, ie_meta;   // co-located (x,y,z,Gamma=R mask), hanging (x,y,z,missing mask)
+    std::vector<int> tfmap;               // co-located index at fine coords (2a,2b,2c), -1 elsewhere
+    int mx = 1, my = 1, mz = 1;
+    std::vector<int4> seg_info;           // (tf_off, tf_cnt, ie_off, ie_cnt)
+    std::vector<int> seg_tf, seg_ie, seg_sten;
+    // interface with the child (coarse co-located nodes, child's order)
+    std::vector<int4> tfc_meta;
+    // workspace offsets
+    int64_t off_f[2] = {0, 0}, off_tf = 0, off_ie = 0, off_X = 0, off_tfc = 0, off_H = 0, off_seg_info = 0,
+            off_seg_tf = 0, off_seg_ie = 0, off_seg_sten = 0;
+    // device pointers
+    void* f[2] = {nullptr, nullptr};
+    int4 *d_tf = nullptr, *d_ie = nullptr, *d_tfc = nullptr, *d_seg_info = nullptr;
+    int *d_seg_tf = nullptr, *d_seg_ie = nullptr, *d_seg_sten = nullptr;
+    void *X = nullptr, *H = nullptr;
+    int parity = 0;
+    int64_t captures = 0;
+
+    LevelDev dev() const
+    {
+        LevelDev g;
+        g.nx = nx;
+        g.ny = ny;
+        g.nz = nz;
+        g.nxb = nxb;
+        g.periodic = periodic;
+        g.boundary = boundary;
+        g.has_child = has_child;
+        for (int a = 0; a < 3; ++a) {
+            g.clo[a] = clo[a];
+            g.chi[a] = chi[a];
+        }
+        return g;
+    }
+    int64_t n_dense() const { return (int64_t)nx * ny * nz; }
+    TileMap tiles() const
+    {
+        TileMap m;
+        m.tx = (nx + 63) / 64;
+        m.ty = (ny + 3) / 4;
+        m.nrows = m.ty * nz;
+        m.per = m.tx * ((m.nrows + 7) / 8);
+        return m;
+    }
+    int64_t elem0(int Q, int x, int y, int z) const
+    {
+        return (((int64_t)z * ny + y) * nxb + (x >> 6)) * (Q * 64) + (x & 63);
+    }
+};
+
+struct Sim;
+
+// Type-erased launcher set for one (lattice, equilibrium order, storage form).
+struct Engine {
+    virtual ~Engine() {}
+    virtual void level_step(Sim& s, int l, int substep, int first) = 0;
+    virtual void probe(Sim& s) = 0;
+    virtual void init(Sim& s, int l, const double* rho, const double* u) = 0;
+    virtual void ring_init(Sim& s, int l) = 0;
+    virtual void fill_nan(Sim& s) = 0;
+    virtual void read(Sim& s, int l, double* f, double* rho, double* u) = 0;
+    virtual void read_shared(Sim& s, int l, double* out) = 0;
+    virtual void balance(Sim& s, int l, double* partial, int nblocks) = 0;
+    // serving: one phase of the resident simulations, and the step tail
+    virtual void launch_multi(hipStream_t st, const MultiArgs& m, unsigned grid) = 0;
+    virtual void launch_tail(hipStream_t st, const MultiArgs& m, unsigned grid) = 0;
+    virtual int multi_blocks_per_cu() = 0;   // resident workgroups of the phase kernel per CU
+};
+
+struct ProbeLoc {
+    int level;
+    int64_t off;
+};
+
+struct Sim {
+    dclbm_config cfg;
+    int D = 2, Q = 9, P = 0, EQ = 2;
+    size_t tsize = 8, rsize = 8;   // storage and arithmetic element sizes
+    std::vector<HostLevel> lv;
+    std::vector<ProbeLoc> probes;
+    std::vector<int32_t> probe_xyz;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0, need_bytes = 0;
+    int64_t off_series = 0, off_counter = 0, off_flags = 0, off_partial = 0, off_bal = 0;
+    double* d_series = nullptr;
+    int64_t* d_counter = nullptr;
+    int* d_flags = nullptr;
+    double* d_partial = nullptr;
+    double* d_bal = nullptr;
+    int partial_blocks = 1024;
+    std::unique_ptr<Engine> eng;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    int64_t steps_done = 0;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[DCLBM_MAX_LEVELS];
+    double tms[DCLBM_MAX_LEVELS] = {0, 0, 0, 0};
+    int64_t tlaunch[DCLBM_MAX_LEVELS] = {0, 0, 0, 0};
+    double newton_tol = 1e-12;
+    int newton_maxit = 20;
+
+    template <typename T>
+    T* at(int64_t off) const
+    {
+        return reinterpret_cast<T*>(ws + off);
+    }
+};
+
+template <typename V>
+inline hipError_t upload(Sim& s, void* dst, const std::vector<V>& v)
+{
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(dst, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, s.stream);
+}
+
+
+// Geometry, classification, interface tables and workspace layout of a
+// configuration (host only, no device calls).
+dclbm_status build_geometry(Sim& s);
+// Point the simulation at its workspace, upload its tables, create its
+// engine, fill the state with NaN and clear its counters; enqueued on the
+// stream, no synchronisation.
+dclbm_status sim_attach(Sim& s, void* d_workspace, size_t bytes, hipStream_t stream);
+// Arguments of one level substep from the current host state, and its grid.
+LevelArgs level_args(const Sim& s, int l, int substep, int first, unsigned* grid);
+// Probe arguments for the current host state (after a coarse step).
+ProbeArgs probe_args(const Sim& s);
+// The level substeps of one coarse step in launch order (level, substep,
+// arguments, grid) from the current host state, and the probe arguments of
+// the state after it.  Advances the host state like a launched step.
+struct StepRecord {
+    int level, substep;
+    LevelArgs args;
+    unsigned grid;
+};
+void record_coarse_step(Sim& s, std::vector<StepRecord>& out, ProbeArgs& probe_after);
+Engine* make_engine(int D, int EQ, int P);
+
+}  // namespace dclbm

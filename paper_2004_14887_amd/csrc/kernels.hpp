@@ -418,17 +418,15 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
     for (int i = 0; i < Q; ++i) F::store(d + i * 64, s[i]);
 }
 
-// Grid order: the capture workgroups first, then segment workgroups in
-// groups of 8 (one per XCD) every seg_period workgroups, bulk tiles in
-// between.  Segment work is latency-bound (Newton, gathers), bulk work is
-// bandwidth-bound, so spreading the segments over the launch overlaps the
-// two; groups of 8 keep bulk workgroup b' on XCD b' % 8 as TileMap assumes.
+// Workgroup b of a level substep.  Grid order: the capture workgroups, then
+// the interface-segment workgroups in groups of 8 (one per XCD) every
+// seg_period workgroups, bulk tiles in between (seg_period = 8 puts every
+// segment before the first bulk tile).  Groups of 8 keep bulk workgroup b'
+// on XCD b' % 8 as TileMap assumes.  Every thread of the workgroup calls
+// this with the same arguments (the segment role synchronises).
 template <int DIM, int EQ, int P>
-__global__ __launch_bounds__(kBlock) void k_level(LevelArgs a)
+__device__ __forceinline__ void level_block(const LevelArgs& a, int b, typename Form<P>::R* lds)
 {
-    using R = typename Form<P>::R;
-    __shared__ R lds[Lat<DIM>::Q * SegLimits<DIM>::TF];
-    const int b = blockIdx.x;
     if (b < a.nb_cap) {
         role_capture<DIM, P>(a, b);
         return;
@@ -442,6 +440,14 @@ __global__ __launch_bounds__(kBlock) void k_level(LevelArgs a)
     }
     const int before = 8 * (j < a.seg_groups ? j + 1 : a.seg_groups);
     role_bulk<DIM, EQ, P>(a, b2 - before);
+}
+
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(kBlock) void k_level(LevelArgs a)
+{
+    using R = typename Form<P>::R;
+    __shared__ R lds[Lat<DIM>::Q * SegLimits<DIM>::TF];
+    level_block<DIM, EQ, P>(a, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------- history ring init
@@ -538,7 +544,7 @@ __global__ __launch_bounds__(128) void k_read_shared(const int4* __restrict__ me
     for (int a = 1; a < 4; ++a) out[(int64_t)a * n + d] = (double)X[(int64_t)a * ntf + t];
 }
 
-__global__ void k_fill_nan_f64(double* p, int64_t n)
+static __global__ void k_fill_nan_f64(double* p, int64_t n)
 {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
         p[k] = __builtin_nan("");
@@ -553,7 +559,7 @@ __global__ void k_fill(T* p, int64_t n, T v)
 
 // Plain 16-byte copy: the bandwidth and HBM-counter reference for the
 // population kernels (read n*16 bytes, write n*16 bytes).
-__global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n)
+static __global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n)
 {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
         dst[k] = src[k];
@@ -567,10 +573,10 @@ struct ProbeArgs {
     int64_t off[32];       // element offset of direction 0 of that node (directions 64 apart)
 };
 
-// One workgroup; p' = (rho - 1)/3 in FP64 after each coarse step.
+// p' = (rho - 1)/3 in FP64 of every probe (thread p), appended to the series
+// at row *counter; thread 0 then advances the counter.  One workgroup.
 template <int DIM, int P>
-__global__ __launch_bounds__(64) void k_probe(ProbeArgs a, double* __restrict__ series,
-                                              int64_t* __restrict__ counter)
+__device__ __forceinline__ void probe_sample(const ProbeArgs& a, double* series, int64_t* counter)
 {
     using F = Form<P>;
     constexpr int Q = Lat<DIM>::Q;
@@ -584,6 +590,86 @@ __global__ __launch_bounds__(64) void k_probe(ProbeArgs a, double* __restrict__ 
     }
     __syncthreads();
     if (threadIdx.x == 0) *counter = step + 1;
+}
+
+template <int DIM, int P>
+__global__ __launch_bounds__(64) void k_probe(ProbeArgs a, double* __restrict__ series,
+                                              int64_t* __restrict__ counter)
+{
+    probe_sample<DIM, P>(a, series, counter);
+}
+
+// ---------------------------------------------------------------- serving
+// Many simulations of one (lattice, order, storage) class advance together:
+// every level substep of the deepest admitted mesh is one "phase" (the
+// depth-first order of the sub-cycling recursion, in which the substeps of a
+// shallower mesh keep their own order), and one persistent launch per phase
+// runs the workgroups of every resident simulation that has that substep.
+struct SlotDev {
+    int64_t step;              // coarse steps done (advanced by k_server_tail)
+    int64_t target;            // coarse steps requested
+    const LevelArgs* args;     // [3][n_phases]: first step, then steady steps of level-0 parity 0 and 1
+    const ProbeArgs* probe;    // [2]: after a step from level-0 parity 0 and 1
+    double* series;
+    int64_t* counter;
+};
+
+// Phase table p at ptab + p * (3 + 2 M): n, total, slot[M], begin[M + 1]
+// (begin[k] = first virtual workgroup of item k, multiples of 8; begin[n] =
+// total).  The tail list follows the last phase: n, slot[M].
+struct MultiArgs {
+    const SlotDev* slots;
+    const int* ptab;
+    int M;          // slot capacity
+    int n_phases;
+    int phase;
+};
+
+// Persistent: workgroup w takes virtual workgroups w, w + G, ... (G a
+// multiple of 8 keeps the XCD of a virtual workgroup as in a plain launch).
+// A finished simulation's workgroups do nothing, so a lagging table is safe.
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(kBlock) void k_level_multi(MultiArgs m)
+{
+    using R = typename Form<P>::R;
+    __shared__ R lds[Lat<DIM>::Q * SegLimits<DIM>::TF];
+    const int* pt = m.ptab + (int64_t)m.phase * (3 + 2 * m.M);
+    const int n = pt[0], total = pt[1];
+    const int* slot = pt + 2;
+    const int* begin = pt + 2 + m.M;
+    for (int v = blockIdx.x; v < total; v += gridDim.x) {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (begin[mid] <= v) lo = mid;
+            else hi = mid - 1;
+        }
+        const SlotDev& sd = m.slots[slot[lo]];
+        const int64_t step = sd.step;
+        if (step < sd.target) {
+            const int var = step == 0 ? 0 : 1 + (int)(step & 1);
+            level_block<DIM, EQ, P>(sd.args[var * m.n_phases + m.phase], v - begin[lo], lds);
+        }
+        __syncthreads();
+    }
+}
+
+// After the phases of a coarse step: probes of every resident simulation
+// that is still running, then its step count.  64 threads per workgroup.
+template <int DIM, int P>
+__global__ __launch_bounds__(64) void k_server_tail(MultiArgs m)
+{
+    const int* pt = m.ptab + (int64_t)m.n_phases * (3 + 2 * m.M);
+    const int n = pt[0];
+    for (int k = blockIdx.x; k < n; k += gridDim.x) {
+        SlotDev* sd = const_cast<SlotDev*>(m.slots) + pt[1 + k];
+        const int64_t step = sd->step;
+        if (step < sd->target) {
+            probe_sample<DIM, P>(sd->probe[step & 1], sd->series, sd->counter);
+            if (threadIdx.x == 0) sd->step = step + 1;
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------- balances
@@ -646,7 +732,7 @@ __global__ __launch_bounds__(256) void k_balance(LevelDev g, const typename Form
     }
 }
 
-__global__ __launch_bounds__(64) void k_balance_final(const double* __restrict__ partial, int nblocks,
+static __global__ __launch_bounds__(64) void k_balance_final(const double* __restrict__ partial, int nblocks,
                                                       double* __restrict__ out)
 {
     for (int k = 0; k < 5; ++k) {

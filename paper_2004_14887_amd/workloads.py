@@ -256,3 +256,51 @@ def uniform_state(lattice: str, n0, boxes, rho0: float = 1.0, u0=(0.0, 0.0, 0.0)
     """A uniform state (rest or uniform flow) on any mesh."""
     return Workload(name="uniform", lattice=lattice, n0=tuple(n0), boxes=list(boxes), tau0=tau0,
                     steps=steps, coupling=coupling, background=tuple(u0), pulses=[])
+
+
+def serving_requests(seed: int = 4, n: int = 256, max_levels: int = 3, min_side: int = 64, max_side: int = 1024,
+                     min_steps: int = 100, max_steps: int = 2000, n_probes: int = 4):
+    """A stream of D2Q9 requests for the serving loop, and their unit-rate
+    Poisson inter-arrival gaps (scale by 1 / rate).
+
+    Per request: periodic side S = 2^U(log2 min_side, log2 max_side), a
+    multiple of 16; 1..max_levels levels, each refined box U(0.25, 0.5) of its
+    parent's extent per axis, placed uniformly at least 4 parent cells from
+    the parent's boundary; a background flow of Mach U(0.05, 0.2) in a random
+    direction; tau0 ~ U(0.51, 0.6); U_int[min_steps, max_steps] coarse steps;
+    one barotropic vortex (strength 0.1 U0, radius max(4, S/16)) and one
+    Gaussian pulse (1e-3, half-width 6) at uniform positions; n_probes probes
+    at uniform level-0 nodes."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(n):
+        S = int(round(2.0 ** rng.uniform(math.log2(min_side), math.log2(max_side)) / 16.0)) * 16
+        S = max(S, min_side)
+        L = int(rng.integers(1, max_levels + 1))
+        boxes = []
+        ext = (S, S)
+        for _ in range(1, L):
+            lo, hi = [], []
+            for a in range(2):
+                side = max(3, int(round(rng.uniform(0.25, 0.5) * ext[a])))
+                side = min(side, ext[a] - 8)
+                s0 = int(rng.integers(4, ext[a] - 4 - side + 1))
+                lo.append(s0)
+                hi.append(s0 + side)
+            boxes.append((tuple(lo), tuple(hi)))
+            ext = (2 * (hi[0] - lo[0]), 2 * (hi[1] - lo[1]))
+        mach = float(rng.uniform(0.05, 0.2))
+        ang = float(rng.uniform(0.0, 2.0 * math.pi))
+        U0 = mach * CS
+        bg = (U0 * math.cos(ang), U0 * math.sin(ang), 0.0)
+        tau0 = float(rng.uniform(0.51, 0.6))
+        steps = int(rng.integers(min_steps, max_steps + 1))
+        vc = rng.uniform(0, S, size=2)
+        pc = rng.uniform(0, S, size=2)
+        vort = [dict(xc=float(vc[0]), yc=float(vc[1]), eps=0.1 * U0, Rc=max(4.0, S / 16.0))]
+        pulses = [dict(c=(float(pc[0]), float(pc[1]), 0.0), A=1e-3, Rc=6.0)]
+        probes = [tuple(int(v) for v in rng.integers(0, S, size=2)) for _ in range(n_probes)]
+        reqs.append(Workload(name=f"request_{k}_S{S}_L{L}", lattice="D2Q9", n0=(S, S), boxes=boxes, tau0=tau0,
+                             steps=steps, probes=probes, background=bg, vortices=vort, pulses=pulses, seed=seed))
+    gaps = rng.exponential(1.0, size=n)
+    return reqs, gaps

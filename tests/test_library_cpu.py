@@ -80,3 +80,29 @@ def test_product_path_does_not_touch_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
                 assert "dclbm_oracle" not in text and "liboracle" not in text, f
+
+
+def test_server_workspace_bytes_and_validation():
+    lib = _lib()
+    import ctypes as C
+
+    from paper_2004_14887_amd import _lib as L
+    from paper_2004_14887_amd.server import server_config
+
+    def total(arena, **kw):
+        out = C.c_size_t()
+        st = lib.dclbm_server_workspace_bytes(C.byref(server_config(**kw)), arena, C.byref(out))
+        return st, out.value
+
+    st, t0 = total(0)
+    assert st == 0 and t0 > 0
+    st, t1 = total(1 << 30)
+    assert st == 0 and t1 - t0 == 1 << 30
+    # tables grow with slots and with the phases of deeper meshes (2^L - 1 per step)
+    assert total(0, max_slots=128)[1] > t0
+    assert total(0, max_levels=4)[1] > total(0, max_levels=2)[1]
+    for bad in (dict(max_slots=0), dict(max_levels=5), dict(steps_per_tick=0), dict(grid=12),
+                dict(max_probes=33), dict(max_probe_steps=0)):
+        st, _ = total(0, **bad)
+        assert st == -1, bad
+    assert L.REQ_STATE[2] == "done"
