@@ -45,6 +45,13 @@ def parse():
     ap.add_argument("--workload", default="pulse_vortices_3level", choices=["pulse_vortices_3level", "pulse_ring_3d"],
                     help="3-level 2048^2 D2Q9 (default) or 2-level 256^3 D3Q19")
     ap.add_argument("--copy-only", action="store_true", help="only run the plain copy kernel (counter calibration)")
+    ap.add_argument("--serving-requests", type=int, default=256, help="requests in the serving run (0: skip it)")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving run")
+    ap.add_argument("--serving-slots", type=int, default=128)
+    ap.add_argument("--serving-steps-per-tick", type=int, default=4)
+    ap.add_argument("--serving-loads", default="0.5,0.9", help="offered loads of the open-loop runs ('' for none)")
+    ap.add_argument("--serving-grid", type=int, default=0, help="workgroups of the persistent launches (0: resident)")
+    ap.add_argument("--serving-steady-only", action="store_true", help="only the steady-state part of the serving run")
     return ap.parse_args()
 
 
@@ -135,6 +142,143 @@ def roofline(form, Q, workload):
             "avg_launch_ms": round(avg_ms, 5), "per_level": per_level}
 
 
+def serving_run(n_requests, slots, steps_per_tick, loads=(0.5, 0.9), seed=4, grid=0, steady_only=False):
+    """Continuous batching of a seeded Poisson stream of D2Q9 FP32 requests
+    (side 64-1024, 1-3 levels, 100-2000 steps) on one long-lived server.
+
+    * warm-up: the whole stream once, closed loop (fills the pinned pool);
+    * capacity: the stream again, every request queued at once (8 submitting
+      threads): aggregate MLUPS = updates / (last completion - first arrival);
+    * steady state: `slots` resident copies of one 3-level request, MLUPS
+      over 20 ticks, beside the same request stepped alone through the
+      single-simulation path;
+    * open loop at `loads` of the capacity: the seeded unit-rate gaps
+      rescaled; latency = completion - arrival (the library's clock)."""
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+
+    from paper_2004_14887_amd import workloads as W
+    from paper_2004_14887_amd.server import Server, request_fields
+    from paper_2004_14887_amd.sim import Simulation
+
+    reqs, gaps = W.serving_requests(seed=seed, n=n_requests)
+    log(f"serving: generating initial fields of {len(reqs)} requests")
+    with ThreadPoolExecutor(8) as ex:
+        fields = list(ex.map(request_fields, reqs))
+    max_nodes = max(r.n_nodes(l) for r in reqs for l in range(r.n_levels))
+    arena = 24 << 30
+    srv = Server(arena, precision="fp32", max_levels=3, max_slots=slots, steps_per_tick=steps_per_tick,
+                 max_probes=8, max_probe_steps=max(r.steps for r in reqs), max_level_nodes=max_nodes, grid=grid)
+
+    def one_run(arrivals, producers=1):
+        torch.cuda.synchronize()
+        ticks0 = srv.stats()["ticks"]
+        ids = [None] * len(reqs)
+        left = [producers]
+        lock = threading.Lock()
+
+        def producer(part):
+            t0 = time.perf_counter()
+            for k in part:
+                if arrivals is not None:
+                    dt = t0 + arrivals[k] - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                ids[k] = srv.submit(reqs[k], fields=fields[k])
+            with lock:
+                left[0] -= 1
+
+        ths = [threading.Thread(target=producer, args=(list(range(j, len(reqs), producers)),))
+               for j in range(producers)]
+        for th in ths:
+            th.start()
+        while True:
+            nr, nq = srv.tick()
+            if nr == 0 and nq == 0:
+                with lock:
+                    if left[0] == 0:
+                        break
+                time.sleep(5e-5)
+        for th in ths:
+            th.join()
+        nr, nq = srv.tick()
+        assert nr == 0 and nq == 0
+        infos = [srv.result(i)[1] if srv.poll(i) == "done" else srv.info(i) for i in ids]
+        for i in ids:
+            srv.release(i)
+        ok = [i for i in infos if i["state"] == 2]
+        lat = np.array([i["t_done"] - i["t_submit"] for i in ok])
+        qd = np.array([i["t_admit"] - i["t_submit"] for i in ok])
+        span = max(i["t_done"] for i in ok) - min(i["t_submit"] for i in infos)
+        ups = sum(i["updates"] for i in ok)
+        return {"mlups": round(ups / span / 1e6, 1), "makespan_s": round(span, 3),
+                "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+                "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+                "queue_p50_s": round(float(np.percentile(qd, 50)), 4),
+                "queue_p99_s": round(float(np.percentile(qd, 99)), 4),
+                "completed": len(ok), "failed": len(infos) - len(ok),
+                "ticks": srv.stats()["ticks"] - ticks0, "updates": int(ups)}
+
+    cap = None
+    if not steady_only:
+        log("serving: warm-up (closed loop)")
+        one_run(None, producers=8)
+        log("serving: closed loop (capacity)")
+        cap = one_run(None, producers=8)
+        log(f"serving: capacity {cap['mlups']} MLUPS over {cap['makespan_s']} s")
+
+    # steady state: `slots` resident copies of one 3-level request
+    tmpl = next(r for r in reqs if r.n_levels == 3 and 400 <= r.n0[0] <= 640)
+    ticks = 20
+    steps = steps_per_tick * (ticks + 4)
+    tf = request_fields(tmpl)
+    ids = [srv.submit(tmpl, steps=steps, fields=tf) for _ in range(slots)]
+    srv.tick()
+    srv.tick()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(ticks):
+        srv.tick()
+    srv.stream.synchronize()
+    dt = time.perf_counter() - t0
+    per_step = srv.info(ids[0])["updates"] // steps
+    srv.drain()
+    for i in ids:
+        srv.release(i)
+    sim = Simulation(tmpl, "fp32", probe_capacity=steps + 8)
+    sim.init_from_workload()
+    sim.step(4)
+    sim.synchronize()
+    t1 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    dt1 = time.perf_counter() - t1
+    sim.close()
+    steady = {"request": tmpl.name, "resident": slots, "updates_per_step_each": int(per_step),
+              "mlups": round(slots * per_step * steps_per_tick * ticks / dt / 1e6, 1),
+              "alone_single_simulation_mlups": round(per_step * steps / dt1 / 1e6, 1)}
+    log(f"serving: steady state {steady}")
+    if steady_only:
+        g = srv.stats()["grid"]
+        srv.close()
+        return {"steady_state": steady, "grid": g}
+
+    out = {"requests": len(reqs), "precision": "fp32", "slots": slots, "steps_per_tick": steps_per_tick,
+           "arena_gb": arena / 2 ** 30, "capacity": cap, "steady_state": steady, "loads": {}}
+    mean_updates = cap["updates"] / max(1, cap["completed"])
+    for load in loads:
+        rate = load * cap["mlups"] * 1e6 / mean_updates      # requests per second
+        arrivals = np.cumsum(gaps) / rate
+        arrivals -= arrivals[0]
+        log(f"serving: open loop at load {load} ({rate:.1f} requests/s)")
+        out["loads"][str(load)] = one_run(arrivals)
+        log(f"serving: load {load}: {out['loads'][str(load)]}")
+    srv.close()
+    return out
+
+
 def cpu_baseline(wl_full, steps):
     """The FP64 oracle as it stands, single-threaded, on the first `steps`
     coarse steps of the same workload."""
@@ -176,6 +320,11 @@ def main():
     if args.copy_only:
         print(json.dumps({"copy_gbs": round(copy_gbs, 1), "copy_ms": copy_ms}))
         return
+    if args.serving_only:
+        print(json.dumps(serving_run(args.serving_requests, args.serving_slots, args.serving_steps_per_tick,
+                        tuple(float(x) for x in args.serving_loads.split(",") if x), grid=args.serving_grid,
+                        steady_only=args.serving_steady_only)))
+        return
     if args.workload == "pulse_ring_3d":
         n0 = args.n0 if args.n0 != 2048 else 256
         wl = W.pulse_ring_3d(seed=3, n0=n0, steps=args.steps)
@@ -207,6 +356,14 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cpu = cpu_baseline(mk(args.cpu_steps), args.cpu_steps)
+    serving = None
+    if args.serving_requests > 0:
+        try:
+            serving = serving_run(args.serving_requests, args.serving_slots, args.serving_steps_per_tick,
+                        tuple(float(x) for x in args.serving_loads.split(",") if x), grid=args.serving_grid,
+                        steady_only=args.serving_steady_only)
+        except Exception as e:   # reported, never hides the main line
+            serving = {"error": repr(e)}
     Q = wl.Q
     rl = roofline(main_form, Q, wl.name)
     bpv = bytes_per_value(args.precision)
@@ -234,6 +391,7 @@ def main():
         "latency_ms": {"p50": round(main_form["p50"], 5), "p99": round(main_form["p99"], 5)},
         "roofline": rl,
         "cpu_baseline": cpu,
+        "serving": serving,
         "forms": {p: {"mlups": round(f["mlups"], 1), "ms_per_step": round(f["wall_ms"] / f["steps"], 5),
                       "p50_ms": round(f["p50"], 5), "p99_ms": round(f["p99"], 5),
                       "speedup_vs_fp64": (round(f["mlups"] / forms["fp64"]["mlups"], 3) if "fp64" in forms else None),

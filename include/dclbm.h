@@ -179,8 +179,9 @@ typedef struct {
     int32_t max_probes;       /* probes per request, 0..32 */
     int64_t max_probe_steps;  /* largest step count of a request (its probe series is kept whole) */
     int64_t max_level_nodes;  /* dense nodes of the largest level of any request (staging of initial fields) */
-    int32_t grid;             /* workgroups of each persistent launch (multiple of 8); 0: all resident at once */
-    int32_t max_inflight;     /* ticks enqueued ahead of the GPU before a tick waits; 0: 2 */
+    int32_t grid;             /* workgroups of every phase launch (multiple of 8); 0: per tick, the smallest
+                               * power of two from 2048 to 262144 covering the largest phase */
+    int32_t max_inflight;     /* ticks enqueued ahead of the GPU before a tick waits (at most 6); 0: 2 */
 } dclbm_server_config;
 
 typedef struct {
@@ -198,7 +199,7 @@ typedef struct {
     int64_t ticks;            /* graph launches so far */
     int32_t running, queued;  /* resident (including finishing) and waiting requests */
     int64_t arena_bytes, arena_free, arena_largest_free;
-    int32_t grid;             /* workgroups of each persistent launch */
+    int32_t grid;             /* workgroups of the phase launches of the last tick */
     int32_t n_phases;         /* persistent launches per coarse step, before the probe launch */
 } dclbm_server_info;
 

@@ -205,12 +205,6 @@ struct EngineImpl final : Engine {
     {
         hipLaunchKernelGGL((k_server_tail<DIM, P>), dim3(grid), dim3(64), 0, st, m);
     }
-    int multi_blocks_per_cu() override
-    {
-        int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_level_multi<DIM, EQ, P>, kBlock, 0) != hipSuccess) return 0;
-        return n;
-    }
 };
 
 template <int DIM, int EQ>

@@ -100,7 +100,6 @@ struct Engine {
     // serving: one phase of the resident simulations, and the step tail
     virtual void launch_multi(hipStream_t st, const MultiArgs& m, unsigned grid) = 0;
     virtual void launch_tail(hipStream_t st, const MultiArgs& m, unsigned grid) = 0;
-    virtual int multi_blocks_per_cu() = 0;   // resident workgroups of the phase kernel per CU
 };
 
 struct ProbeLoc {

@@ -424,22 +424,27 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
 // segment before the first bulk tile).  Groups of 8 keep bulk workgroup b'
 // on XCD b' % 8 as TileMap assumes.  Every thread of the workgroup calls
 // this with the same arguments (the segment role synchronises).
+// Returns true when the workgroup used the LDS (segment role).
 template <int DIM, int EQ, int P>
-__device__ __forceinline__ void level_block(const LevelArgs& a, int b, typename Form<P>::R* lds)
+__device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename Form<P>::R* lds)
 {
     if (b < a.nb_cap) {
         role_capture<DIM, P>(a, b);
-        return;
+        return false;
     }
     const int b2 = b - a.nb_cap;
     const int j = b2 / a.seg_period, r = b2 - j * a.seg_period;
     if (j < a.seg_groups && r < 8) {
         const int sg = 8 * j + r;
-        if (sg < a.nb_seg) role_segment<DIM, EQ, P>(a, sg, lds);
-        return;
+        if (sg < a.nb_seg) {
+            role_segment<DIM, EQ, P>(a, sg, lds);
+            return true;
+        }
+        return false;
     }
     const int before = 8 * (j < a.seg_groups ? j + 1 : a.seg_groups);
     role_bulk<DIM, EQ, P>(a, b2 - before);
+    return false;
 }
 
 template <int DIM, int EQ, int P>
@@ -628,15 +633,36 @@ struct MultiArgs {
 // Persistent: workgroup w takes virtual workgroups w, w + G, ... (G a
 // multiple of 8 keeps the XCD of a virtual workgroup as in a plain launch).
 // A finished simulation's workgroups do nothing, so a lagging table is safe.
+// The tables are read-only while a phase runs: reading them through the
+// constant address space lets the compiler keep them in scalar loads (a
+// generic pointer inside the loop would be reloaded per lane after every
+// store of the previous iteration).
+template <class T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <class T>
+__device__ __forceinline__ T load_const(const T* p)
+{
+    static_assert(sizeof(T) % 4 == 0, "dword copy");
+    constexpr int N = sizeof(T) / 4;
+    const cptr<uint32_t> w = (cptr<uint32_t>)p;
+    T out;
+    uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+    for (int i = 0; i < N; ++i) o[i] = w[i];
+    return out;
+}
+
 template <int DIM, int EQ, int P>
 __global__ __launch_bounds__(kBlock) void k_level_multi(MultiArgs m)
 {
     using R = typename Form<P>::R;
     __shared__ R lds[Lat<DIM>::Q * SegLimits<DIM>::TF];
-    const int* pt = m.ptab + (int64_t)m.phase * (3 + 2 * m.M);
+    const cptr<int> pt = (cptr<int>)(m.ptab + (int64_t)m.phase * (3 + 2 * m.M));
     const int n = pt[0], total = pt[1];
-    const int* slot = pt + 2;
-    const int* begin = pt + 2 + m.M;
+    const cptr<int> slot = pt + 2;
+    const cptr<int> begin = pt + 2 + m.M;
+    const cptr<SlotDev> slots = (cptr<SlotDev>)m.slots;
     for (int v = blockIdx.x; v < total; v += gridDim.x) {
         int lo = 0, hi = n - 1;
         while (lo < hi) {
@@ -644,13 +670,16 @@ __global__ __launch_bounds__(kBlock) void k_level_multi(MultiArgs m)
             if (begin[mid] <= v) lo = mid;
             else hi = mid - 1;
         }
-        const SlotDev& sd = m.slots[slot[lo]];
-        const int64_t step = sd.step;
-        if (step < sd.target) {
+        const cptr<SlotDev> sd = slots + slot[lo];
+        const int64_t step = sd->step;
+        if (step < sd->target) {
             const int var = step == 0 ? 0 : 1 + (int)(step & 1);
-            level_block<DIM, EQ, P>(sd.args[var * m.n_phases + m.phase], v - begin[lo], lds);
+            const LevelArgs a = load_const(sd->args + var * m.n_phases + m.phase);
+            // only a segment iteration leaves LDS behind; a barrier after
+            // every iteration would also wait for each tile's stores.  Every
+            // wave runs the same iterations, so the barriers still pair up.
+            if (level_block<DIM, EQ, P>(a, v - begin[lo], lds)) __syncthreads();
         }
-        __syncthreads();
     }
 }
 

@@ -84,11 +84,56 @@ struct Arena {
     }
 };
 
+// Page-locked host buffers in power-of-two size classes, reused, freed with
+// the server.  Initial fields wait in them between submission and admission,
+// so that their upload is a true asynchronous copy.
+struct PinnedPool {
+    std::mutex mu;
+    std::map<size_t, std::vector<void*>> free_;
+    std::vector<void*> all;
+    static size_t cls(size_t n)
+    {
+        size_t c = 1 << 16;
+        while (c < n) c <<= 1;
+        return c;
+    }
+    void* get(size_t n)
+    {
+        const size_t c = cls(n);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto& v = free_[c];
+            if (!v.empty()) {
+                void* p = v.back();
+                v.pop_back();
+                return p;
+            }
+        }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) return nullptr;
+        std::lock_guard<std::mutex> lk(mu);
+        all.push_back(p);
+        return p;
+    }
+    void put(void* p, size_t n)
+    {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu);
+        free_[cls(n)].push_back(p);
+    }
+    ~PinnedPool()
+    {
+        for (void* p : all) (void)hipHostFree(p);
+    }
+};
+
 struct Request {
     uint64_t id = 0;
     int64_t steps = 0;
     std::unique_ptr<Sim> sim;
-    std::vector<std::vector<double>> rho, u;   // per level, dense FP64 (host)
+    double* fields = nullptr;                  // pinned: per level rho [n] then u [D][n]
+    size_t fields_bytes = 0;
+    std::vector<size_t> field_off;             // per level, in doubles
     size_t bytes = 0, off = 0;
     int state = DCLBM_REQ_QUEUED;
     int slot = -1;
@@ -128,14 +173,23 @@ struct Server {
     SlotDev* h_slots = nullptr;
     LevelArgs* h_args = nullptr;
     ProbeArgs* h_probe = nullptr;
-    int* h_ptab[2] = {nullptr, nullptr};
-    hipEvent_t ptab_ev[2] = {nullptr, nullptr};
+    static constexpr int kTabs = 8;  // table upload buffers in rotation (more than ticks in flight)
+    int* h_ptab[kTabs] = {};
+    hipEvent_t ptab_ev[kTabs] = {};
     int ptab_cur = 0;
     char* h_res = nullptr;
     std::unique_ptr<Engine> eng;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    std::mutex mu;
+    // one tick graph per grid size (powers of two); a tick replays the
+    // smallest one covering the largest phase: a workgroup per tile measured
+    // faster than fewer workgroups looping over the tiles
+    std::vector<int> gsize;
+    std::vector<hipGraph_t> graph;
+    std::vector<hipGraphExec_t> gexec;
+    int need = 0;         // largest phase of the current tables, in workgroups
+    int last_grid = 0;
+    std::mutex tick_mu;   // one tick at a time; the throttle waits under it only
+    std::mutex mu;        // requests, queue, slots: held only for non-blocking work
+    PinnedPool pinned;
     std::map<uint64_t, std::unique_ptr<Request>> reqs;
     std::deque<uint64_t> queue;
     std::vector<uint64_t> slot_req;
@@ -221,7 +275,9 @@ Layout layout(const dclbm_server_config& c, size_t bytes)
 dclbm_status upload_tables(Server& sv)
 {
     const int cur = sv.ptab_cur;
-    HIPCHECK(hipEventSynchronize(sv.ptab_ev[cur]));   // the copy from this buffer two uploads ago
+    // the copy from this buffer was enqueued kTabs uploads (so at least as
+    // many ticks) ago, beyond the ticks allowed in flight: already complete
+    HIPCHECK(hipEventSynchronize(sv.ptab_ev[cur]));
     int* t = sv.h_ptab[cur];
     const int M = sv.M, stride = 3 + 2 * M;
     std::vector<int> live;
@@ -253,7 +309,10 @@ dclbm_status upload_tables(Server& sv)
     for (size_t i = 0; i < live.size(); ++i) tl[1 + i] = live[i];
     HIPCHECK(hipMemcpyAsync(sv.d_ptab, t, sv.ptab_ints * sizeof(int), hipMemcpyHostToDevice, sv.stream));
     HIPCHECK(hipEventRecord(sv.ptab_ev[cur], sv.stream));
-    sv.ptab_cur ^= 1;
+    sv.ptab_cur = (cur + 1) % Server::kTabs;
+    int need = 0;
+    for (int p = 0; p < sv.NPH; ++p) need = std::max(need, t[(size_t)p * stride + 1]);
+    sv.need = need;
     sv.dirty = false;
     return DCLBM_OK;
 }
@@ -274,8 +333,7 @@ dclbm_status admit(Server& sv, Request& r, int k, size_t off)
     if (st != DCLBM_OK) return st;
     for (size_t l = 0; l < s.lv.size(); ++l) {
         const size_t n = (size_t)s.lv[l].n_dense();
-        HIPCHECK(hipMemcpyAsync(sv.d_stage, r.rho[l].data(), n * sizeof(double), hipMemcpyHostToDevice, sv.stream));
-        HIPCHECK(hipMemcpyAsync(sv.d_stage + n, r.u[l].data(), (size_t)s.D * n * sizeof(double),
+        HIPCHECK(hipMemcpyAsync(sv.d_stage, r.fields + r.field_off[l], (size_t)(1 + s.D) * n * sizeof(double),
                                 hipMemcpyHostToDevice, sv.stream));
         s.eng->init(s, (int)l, sv.d_stage, sv.d_stage + n);
         if (s.lv[l].has_child) s.eng->ring_init(s, (int)l);
@@ -344,8 +402,8 @@ dclbm_status retire(Server& sv)
         sv.pool.push_back(r.done);
         r.done = nullptr;
         r.sim.reset();
-        r.rho.clear();
-        r.u.clear();
+        sv.pinned.put(r.fields, r.fields_bytes);
+        r.fields = nullptr;
     }
     return DCLBM_OK;
 }
@@ -391,7 +449,10 @@ dclbm_status tick_locked(Server& sv)
     for (int k = 0; k < sv.M && !any; ++k)
         if (sv.slot_req[k] && !sv.reqs[sv.slot_req[k]]->finishing) any = true;
     if (!any) return DCLBM_OK;
-    HIPCHECK(hipGraphLaunch(sv.gexec, sv.stream));
+    size_t gi = 0;
+    while (gi + 1 < sv.gexec.size() && sv.gsize[gi] < sv.need) ++gi;
+    HIPCHECK(hipGraphLaunch(sv.gexec[gi], sv.stream));
+    sv.last_grid = sv.gsize[gi];
     ++sv.ticks;
     for (int k = 0; k < sv.M; ++k) {
         const uint64_t id = sv.slot_req[k];
@@ -418,11 +479,6 @@ dclbm_status tick_locked(Server& sv)
     if (!e) return fail(DCLBM_ERR_HIP, "hipEventCreate failed");
     HIPCHECK(hipEventRecord(e, sv.stream));
     sv.inflight.push_back(e);
-    while ((int)sv.inflight.size() > sv.depth) {
-        HIPCHECK(hipEventSynchronize(sv.inflight.front()));
-        sv.pool.push_back(sv.inflight.front());
-        sv.inflight.pop_front();
-    }
     return DCLBM_OK;
 }
 
@@ -477,7 +533,7 @@ dclbm_status dclbm_server_create(const dclbm_server_config* cfg, void* d_workspa
     dfs_phases(0, 0, cfg->max_levels, sv.phases);
     sv.NPH = (int)sv.phases.size();
     sv.K = cfg->steps_per_tick;
-    sv.depth = cfg->max_inflight > 0 ? cfg->max_inflight : 2;
+    sv.depth = cfg->max_inflight > 0 ? std::min(cfg->max_inflight, Server::kTabs - 2) : 2;
     sv.D = cfg->lattice == DCLBM_D2Q9 ? 2 : 3;
     sv.Q = cfg->lattice == DCLBM_D2Q9 ? 9 : 19;
     sv.d_slots = (SlotDev*)(sv.ws + L.slots);
@@ -491,17 +547,19 @@ dclbm_status dclbm_server_create(const dclbm_server_config* cfg, void* d_workspa
     sv.res_stride = (size_t)round_up((int64_t)((size_t)cfg->max_probe_steps * std::max(1, cfg->max_probes) * sizeof(double) + 64), 256);
     sv.slot_req.assign(sv.M, 0);
     sv.eng.reset(make_engine(sv.D, cfg->eq_order, cfg->precision));
-    // persistent grids: every workgroup resident at once
-    int dev = 0, cus = 0, per_cu = 0;
-    HIPCHECK(hipGetDevice(&dev));
-    HIPCHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    per_cu = sv.eng->multi_blocks_per_cu();
-    sv.G = cfg->grid > 0 ? cfg->grid : std::max(8, (cus * std::max(1, per_cu)) / 8 * 8);
+    // grids of the phase launches: a configured size, else powers of two
+    // from 2048 to 262144 workgroups (beyond that a launch loops)
+    if (cfg->grid > 0) {
+        sv.gsize.push_back(cfg->grid);
+    } else {
+        for (int g = 2048; g <= (1 << 18); g *= 2) sv.gsize.push_back(g);
+    }
+    sv.G = sv.gsize.back();
     sv.Gt = std::min(sv.M, 256);
     HIPCHECK(hipHostMalloc((void**)&sv.h_slots, sizeof(SlotDev) * sv.M, hipHostMallocDefault));
     HIPCHECK(hipHostMalloc((void**)&sv.h_args, sizeof(LevelArgs) * sv.M * 3 * sv.NPH, hipHostMallocDefault));
     HIPCHECK(hipHostMalloc((void**)&sv.h_probe, sizeof(ProbeArgs) * sv.M * 2, hipHostMallocDefault));
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < Server::kTabs; ++b) {
         HIPCHECK(hipHostMalloc((void**)&sv.h_ptab[b], sv.ptab_ints * sizeof(int), hipHostMallocDefault));
         memset(sv.h_ptab[b], 0, sv.ptab_ints * sizeof(int));
         HIPCHECK(hipEventCreateWithFlags(&sv.ptab_ev[b], hipEventDisableTiming));
@@ -513,20 +571,24 @@ dclbm_status dclbm_server_create(const dclbm_server_config* cfg, void* d_workspa
     HIPCHECK(hipMemcpyAsync(sv.d_ptab, sv.h_ptab[0], sv.ptab_ints * sizeof(int), hipMemcpyHostToDevice, sv.stream));
     HIPCHECK(hipMemcpyAsync(sv.d_slots, sv.h_slots, sizeof(SlotDev) * sv.M, hipMemcpyHostToDevice, sv.stream));
     HIPCHECK(hipStreamSynchronize(sv.stream));
-    HIPCHECK(hipStreamBeginCapture(sv.stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < sv.K; ++k) {
-        for (int p = 0; p < sv.NPH; ++p) {
-            MultiArgs m{sv.d_slots, sv.d_ptab, sv.M, sv.NPH, p};
-            sv.eng->launch_multi(sv.stream, m, (unsigned)sv.G);
+    for (int G : sv.gsize) {
+        HIPCHECK(hipStreamBeginCapture(sv.stream, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < sv.K; ++k) {
+            for (int p = 0; p < sv.NPH; ++p) {
+                MultiArgs m{sv.d_slots, sv.d_ptab, sv.M, sv.NPH, p};
+                sv.eng->launch_multi(sv.stream, m, (unsigned)G);
+            }
+            MultiArgs m{sv.d_slots, sv.d_ptab, sv.M, sv.NPH, sv.NPH};
+            sv.eng->launch_tail(sv.stream, m, (unsigned)sv.Gt);
         }
-        MultiArgs m{sv.d_slots, sv.d_ptab, sv.M, sv.NPH, sv.NPH};
-        sv.eng->launch_tail(sv.stream, m, (unsigned)sv.Gt);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(sv.stream, &g);
+        if (ce != hipSuccess) return fail(DCLBM_ERR_HIP, "graph capture: %s", hipGetErrorString(ce));
+        sv.graph.push_back(g);
+        hipGraphExec_t ge = nullptr;
+        HIPCHECK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        sv.gexec.push_back(ge);
     }
-    hipGraph_t g = nullptr;
-    const hipError_t ce = hipStreamEndCapture(sv.stream, &g);
-    if (ce != hipSuccess) return fail(DCLBM_ERR_HIP, "graph capture: %s", hipGetErrorString(ce));
-    sv.graph = g;
-    HIPCHECK(hipGraphInstantiate(&sv.gexec, g, nullptr, nullptr, 0));
     sv.origin = Clock::now();
     *out = h.release();
     return DCLBM_OK;
@@ -537,13 +599,13 @@ dclbm_status dclbm_server_destroy(dclbm_server* h)
     if (!h) return DCLBM_OK;
     Server& sv = h->s;
     if (sv.stream) (void)hipStreamSynchronize(sv.stream);
-    if (sv.gexec) (void)hipGraphExecDestroy(sv.gexec);
-    if (sv.graph) (void)hipGraphDestroy(sv.graph);
+    for (hipGraphExec_t e : sv.gexec) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t g : sv.graph) (void)hipGraphDestroy(g);
     for (auto& kv : sv.reqs)
         if (kv.second->done) (void)hipEventDestroy(kv.second->done);
     for (hipEvent_t e : sv.inflight) (void)hipEventDestroy(e);
     for (hipEvent_t e : sv.pool) (void)hipEventDestroy(e);
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < Server::kTabs; ++b) {
         if (sv.ptab_ev[b]) (void)hipEventDestroy(sv.ptab_ev[b]);
         if (sv.h_ptab[b]) (void)hipHostFree(sv.h_ptab[b]);
     }
@@ -582,12 +644,20 @@ dclbm_status dclbm_server_submit(dclbm_server* h, const dclbm_config* cfg, int64
     r->bytes = s.need_bytes;
     if (r->bytes > sv.arena.cap) return fail(DCLBM_ERR_NOMEM, "request needs %zu bytes, arena holds %zu", r->bytes, sv.arena.cap);
     r->n_probes = cfg->n_probes;
+    size_t nd = 0;
     for (size_t l = 0; l < s.lv.size(); ++l) {
         if (!h_rho[l] || !h_u[l]) return fail(DCLBM_ERR_INVALID, "null field of level %zu", l);
-        const size_t n = (size_t)s.lv[l].n_dense();
-        r->rho.emplace_back(h_rho[l], h_rho[l] + n);
-        r->u.emplace_back(h_u[l], h_u[l] + (size_t)s.D * n);
+        r->field_off.push_back(nd);
+        nd += (size_t)(1 + s.D) * (size_t)s.lv[l].n_dense();
         r->updates_per_step += s.lv[l].n_active << l;
+    }
+    r->fields_bytes = nd * sizeof(double);
+    r->fields = (double*)sv.pinned.get(r->fields_bytes);
+    if (!r->fields) return fail(DCLBM_ERR_HIP, "hipHostMalloc of %zu bytes failed", r->fields_bytes);
+    for (size_t l = 0; l < s.lv.size(); ++l) {
+        const size_t n = (size_t)s.lv[l].n_dense();
+        memcpy(r->fields + r->field_off[l], h_rho[l], n * sizeof(double));
+        memcpy(r->fields + r->field_off[l] + n, h_u[l], (size_t)s.D * n * sizeof(double));
     }
     std::lock_guard<std::mutex> lk(sv.mu);
     r->id = sv.next_id++;
@@ -602,6 +672,14 @@ dclbm_status dclbm_server_tick(dclbm_server* h, int32_t* n_running, int32_t* n_q
 {
     if (!h) return fail(DCLBM_ERR_INVALID, "null server");
     Server& sv = h->s;
+    std::lock_guard<std::mutex> tk(sv.tick_mu);
+    // bound the ticks queued on the stream, without holding the request lock
+    // (a submitting thread must not wait for the GPU)
+    while ((int)sv.inflight.size() >= sv.depth) {
+        HIPCHECK(hipEventSynchronize(sv.inflight.front()));
+        sv.pool.push_back(sv.inflight.front());
+        sv.inflight.pop_front();
+    }
     std::lock_guard<std::mutex> lk(sv.mu);
     dclbm_status st = tick_locked(sv);
     counts(sv, n_running, n_queued);
@@ -672,7 +750,7 @@ dclbm_status dclbm_server_stats(dclbm_server* h, dclbm_server_info* out)
     out->arena_bytes = (int64_t)sv.arena.cap;
     out->arena_free = (int64_t)sv.arena.free_bytes();
     out->arena_largest_free = (int64_t)sv.arena.largest();
-    out->grid = sv.G;
+    out->grid = sv.last_grid;
     out->n_phases = sv.NPH;
     return DCLBM_OK;
 }
