@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define DCLBM_ABI_VERSION 1
+#define DCLBM_ABI_VERSION 2
 #define DCLBM_MAX_LEVELS 4
 
 typedef enum {
@@ -50,6 +50,10 @@ typedef enum { DCLBM_D2Q9 = 0, DCLBM_D3Q19 = 1 } dclbm_lattice;
  *                as FP32 deviations f_i - w_i from the rest state.
  *  FP32_FP16:    FP32 arithmetic, populations stored as FP16 values of
  *                256 (f_i - w_i) (round to nearest even).
+ * In both reduced forms w_i generalises to E_i = f0_i(1, u_ref), the
+ * equilibrium of a uniform reference flow (dclbm_config.u_ref; the rest
+ * state when zero), and velocities are carried relative to u_ref, so that a
+ * mean flow does not eat the precision of the deviations.
  * Probes and balances always accumulate in FP64. */
 typedef enum { DCLBM_FP64 = 0, DCLBM_FP32 = 1, DCLBM_FP32_FP16 = 2 } dclbm_precision;
 
@@ -76,6 +80,8 @@ typedef struct {
     int64_t probe_capacity;   /* coarse steps of probe history kept on the device */
     int32_t newton_max_iter;  /* 0 -> 20 */
     double newton_tol;        /* 0 -> 1e-12 (FP64) or 2e-6 (FP32 forms); Sec. 3.2 stop rule |dX| < tol */
+    double u_ref[3];          /* reference velocity of the reduced-precision storage (ignored by FP64);
+                               * |u_ref| below the sound speed; zero: deviations from w_i */
 } dclbm_config;
 
 typedef struct dclbm_sim dclbm_sim;

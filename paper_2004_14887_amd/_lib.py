@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdclbm.so")
 
 MAX_LEVELS = 4
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 LATTICE = {"D2Q9": 0, "D3Q19": 1}
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2}
@@ -45,6 +45,7 @@ class Config(C.Structure):
         ("probe_capacity", C.c_int64),
         ("newton_max_iter", C.c_int32),
         ("newton_tol", C.c_double),
+        ("u_ref", C.c_double * 3),
     ]
 
 

@@ -177,7 +177,7 @@ struct EngineImpl final : Engine {
     void read(Sim& s, int l, double* f, double* rho, double* u) override
     {
         HostLevel& L = s.lv[l];
-        hipLaunchKernelGGL((k_read<DIM, P>), dense_grid(L), dim3(64, 4, 1), 0, s.stream, L.dev(),
+        hipLaunchKernelGGL((k_read<DIM, EQ, P>), dense_grid(L), dim3(64, 4, 1), 0, s.stream, L.dev(),
                            (const T*)L.f[L.parity], f, rho, u);
     }
     void read_shared(Sim& s, int l, double* out) override
@@ -188,13 +188,13 @@ struct EngineImpl final : Engine {
         const int ntf = (int)L.tf_meta.size();
         if (ntf)
             hipLaunchKernelGGL((k_read_shared<P>), dim3((ntf + 127) / 128), dim3(128), 0, s.stream, L.d_tf, ntf,
-                               L.nx, L.ny, n, (const R*)L.X, out);
+                               L.dev(), n, (const R*)L.X, out);
     }
     void balance(Sim& s, int l, double* partial, int nblocks) override
     {
         HostLevel& L = s.lv[l];
         const double vol = std::ldexp(1.0, -DIM * l);
-        hipLaunchKernelGGL((k_balance<DIM, P>), dim3(nblocks), dim3(256), 0, s.stream, L.dev(),
+        hipLaunchKernelGGL((k_balance<DIM, EQ, P>), dim3(nblocks), dim3(256), 0, s.stream, L.dev(),
                            (const T*)L.f[L.parity], vol, partial, s.d_flags);
     }
     void launch_multi(hipStream_t st, const MultiArgs& m, unsigned grid) override
@@ -370,7 +370,26 @@ dclbm_status build_geometry(Sim& s)
     s.newton_maxit = c.newton_max_iter > 0 ? c.newton_max_iter : 20;
     s.newton_tol = c.newton_tol > 0 ? c.newton_tol : (s.P == 0 ? 1e-12 : 2e-6);
     const int D = s.D, Q = s.Q;
+    double ur2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(c.u_ref[a])) return fail(DCLBM_ERR_INVALID, "u_ref must be finite");
+        if (a < D) ur2 += c.u_ref[a] * c.u_ref[a];
+    }
+    if (ur2 >= 1.0 / 3.0) return fail(DCLBM_ERR_INVALID, "|u_ref| must be below the sound speed");
     s.lv.assign(c.n_levels, HostLevel());
+    for (auto& L : s.lv) {
+        for (int a = 0; a < 3; ++a) L.ur[a] = (s.P == 0 || a >= D) ? 0.0 : c.u_ref[a];
+        // w_i (1 + B_i(ur)) and 3 + 9 xi_i.ur of the second-order equilibrium
+        const double uu = L.ur[0] * L.ur[0] + L.ur[1] * L.ur[1] + L.ur[2] * L.ur[2];
+        for (int i = 0; i < Q; ++i) {
+            int xi[3];
+            dirs(D, i, xi);
+            const double cr = xi[0] * L.ur[0] + xi[1] * L.ur[1] + xi[2] * L.ur[2];
+            const double w = D == 2 ? Lat<2>::w[i] : Lat<3>::w[i];
+            L.k1[i] = (float)(w * (1.0 + 3.0 * cr + 4.5 * cr * cr - 1.5 * uu));
+            L.k2[i] = (float)(3.0 + 9.0 * cr);
+        }
+    }
     double tau = c.tau0;
     for (int l = 0; l < c.n_levels; ++l) {
         HostLevel& L = s.lv[l];

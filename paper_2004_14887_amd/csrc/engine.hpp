@@ -31,6 +31,8 @@ struct HostLevel {
     int periodic = 0, boundary = 0, has_child = 0;
     int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
     int plo[3] = {0, 0, 0};
+    double ur[3] = {0.0, 0.0, 0.0};   // reference velocity of the carried variable (shifted forms)
+    float k1[19] = {}, k2[19] = {};   // per-direction constants of the shifted equilibrium
     double tau = 0.0;
     int64_t n_active = 0;
     // interface with the parent (level >= 1)
@@ -65,6 +67,11 @@ struct HostLevel {
         for (int a = 0; a < 3; ++a) {
             g.clo[a] = clo[a];
             g.chi[a] = chi[a];
+            g.ur[a] = ur[a];
+        }
+        for (int i = 0; i < 19; ++i) {
+            g.k1[i] = k1[i];
+            g.k2[i] = k2[i];
         }
         return g;
     }

@@ -45,6 +45,7 @@ struct Form<0> {
     using T = double;
     using R = double;
     static constexpr double rho0 = 0.0;
+    static constexpr bool shifted = false;
     __device__ static __forceinline__ R load(const T* p) { return *p; }
     __device__ static __forceinline__ void store(T* p, R v) { __builtin_nontemporal_store(v, p); }
     __device__ static __forceinline__ T nan() { return __builtin_nan(""); }
@@ -54,6 +55,7 @@ struct Form<1> {
     using T = float;
     using R = float;
     static constexpr double rho0 = 1.0;
+    static constexpr bool shifted = true;
     __device__ static __forceinline__ R load(const T* p) { return *p; }
     __device__ static __forceinline__ void store(T* p, R v) { __builtin_nontemporal_store(v, p); }
     __device__ static __forceinline__ T nan() { return __builtin_nanf(""); }
@@ -63,6 +65,7 @@ struct Form<2> {
     using T = __half;
     using R = float;
     static constexpr double rho0 = 1.0;
+    static constexpr bool shifted = true;
     static constexpr float scale = 256.0f;
     __device__ static __forceinline__ R load(const T* p)
     {
@@ -85,7 +88,68 @@ struct LevelDev {
     int boundary;      // own box faces are interfaces (level >= 1)
     int has_child;
     int clo[3], chi[3];// child box, closed, in this level's node coordinates
+    double ur[3];      // reference velocity of the carried variable (shifted forms; 0 for FP64)
+    // per direction, for the second-order shifted equilibrium (host-computed
+    // from ur, the same for every node): w_i (1 + B_i(ur)) and 3 + 9 xi_i.ur
+    float k1[19], k2[19];
 };
+
+template <typename R>
+__device__ __forceinline__ Ref<R> ref_of(const LevelDev& g)
+{
+    Ref<R> r;
+    r.ur[0] = R(g.ur[0]);
+    r.ur[1] = R(g.ur[1]);
+    r.ur[2] = R(g.ur[2]);
+    return r;
+}
+
+// E_i = f0_i(1, ur) in FP64: the population the shifted forms subtract.
+template <int DIM, int EQ>
+__device__ __forceinline__ double ref_pop(int i, const LevelDev& g)
+{
+    const double uu = g.ur[0] * g.ur[0] + g.ur[1] * g.ur[1] + g.ur[2] * g.ur[2];
+    return Lat<DIM>::w[i] * (1.0 + eq_bracket<DIM, EQ, double>(i, g.ur, uu));
+}
+
+// BGK of a bulk node in a shifted form with the second-order equilibrium,
+// from the per-direction constants of LevelDev: s0_i = drho k1_i + w_i rho
+// (dc (k2_i + 4.5 dc) - 1.5 q), dc = xi_i.du (the expansion of eq_s with
+// B_i(ur) and xi_i.ur precomputed; only drho, du and q vary per node).
+template <int DIM, typename R>
+__device__ __forceinline__ void bgk_shift2(R s[], const LevelDev& g, R drho, const R du[3], R keep)
+{
+    R q = R(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) q += du[a] * (R(2) * R(g.ur[a]) + du[a]);
+    const R rho = R(1) + drho;
+    const R q15 = R(1.5) * q;
+#pragma unroll
+    for (int i = 0; i < Lat<DIM>::Q; ++i) {
+        R dc = R(0);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            if (cdir<DIM>(i, a) > 0) dc += du[a];
+            if (cdir<DIM>(i, a) < 0) dc -= du[a];
+        }
+        const R e = drho * R(g.k1[i]) + R(Lat<DIM>::w[i]) * rho * (dc * (R(g.k2[i]) + R(4.5) * dc) - q15);
+        s[i] = e + keep * (s[i] - e);
+    }
+}
+
+// Reciprocal: in FP32 the hardware estimate refined by one Newton step
+// (r + r (1 - x r), two FMAs; the bare 1-ulp estimate biases u step after
+// step), exact division in FP64.
+template <typename R>
+__device__ __forceinline__ R recip(R x)
+{
+    if constexpr (sizeof(R) == 4) {
+        const float r = __builtin_amdgcn_rcpf(x);
+        return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+    } else {
+        return R(1) / x;
+    }
+}
 
 // Element index of direction i at node (x, y, z).
 template <int DIM>
@@ -246,7 +310,8 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
     const int4 info = a.seg_info[sgi];
     const T* src = (const T*)a.src;
     T* dst = (T*)a.dst;
-    const R rho0 = R(F::rho0);
+    constexpr bool SH = F::shifted;
+    const Ref<R> rf = ref_of<R>(a.g);
     const int j = threadIdx.x;
     // ---- phase 1: co-located nodes (own and halo).  Column j of the LDS
     // tile holds the node's h (fine value where Gamma = 1, time-interpolated
@@ -277,8 +342,8 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
             col[i * TFM] = v;
         }
         auto hv = [&](int i) -> R { return col[i * TFM]; };
-        R drho, u[3];
-        const int it = newton_v<DIM, EQ, R>(hv, gR, R(a.Rfac), rho0, R(a.tol), a.maxit, drho, u);
+        R drho, du[3];
+        const int it = newton_v<DIM, EQ, SH, R>(hv, gR, R(a.Rfac), rf, R(a.tol), a.maxit, drho, du);
         if (it < 0) {
             if (owned) atomicOr(a.flags, 1);
             R jj[3] = {R(0), R(0), R(0)};
@@ -291,26 +356,23 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
                 jj[1] += R(cdir<DIM>(i, 1)) * v;
                 jj[2] += R(cdir<DIM>(i, 2)) * v;
             }
-            const R rr = rho0 + drho;
-            u[0] = jj[0] / rr;
-            u[1] = jj[1] / rr;
-            u[2] = DIM == 3 ? jj[2] / rr : R(0);
+            velocity<DIM, SH, R>(rf, drho, jj, du);
         }
-        const R uu = u[0] * u[0] + u[1] * u[1] + (DIM == 3 ? u[2] * u[2] : R(0));
+        const Mac<R> mx = make_mac<DIM, SH, R>(rf, drho, du);
         // Eq.(rescff) on every coarse-coupled direction
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             if ((gR >> i) & 1u) {
-                const R e0 = eq_s<DIM, EQ, R>(i, rho0, drho, u, uu);
+                const R e0 = eq_s<DIM, EQ, SH, R>(i, rf, mx);
                 col[i * TFM] = e0 + R(a.Rfac) * (col[i * TFM] - e0);
             }
         }
         if (owned) {
             R* X = (R*)a.X;
             X[t] = drho;
-            X[n + t] = u[0];
-            X[2 * n + t] = u[1];
-            X[3 * n + t] = u[2];
+            X[n + t] = mx.du[0];
+            X[2 * n + t] = mx.du[1];
+            X[3 * n + t] = mx.du[2];
             if (a.substep == 2) {
                 // Eq.(rescfc): every coarse population from the completed fine
                 // ones, then the coarse collision with X
@@ -319,7 +381,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
                 T* dp = (T*)a.dst_parent;
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    const R e0 = eq_s<DIM, EQ, R>(i, rho0, drho, u, uu);
+                    const R e0 = eq_s<DIM, EQ, SH, R>(i, rf, mx);
                     const R c = e0 + invR * (col[i * TFM] - e0);
                     F::store(dp + eoff<DIM>(a.gp, i, pm.x, pm.y, pm.z), e0 + keepp * (c - e0));
                 }
@@ -327,7 +389,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
             const R keep = R(a.keep);
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                const R e0 = eq_s<DIM, EQ, R>(i, rho0, drho, u, uu);
+                const R e0 = eq_s<DIM, EQ, SH, R>(i, rf, mx);
                 F::store(dst + eoff<DIM>(a.g, i, m.x, m.y, m.z), e0 + keep * (col[i * TFM] - e0));
             }
         }
@@ -374,11 +436,10 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
                     if ((miss >> i) & 1u) s[i] += wq * lds[i * TFM + idx];
             }
         }
-        R drho, jj[3];
+        R drho, jj[3], du[3];
         moments<DIM, R>(s, drho, jj);
-        const R rho = rho0 + drho;
-        const R u[3] = {jj[0] / rho, jj[1] / rho, DIM == 3 ? jj[2] / rho : R(0)};
-        bgk<DIM, EQ, R>(s, rho0, drho, u, R(a.keep));
+        velocity<DIM, SH, R>(rf, drho, jj, du);
+        bgk<DIM, EQ, SH, R>(s, rf, make_mac<DIM, SH, R>(rf, drho, du), R(a.keep));
 #pragma unroll
         for (int i = 0; i < Q; ++i) F::store(dst + eoff<DIM>(a.g, i, m.x, m.y, m.z), s[i]);
     }
@@ -404,16 +465,45 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
     if (x >= g.nx || y >= g.ny) return;
     if (is_interface_or_hole<DIM>(g, x, y, z)) return;
     const T* src = (const T*)a.src;
+    // pull sources: the node's element plus per-axis neighbour deltas (the
+    // 64-node x blocks and the periodic wrap of level 0 resolved once per
+    // node), so each direction costs one add
+    constexpr int64_t XQ = (int64_t)Q * 64;
+    const int64_t rowe = (int64_t)g.nxb * XQ, plane = rowe * g.ny;
+    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1, zm = z - 1, zp = z + 1;
+    if (g.periodic) {
+        xm = xm < 0 ? xm + g.nx : xm;
+        xp = xp >= g.nx ? xp - g.nx : xp;
+        ym = ym < 0 ? ym + g.ny : ym;
+        yp = yp >= g.ny ? yp - g.ny : yp;
+        if (DIM == 3) {
+            zm = zm < 0 ? zm + g.nz : zm;
+            zp = zp >= g.nz ? zp - g.nz : zp;
+        }
+    }
+    const int64_t ex = (int64_t)(x >> 6) * XQ + (x & 63);
+    // index c + 1 for xi component c: the source is at coordinate - c
+    const int64_t dx[3] = {(int64_t)(xp >> 6) * XQ + (xp & 63) - ex, 0, (int64_t)(xm >> 6) * XQ + (xm & 63) - ex};
+    const int64_t dy[3] = {(int64_t)(yp - y) * rowe, 0, (int64_t)(ym - y) * rowe};
+    const int64_t dz[3] = {(int64_t)(zp - z) * plane, 0, (int64_t)(zm - z) * plane};
+    const int64_t e0 = (int64_t)z * plane + (int64_t)y * rowe + ex;
     R s[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) s[i] = F::load(src + src_off<DIM>(g, x, y, z, i));
-    R drho, j[3];
+    for (int i = 0; i < Q; ++i)
+        s[i] = F::load(src + (e0 + dx[cdir<DIM>(i, 0) + 1] + dy[cdir<DIM>(i, 1) + 1] +
+                              (DIM == 3 ? dz[cdir<DIM>(i, 2) + 1] : 0) + i * 64));
+    constexpr bool SH = F::shifted;
+    const Ref<R> rf = ref_of<R>(g);
+    R drho, j[3], du[3];
     moments<DIM, R>(s, drho, j);
-    const R rho = R(F::rho0) + drho;
-    const R inv = R(1) / rho;
-    const R u[3] = {j[0] * inv, j[1] * inv, DIM == 3 ? j[2] * inv : R(0)};
-    bgk<DIM, EQ, R>(s, R(F::rho0), drho, u, R(a.keep));
-    T* d = (T*)a.dst + eoff<DIM>(g, 0, x, y, z);
+    const R inv = recip<R>((SH ? R(1) : R(0)) + drho);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) du[c] = c < DIM ? (SH ? j[c] - drho * rf.ur[c] : j[c]) * inv : R(0);
+    if constexpr (SH && EQ == 2)
+        bgk_shift2<DIM, R>(s, g, drho, du, R(a.keep));
+    else
+        bgk<DIM, EQ, SH, R>(s, rf, make_mac<DIM, SH, R>(rf, drho, du), R(a.keep));
+    T* d = (T*)a.dst + e0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) F::store(d + i * 64, s[i]);
 }
@@ -494,18 +584,17 @@ __global__ __launch_bounds__(256) void k_init(LevelDev g, typename Form<P>::T* _
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const int64_t d = ((int64_t)z * g.ny + y) * g.nx + x;
     // equilibrium evaluated in FP64, then carried in the storage form
-    const double r = rho[d];
+    constexpr bool SH = F::shifted;
+    const Ref<double> rf = ref_of<double>(g);
     const double uu3[3] = {u[d], u[n + d], DIM == 3 ? u[2 * n + d] : 0.0};
-    const double uu = uu3[0] * uu3[0] + uu3[1] * uu3[1] + uu3[2] * uu3[2];
-    const double drho = r - F::rho0;
+    const double du[3] = {SH ? uu3[0] - rf.ur[0] : uu3[0], SH ? uu3[1] - rf.ur[1] : uu3[1],
+                          SH ? uu3[2] - rf.ur[2] : uu3[2]};
+    const Mac<double> mc = make_mac<DIM, SH, double>(rf, rho[d] - F::rho0, du);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const double e = eq_s<DIM, EQ, double>(i, F::rho0, drho, uu3, uu);
-        F::store(dst + eoff<DIM>(g, i, x, y, z), R(e));
-    }
+    for (int i = 0; i < Q; ++i) F::store(dst + eoff<DIM>(g, i, x, y, z), R(eq_s<DIM, EQ, SH, double>(i, rf, mc)));
 }
 
-template <int DIM, int P>
+template <int DIM, int EQ, int P>
 __global__ __launch_bounds__(256) void k_read(LevelDev g, const typename Form<P>::T* __restrict__ src,
                                               double* __restrict__ fout, double* __restrict__ rho,
                                               double* __restrict__ u)
@@ -523,7 +612,7 @@ __global__ __launch_bounds__(256) void k_read(LevelDev g, const typename Form<P>
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const double s = hole ? __builtin_nan("") : (double)F::load(src + eoff<DIM>(g, i, x, y, z));
-        const double f = s + F::rho0 * Lat<DIM>::w[i];
+        const double f = s + F::rho0 * ref_pop<DIM, EQ>(i, g);
         if (fout) fout[(int64_t)i * n + d] = f;
         r += f;
         j[0] += cdir<DIM>(i, 0) * f;
@@ -537,16 +626,17 @@ __global__ __launch_bounds__(256) void k_read(LevelDev g, const typename Form<P>
 
 // X of co-located nodes scattered to a dense [4][n] FP64 array (rho, u).
 template <int P>
-__global__ __launch_bounds__(128) void k_read_shared(const int4* __restrict__ meta, int ntf, int nx, int ny,
+__global__ __launch_bounds__(128) void k_read_shared(const int4* __restrict__ meta, int ntf, LevelDev g,
                                                      int64_t n, const typename Form<P>::R* __restrict__ X,
                                                      double* __restrict__ out)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntf) return;
     const int4 m = meta[t];
-    const int64_t d = ((int64_t)m.z * ny + m.y) * nx + m.x;
+    const int64_t d = ((int64_t)m.z * g.ny + m.y) * g.nx + m.x;
     out[d] = Form<P>::rho0 + (double)X[t];
-    for (int a = 1; a < 4; ++a) out[(int64_t)a * n + d] = (double)X[(int64_t)a * ntf + t];
+    for (int a = 1; a < 4; ++a)
+        out[(int64_t)a * n + d] = (double)X[(int64_t)a * ntf + t] + (Form<P>::shifted ? g.ur[a - 1] : 0.0);
 }
 
 static __global__ void k_fill_nan_f64(double* p, int64_t n)
@@ -711,7 +801,7 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <int DIM, int P>
+template <int DIM, int EQ, int P>
 __global__ __launch_bounds__(256) void k_balance(LevelDev g, const typename Form<P>::T* __restrict__ src,
                                                  double vol, double* __restrict__ partial,
                                                  int* __restrict__ flags)
@@ -732,7 +822,7 @@ __global__ __launch_bounds__(256) void k_balance(LevelDev g, const typename Form
             continue;   // hole or owned by the finer level
         double r = 0.0, j[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < Q; ++i) {
-            const double f = (double)F::load(src + eoff<DIM>(g, i, x, y, z)) + F::rho0 * Lat<DIM>::w[i];
+            const double f = (double)F::load(src + eoff<DIM>(g, i, x, y, z)) + F::rho0 * ref_pop<DIM, EQ>(i, g);
             r += f;
             j[0] += cdir<DIM>(i, 0) * f;
             j[1] += cdir<DIM>(i, 1) * f;

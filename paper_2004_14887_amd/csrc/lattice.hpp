@@ -4,10 +4,12 @@
 // solve for the shared equilibrium at co-located nodes (Sec. 3.2,
 // Eq.(system_fi), Eq.(updated_macro)).
 //
-// Populations are carried as s_i = f_i - rho0 * w_i.  The FP64 form uses
-// rho0 = 0 (s = f); the FP32 and FP16-storage forms use rho0 = 1, i.e. the
-// deviation from the rest state, so density and momentum sums never cancel
-// against the O(1) rest weights.
+// Populations are carried as s_i = f_i - E_i.  The FP64 form carries f
+// itself (E = 0).  The FP32 and FP16-storage forms carry the deviation from
+// the equilibrium of a uniform reference state, E_i = f0_i(1, ur) (the rest
+// state w_i when ur = 0), and the velocity as du = u - ur: density and
+// momentum sums then never cancel against O(1) values, and a mean flow ur
+// costs no precision.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -77,24 +79,98 @@ __device__ __forceinline__ R eq_bracket(int i, const R u[3], R uu)
     return b;
 }
 
-// Equilibrium in the carried variable: s0_i = f0_i - rho0 w_i
-//   = w_i (drho + rho B_i),  with rho = rho0 + drho.
-template <int DIM, int EQ, typename R>
-__device__ __forceinline__ R eq_s(int i, R rho0, R drho, const R u[3], R uu)
+// Reference state of the shifted forms.
+template <typename R>
+struct Ref {
+    R ur[3];
+};
+
+// Macroscopic state of a node in carried form.  SH: shifted form (rho0 = 1,
+// E_i = f0_i(1, ur)); otherwise rho0 = 0 and du is u itself.
+template <typename R>
+struct Mac {
+    R drho;    // rho - rho0
+    R du[3];   // u - ur
+    R u[3];    // ur + du
+    R uu;      // |u|^2
+    R q;       // |u|^2 - |ur|^2 = du.(2 ur + du)
+};
+
+template <int DIM, bool SH, typename R>
+__device__ __forceinline__ Mac<R> make_mac(const Ref<R>& rf, R drho, const R du[3])
 {
-    const R rho = rho0 + drho;
-    return R(Lat<DIM>::w[i]) * (drho + rho * eq_bracket<DIM, EQ, R>(i, u, uu));
+    Mac<R> m;
+    m.drho = drho;
+    m.uu = R(0);
+    m.q = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        m.du[a] = a < DIM ? du[a] : R(0);
+        m.u[a] = SH ? rf.ur[a] + m.du[a] : m.du[a];
+        m.uu += m.u[a] * m.u[a];
+        if (SH) m.q += m.du[a] * (R(2) * rf.ur[a] + m.du[a]);
+    }
+    return m;
 }
 
-// d s0_i / d(drho, u_b)
+// B_i(ur + du) - B_i(ur), written in du so that nothing cancels:
+//   3 dc + 4.5 dc (2 c_r + dc) - 1.5 du.(2 ur + du)   [+ 13.5 sum_{a!=g} h_ag
+//   (du_a (2 ur_a + du_a) u_g + ur_a^2 du_g)],  c_r = xi.ur, dc = xi.du.
 template <int DIM, int EQ, typename R>
-__device__ __forceinline__ void eq_s_grad(int i, R rho0, R drho, const R u[3], R uu, R g[4])
+__device__ __forceinline__ R eq_dbracket(int i, const Ref<R>& rf, const Mac<R>& m)
 {
-    const R rho = rho0 + drho;
+    R cr = R(0), dc = R(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        cr += R(cdir<DIM>(i, a)) * rf.ur[a];
+        dc += R(cdir<DIM>(i, a)) * m.du[a];
+    }
+    R d = dc * (R(3) + R(4.5) * (R(2) * cr + dc)) - R(1.5) * m.q;
+    if constexpr (EQ == 3) {
+        R t = R(0);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+            for (int g = 0; g < DIM; ++g) {
+                if (a == g) continue;
+                const int h3 = cdir<DIM>(i, a) * cdir<DIM>(i, a) * cdir<DIM>(i, g);
+                const int xg = cdir<DIM>(i, g);
+                if (h3 == 0 && xg == 0) continue;
+                t += (R(h3) - R(xg) / R(3)) *
+                     (m.du[a] * (R(2) * rf.ur[a] + m.du[a]) * m.u[g] + rf.ur[a] * rf.ur[a] * m.du[g]);
+            }
+        d += R(13.5) * t;
+    }
+    return d;
+}
+
+// Equilibrium in the carried variable, s0_i = f0_i(rho, u) - E_i:
+//   FP64 (E = 0):  w_i rho (1 + B_i(u));
+//   shifted:       w_i (drho (1 + B_i(ur)) + rho (B_i(u) - B_i(ur))),
+// where B_i(ur) is the same for every node (uniform registers) and the
+// bracket difference is written in du, so only drho and du vary per lane.
+template <int DIM, int EQ, bool SH, typename R>
+__device__ __forceinline__ R eq_s(int i, const Ref<R>& rf, const Mac<R>& m)
+{
+    if constexpr (SH) {
+        const R uur = rf.ur[0] * rf.ur[0] + rf.ur[1] * rf.ur[1] + (DIM == 3 ? rf.ur[2] * rf.ur[2] : R(0));
+        const R br = eq_bracket<DIM, EQ, R>(i, rf.ur, uur);
+        return R(Lat<DIM>::w[i]) * (m.drho * (R(1) + br) + (R(1) + m.drho) * eq_dbracket<DIM, EQ, R>(i, rf, m));
+    } else {
+        return R(Lat<DIM>::w[i]) * m.drho * (R(1) + eq_bracket<DIM, EQ, R>(i, m.u, m.uu));
+    }
+}
+
+// d s0_i / d(drho, du_b) (= d f0_i / d(rho, u_b)).
+template <int DIM, int EQ, bool SH, typename R>
+__device__ __forceinline__ void eq_s_grad(int i, const Mac<R>& m, R g[4])
+{
+    const R rho = (SH ? R(1) : R(0)) + m.drho;
     const R wi = R(Lat<DIM>::w[i]);
+    const R* u = m.u;
     const R cu = R(cdir<DIM>(i, 0)) * u[0] + R(cdir<DIM>(i, 1)) * u[1] +
                  (DIM == 3 ? R(cdir<DIM>(i, 2)) * u[2] : R(0));
-    g[0] = wi * (R(1) + eq_bracket<DIM, EQ, R>(i, u, uu));
+    g[0] = wi * (R(1) + eq_bracket<DIM, EQ, R>(i, u, m.uu));
 #pragma unroll
     for (int b = 0; b < DIM; ++b) {
         const R xb = R(cdir<DIM>(i, b));
@@ -120,7 +196,8 @@ __device__ __forceinline__ void eq_s_grad(int i, R rho0, R drho, const R u[3], R
     if (DIM == 2) g[3] = R(0);
 }
 
-// Moments of the carried variable: drho = sum s, j = sum xi s  (sum w = 1, sum w xi = 0).
+// Moments of the carried variable: drho = sum s, dj = sum xi s
+// (sum E = rho0, sum xi E = rho0 ur).
 template <int DIM, typename R>
 __device__ __forceinline__ void moments(const R s[], R& drho, R j[3])
 {
@@ -135,14 +212,23 @@ __device__ __forceinline__ void moments(const R s[], R& drho, R j[3])
     }
 }
 
-// BGK relaxation towards f0(rho, u), in place on the carried variable.
-template <int DIM, int EQ, typename R>
-__device__ __forceinline__ void bgk(R s[], R rho0, R drho, const R u[3], R keep /* 1 - 1/tau */)
+// du = u - ur from the carried moments: u = (rho0 ur + dj) / rho, so
+// du = (dj - drho ur) / rho (shifted) or dj / rho (rho0 = 0).
+template <int DIM, bool SH, typename R>
+__device__ __forceinline__ void velocity(const Ref<R>& rf, R drho, const R dj[3], R du[3])
 {
-    const R uu = u[0] * u[0] + u[1] * u[1] + (DIM == 3 ? u[2] * u[2] : R(0));
+    const R inv = R(1) / ((SH ? R(1) : R(0)) + drho);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) du[a] = a < DIM ? (SH ? dj[a] - drho * rf.ur[a] : dj[a]) * inv : R(0);
+}
+
+// BGK relaxation towards f0(rho, u), in place on the carried variable.
+template <int DIM, int EQ, bool SH, typename R>
+__device__ __forceinline__ void bgk(R s[], const Ref<R>& rf, const Mac<R>& m, R keep /* 1 - 1/tau */)
+{
 #pragma unroll
     for (int i = 0; i < Lat<DIM>::Q; ++i) {
-        const R e = eq_s<DIM, EQ, R>(i, rho0, drho, u, uu);
+        const R e = eq_s<DIM, EQ, SH, R>(i, rf, m);
         s[i] = e + keep * (s[i] - e);
     }
 }
@@ -198,68 +284,16 @@ __device__ __forceinline__ bool solve_small(R A[4][4], R b[4], R x[4])
     return true;
 }
 
-// Newton-Raphson for F(X) = sum_i G_i Phi_i (h_i - f0_i(X)) = 0, Phi = (1, xi),
-// in the carried variable (h and f0 both shifted by rho0 w_i, which cancels
-// in F because sum_i G_i Phi_i w_i is common to both terms).  Unknowns
-// (drho, u).  Start: raw moments of h.  Stop when |dX|_inf < tol.
-// Returns the number of updates made, or -1 on failure.
-template <int DIM, int EQ, typename R>
-__device__ __forceinline__ int newton(const R h[], uint32_t gamma_R_mask, R Rfac, R rho0, R tol,
-                                      int maxit, R& drho, R u[3])
-{
-    constexpr int Q = Lat<DIM>::Q;
-    constexpr int N = DIM + 1;
-    R j[3];
-    moments<DIM, R>(h, drho, j);
-    const R rho_init = rho0 + drho;
-    u[0] = j[0] / rho_init;
-    u[1] = j[1] / rho_init;
-    u[2] = DIM == 3 ? j[2] / rho_init : R(0);
-    for (int it = 1; it <= maxit; ++it) {
-        const R uu = u[0] * u[0] + u[1] * u[1] + (DIM == 3 ? u[2] * u[2] : R(0));
-        R F[4] = {R(0), R(0), R(0), R(0)};
-        R J[4][4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) J[r][c] = R(0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const R G = ((gamma_R_mask >> i) & 1u) ? Rfac : R(1);
-            const R e = eq_s<DIM, EQ, R>(i, rho0, drho, u, uu);
-            R g[4];
-            eq_s_grad<DIM, EQ, R>(i, rho0, drho, u, uu, g);
-            const R d = G * (h[i] - e);
-            const R phi[4] = {R(1), R(cdir<DIM>(i, 0)), R(cdir<DIM>(i, 1)), R(cdir<DIM>(i, 2))};
-#pragma unroll
-            for (int r = 0; r < N; ++r) {
-                if (phi[r] == R(0)) continue;
-                F[r] += phi[r] * d;
-#pragma unroll
-                for (int c = 0; c < N; ++c) J[r][c] -= G * phi[r] * g[c];
-            }
-        }
-        R rhs[4] = {-F[0], -F[1], -F[2], -F[3]};
-        R dX[4] = {R(0), R(0), R(0), R(0)};
-        if (!solve_small<N, R>(J, rhs, dX)) return -1;
-        drho += dX[0];
-        R nrm = fabs(dX[0]);
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) {
-            u[b] += dX[1 + b];
-            nrm = fmax(nrm, fabs(dX[1 + b]));
-        }
-        if (!(nrm == nrm)) return -1;
-        if (nrm < tol) return it;
-    }
-    return -1;
-}
-
-// The same Newton iteration with h_i read through an accessor hv(i) (the
-// interface kernels keep h in LDS, so only X, F and J occupy registers).
-template <int DIM, int EQ, typename R, typename HV>
-__device__ __forceinline__ int newton_v(const HV& hv, uint32_t gamma_R_mask, R Rfac, R rho0, R tol, int maxit,
-                                        R& drho, R u[3])
+// Newton-Raphson for F(X) = sum_i G_i Phi_i (h_i - f0_i(X)) = 0, Phi = (1, xi)
+// (Sec. 3.2, Eq.(system_fi)), in the carried variable (h and f0 are both
+// shifted by E_i, which cancels in F).  Unknowns X = (drho, du); the
+// Jacobian is analytic.  Start: raw moments of h.  Stop when |dX|_inf < tol.
+// h_i is read through an accessor hv(i) (the interface kernels keep h in
+// LDS, so only X, F and J occupy registers).  Returns the number of updates
+// made, or -1 on failure.
+template <int DIM, int EQ, bool SH, typename R, typename HV>
+__device__ __forceinline__ int newton_v(const HV& hv, uint32_t gamma_R_mask, R Rfac, const Ref<R>& rf, R tol,
+                                        int maxit, R& drho, R du[3])
 {
     constexpr int Q = Lat<DIM>::Q;
     constexpr int N = DIM + 1;
@@ -273,24 +307,24 @@ __device__ __forceinline__ int newton_v(const HV& hv, uint32_t gamma_R_mask, R R
         if (cdir<DIM>(i, 1)) j[1] += R(cdir<DIM>(i, 1)) * v;
         if (DIM == 3 && cdir<DIM>(i, 2)) j[2] += R(cdir<DIM>(i, 2)) * v;
     }
-    const R rho_init = rho0 + drho;
-    u[0] = j[0] / rho_init;
-    u[1] = j[1] / rho_init;
-    u[2] = DIM == 3 ? j[2] / rho_init : R(0);
+    velocity<DIM, SH, R>(rf, drho, j, du);
     for (int it = 1; it <= maxit; ++it) {
-        const R uu = u[0] * u[0] + u[1] * u[1] + (DIM == 3 ? u[2] * u[2] : R(0));
+        const Mac<R> m = make_mac<DIM, SH, R>(rf, drho, du);
         R F[4] = {R(0), R(0), R(0), R(0)};
         R J[4][4];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int c = 0; c < 4; ++c) J[r][c] = R(0);
-#pragma unroll
+        // one direction at a time (the index is uniform): unrolled, the
+        // interleaved equilibria and gradients of all Q directions would set
+        // the register count of the whole level kernel
+#pragma unroll 1
         for (int i = 0; i < Q; ++i) {
             const R G = ((gamma_R_mask >> i) & 1u) ? Rfac : R(1);
-            const R e = eq_s<DIM, EQ, R>(i, rho0, drho, u, uu);
+            const R e = eq_s<DIM, EQ, SH, R>(i, rf, m);
             R g[4];
-            eq_s_grad<DIM, EQ, R>(i, rho0, drho, u, uu, g);
+            eq_s_grad<DIM, EQ, SH, R>(i, m, g);
             const R d = G * (hv(i) - e);
             const R phi[4] = {R(1), R(cdir<DIM>(i, 0)), R(cdir<DIM>(i, 1)), R(cdir<DIM>(i, 2))};
 #pragma unroll
@@ -308,7 +342,7 @@ __device__ __forceinline__ int newton_v(const HV& hv, uint32_t gamma_R_mask, R R
         R nrm = fabs(dX[0]);
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {
-            u[b] += dX[1 + b];
+            du[b] += dX[1 + b];
             nrm = fmax(nrm, fabs(dX[1 + b]));
         }
         if (!(nrm == nrm)) return -1;

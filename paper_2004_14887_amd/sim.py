@@ -20,7 +20,9 @@ from .workloads import Workload, initial_fields
 
 
 def make_config(wl: Workload, precision: str = "fp64", probe_capacity: Optional[int] = None,
-                newton_max_iter: int = 0, newton_tol: float = 0.0):
+                newton_max_iter: int = 0, newton_tol: float = 0.0, u_ref=None):
+    """C configuration of a workload.  u_ref (reduced-precision storage
+    reference velocity) defaults to the workload's background flow."""
     cfg = _lib.Config()
     cfg.abi_version = _lib.ABI_VERSION
     cfg.lattice = _lib.LATTICE[wl.lattice]
@@ -44,6 +46,9 @@ def make_config(wl: Workload, precision: str = "fp64", probe_capacity: Optional[
     cfg.probe_capacity = probe_capacity if probe_capacity is not None else max(1, wl.steps)
     cfg.newton_max_iter = newton_max_iter
     cfg.newton_tol = newton_tol
+    ur = wl.background if u_ref is None else u_ref
+    for a in range(3):
+        cfg.u_ref[a] = float(ur[a]) if a < len(ur) and a < wl.D else 0.0
     return cfg, probes
 
 
@@ -58,13 +63,13 @@ def workspace_bytes(wl: Workload, precision: str = "fp64", **kw) -> int:
 class Simulation:
     def __init__(self, wl: Workload, precision: str = "fp64", device="cuda:0",
                  stream: Optional[torch.cuda.Stream] = None, probe_capacity: Optional[int] = None,
-                 newton_max_iter: int = 0, newton_tol: float = 0.0):
+                 newton_max_iter: int = 0, newton_tol: float = 0.0, u_ref=None):
         self.lib = _lib.load()
         self.wl = wl
         self.precision = precision
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
-        cfg, self._probe_buf = make_config(wl, precision, probe_capacity, newton_max_iter, newton_tol)
+        cfg, self._probe_buf = make_config(wl, precision, probe_capacity, newton_max_iter, newton_tol, u_ref)
         self.cfg = cfg
         nbytes = C.c_size_t()
         _lib.check(self.lib.dclbm_workspace_bytes(C.byref(cfg), C.byref(nbytes)))

@@ -59,6 +59,11 @@ def test_workspace_bytes_and_validation():
     bad.tau0 = 0.5
     with pytest.raises(DclbmError):
         workspace_bytes(bad)
+    # the storage reference velocity must be subsonic (and is ignored by FP64)
+    with pytest.raises(DclbmError) as ei:
+        workspace_bytes(wl, "fp32", u_ref=(0.6, 0.0))
+    assert "u_ref" in str(ei.value)
+    assert workspace_bytes(wl, "fp32", u_ref=(0.1, 0.05)) == b32
 
 
 def test_lattice_table_matches_paper_numbering():
