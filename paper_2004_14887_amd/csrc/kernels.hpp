@@ -137,6 +137,31 @@ __device__ __forceinline__ void bgk_shift2(R s[], const LevelDev& g, R drho, con
     }
 }
 
+// Equilibrium and gradient for Newton in a shifted form with the
+// second-order equilibrium, from the same per-direction constants:
+//   s0_i = drho k1_i + w_i rho (dc (k2_i + 4.5 dc) - 1.5 q),
+//   d s0_i / d drho = k1_i + w_i (dc (k2_i + 4.5 dc) - 1.5 q),
+//   d s0_i / d du_b = w_i rho (xi_ib (k2_i + 9 dc) - 3 u_b),  dc = xi_i.du.
+template <int DIM, typename R>
+struct EqGradShift2 {
+    const LevelDev& g;
+    __device__ __forceinline__ void operator()(int i, const Mac<R>& m, R& e, R gr[4]) const
+    {
+        R dc = R(0);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) dc += R(cdir<DIM>(i, a)) * m.du[a];
+        const R wi = R(Lat<DIM>::w[i]), k1 = R(g.k1[i]), k2 = R(g.k2[i]);
+        const R rho = R(1) + m.drho;
+        const R D = dc * (k2 + R(4.5) * dc) - R(1.5) * m.q;
+        e = m.drho * k1 + wi * rho * D;
+        gr[0] = k1 + wi * D;
+        const R t = k2 + R(9) * dc;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) gr[1 + b] = wi * rho * (R(cdir<DIM>(i, b)) * t - R(3) * m.u[b]);
+        if (DIM == 2) gr[3] = R(0);
+    }
+};
+
 // Reciprocal: in FP32 the hardware estimate refined by one Newton step
 // (r + r (1 - x r), two FMAs; the bare 1-ulp estimate biases u step after
 // step), exact division in FP64.
@@ -343,7 +368,13 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
         }
         auto hv = [&](int i) -> R { return col[i * TFM]; };
         R drho, du[3];
-        const int it = newton_v<DIM, EQ, SH, R>(hv, gR, R(a.Rfac), rf, R(a.tol), a.maxit, drho, du);
+        int it;
+        if constexpr (SH && EQ == 2)
+            it = newton_v<DIM, EQ, SH, R>(hv, gR, R(a.Rfac), rf, R(a.tol), a.maxit, drho, du,
+                                          EqGradShift2<DIM, R>{a.g});
+        else
+            it = newton_v<DIM, EQ, SH, R>(hv, gR, R(a.Rfac), rf, R(a.tol), a.maxit, drho, du,
+                                          EqGrad<DIM, EQ, SH, R>{rf});
         if (it < 0) {
             if (owned) atomicOr(a.flags, 1);
             R jj[3] = {R(0), R(0), R(0)};
@@ -359,11 +390,20 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
             velocity<DIM, SH, R>(rf, drho, jj, du);
         }
         const Mac<R> mx = make_mac<DIM, SH, R>(rf, drho, du);
+        auto eq0 = [&](int i) -> R {
+            if constexpr (SH && EQ == 2) {
+                R e, gr[4];
+                EqGradShift2<DIM, R>{a.g}(i, mx, e, gr);
+                return e;
+            } else {
+                return eq_s<DIM, EQ, SH, R>(i, rf, mx);
+            }
+        };
         // Eq.(rescff) on every coarse-coupled direction
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             if ((gR >> i) & 1u) {
-                const R e0 = eq_s<DIM, EQ, SH, R>(i, rf, mx);
+                const R e0 = eq0(i);
                 col[i * TFM] = e0 + R(a.Rfac) * (col[i * TFM] - e0);
             }
         }
@@ -381,7 +421,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
                 T* dp = (T*)a.dst_parent;
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    const R e0 = eq_s<DIM, EQ, SH, R>(i, rf, mx);
+                    const R e0 = eq0(i);
                     const R c = e0 + invR * (col[i * TFM] - e0);
                     F::store(dp + eoff<DIM>(a.gp, i, pm.x, pm.y, pm.z), e0 + keepp * (c - e0));
                 }
@@ -389,7 +429,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
             const R keep = R(a.keep);
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                const R e0 = eq_s<DIM, EQ, SH, R>(i, rf, mx);
+                const R e0 = eq0(i);
                 F::store(dst + eoff<DIM>(a.g, i, m.x, m.y, m.z), e0 + keep * (col[i * TFM] - e0));
             }
         }

@@ -291,9 +291,20 @@ __device__ __forceinline__ bool solve_small(R A[4][4], R b[4], R x[4])
 // h_i is read through an accessor hv(i) (the interface kernels keep h in
 // LDS, so only X, F and J occupy registers).  Returns the number of updates
 // made, or -1 on failure.
-template <int DIM, int EQ, bool SH, typename R, typename HV>
+// The equilibrium s0_i(X) and its gradient d s0_i / d(drho, du) together.
+template <int DIM, int EQ, bool SH, typename R>
+struct EqGrad {
+    const Ref<R>& rf;
+    __device__ __forceinline__ void operator()(int i, const Mac<R>& m, R& e, R g[4]) const
+    {
+        e = eq_s<DIM, EQ, SH, R>(i, rf, m);
+        eq_s_grad<DIM, EQ, SH, R>(i, m, g);
+    }
+};
+
+template <int DIM, int EQ, bool SH, typename R, typename HV, typename EG>
 __device__ __forceinline__ int newton_v(const HV& hv, uint32_t gamma_R_mask, R Rfac, const Ref<R>& rf, R tol,
-                                        int maxit, R& drho, R du[3])
+                                        int maxit, R& drho, R du[3], const EG& eqg)
 {
     constexpr int Q = Lat<DIM>::Q;
     constexpr int N = DIM + 1;
@@ -316,15 +327,15 @@ __device__ __forceinline__ int newton_v(const HV& hv, uint32_t gamma_R_mask, R R
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int c = 0; c < 4; ++c) J[r][c] = R(0);
-        // one direction at a time (the index is uniform): unrolled, the
-        // interleaved equilibria and gradients of all Q directions would set
+        // 3-D: one direction at a time (the index is uniform): unrolled, the
+        // interleaved equilibria and gradients of all 19 directions would set
         // the register count of the whole level kernel
-#pragma unroll 1
+        constexpr int UNROLL = DIM == 2 ? Q : 1;
+#pragma unroll UNROLL
         for (int i = 0; i < Q; ++i) {
             const R G = ((gamma_R_mask >> i) & 1u) ? Rfac : R(1);
-            const R e = eq_s<DIM, EQ, SH, R>(i, rf, m);
-            R g[4];
-            eq_s_grad<DIM, EQ, SH, R>(i, m, g);
+            R e, g[4];
+            eqg(i, m, e, g);
             const R d = G * (hv(i) - e);
             const R phi[4] = {R(1), R(cdir<DIM>(i, 0)), R(cdir<DIM>(i, 1)), R(cdir<DIM>(i, 2))};
 #pragma unroll

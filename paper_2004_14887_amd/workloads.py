@@ -304,3 +304,35 @@ def serving_requests(seed: int = 4, n: int = 256, max_levels: int = 3, min_side:
                              steps=steps, probes=probes, background=bg, vortices=vort, pulses=pulses, seed=seed))
     gaps = rng.exponential(1.0, size=n)
     return reqs, gaps
+
+
+def rings_4level(seed: int = 5, n0: int = 512, sides=(344, 476, 520), steps: int = 200, n_rings: int = 64,
+                 n_pulses: int = 8, tau0: float = 0.52) -> Workload:
+    """D3Q19, 4 levels: periodic n0^3 with three nested centred boxes (sides
+    in parent cells; the default 344 / 476 / 520 covers 30.3%, 10.0% and 1.64%
+    of the volume, about 193 GB of FP16 storage); seeded vortex rings
+    (radius U(8, 16), core radius/4, peak swirl U(0.05, 0.2) c_s, random axes,
+    no background) and Gaussian pulses (1e-3, half-width 6); 16 probes on a
+    sphere of radius 0.375 n0.  Replicas keep the layout with smaller n0 and
+    sides."""
+    rng = np.random.default_rng(seed)
+    boxes = []
+    ext = n0
+    for sd in sides:
+        lo = (ext - sd) // 2
+        boxes.append(((lo, lo, lo), (lo + sd, lo + sd, lo + sd)))
+        ext = 2 * sd
+    c = n0 / 2.0
+    scale = n0 / 512.0
+    rings = []
+    for _ in range(n_rings):
+        axis = rng.normal(size=3)
+        axis /= np.linalg.norm(axis)
+        R = float(rng.uniform(8.0, 16.0)) * max(scale, 0.25)
+        rings.append(dict(c=tuple(rng.uniform(0, n0, size=3)), axis=tuple(axis), R=R, core=R / 4.0,
+                          peak=float(rng.uniform(0.05, 0.2)) * CS))
+    pulses = [dict(c=tuple(rng.uniform(0, n0, size=3)), A=1e-3, Rc=6.0 * max(scale, 0.25))
+              for _ in range(n_pulses)]
+    probes = _sphere_probes((c, c, c), 0.375 * n0, 16)
+    return Workload(name=f"rings_4level_{n0}", lattice="D3Q19", n0=(n0, n0, n0), boxes=boxes, tau0=tau0,
+                    steps=steps, probes=probes, rings=rings, pulses=pulses, seed=seed)
