@@ -239,6 +239,56 @@ def test_fp32_3d_ring_with_background_flow_within_1e_4():
     assert e <= 1e-4
 
 
+@requires_gpu
+@pytest.mark.parametrize("lattice,n0", [("D2Q9", (70, 53)), ("D3Q19", (20, 17, 13))])
+def test_single_level_periodic_fp64_parity(lattice, n0):
+    """One periodic level (the plain scheme the refined step reduces to), on
+    ragged sizes that leave partial 64 x 4 tiles: every population against
+    the oracle after 10 steps."""
+    wl = W.Workload(name=f"single_{lattice}", lattice=lattice, n0=n0, boxes=[], tau0=0.6, steps=10,
+                    pulses=[dict(c=tuple(v / 2.0 for v in n0) + (0.0,) * (3 - len(n0)), A=1e-3, Rc=3.0)],
+                    background=(0.02, -0.01, 0.005)[:len(n0)] + (0.0,) * (3 - len(n0)))
+    sim = gpu_run(wl, wl.steps)
+    sim.check()
+    assert_population_parity(sim, oracle_run(wl, wl.steps), wl)
+
+
+@requires_gpu
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+def test_smallest_legal_box_fp64_parity(lattice):
+    """The smallest legal refinement: an 8-node periodic level 0 and a box of
+    3 parent cells at the minimum margin of 2 (7 fine nodes per axis, so every
+    hanging node uses the one-sided line-end stencil)."""
+    D = 2 if lattice == "D2Q9" else 3
+    wl = W.Workload(name=f"smallest_{lattice}", lattice=lattice, n0=(8,) * D,
+                    boxes=[((2,) * D, (5,) * D)], tau0=0.58, steps=20,
+                    pulses=[dict(c=(3.5, 3.5, 3.5 if D == 3 else 0.0), A=1e-3, Rc=1.5)],
+                    background=(0.03, 0.01, -0.02)[:D] + (0.0,) * (3 - D), probes=[(3,) * D, (6,) * D])
+    sim = gpu_run(wl, wl.steps)
+    sim.check()
+    o = oracle_run(wl, wl.steps)
+    assert_population_parity(sim, o, wl)
+    assert np.abs(sim.probes().cpu().numpy() - o.probes()).max() <= 1e-15
+
+
+@requires_gpu
+def test_zero_steps_and_no_probes():
+    """Degenerate calls: zero coarse steps leave the initial state, a
+    configuration without probes steps and reports an empty series."""
+    wl = W.vortex_2level(seed=1, n0=64, steps=4)
+    wl.probes = []
+    from paper_2004_14887_amd.sim import Simulation
+    sim = Simulation(wl, "fp64", probe_capacity=1)
+    sim.init_from_workload()
+    f0 = sim.populations(1).cpu().numpy()
+    sim.step(0)
+    assert np.array_equal(sim.populations(1).cpu().numpy(), f0, equal_nan=True)
+    sim.step(4)
+    sim.check()
+    assert sim.probes().shape[0] == 0 or sim.probes().numel() == 0
+    assert_population_parity(sim, oracle_run(wl, 4), wl)
+
+
 def _four_level_replica(steps, n0=32):
     # the 4-level 512^3 nesting at n0 = 32: centred boxes of 22, 30, 32 parent cells
     return W.rings_4level(seed=5, n0=n0, sides=(22, 30, 32), steps=steps, n_rings=4, n_pulses=2)
