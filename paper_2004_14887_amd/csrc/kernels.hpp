@@ -369,7 +369,10 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
         auto hv = [&](int i) -> R { return col[i * TFM]; };
         R drho, du[3];
         int it;
-        if constexpr (SH && EQ == 2)
+        // the constants table is indexed by a loop counter only in 3-D, where
+        // the Newton loop is not unrolled; a dynamic index into the serving
+        // kernel's register copy of the arguments would put it in scratch
+        if constexpr (SH && EQ == 2 && DIM == 2)
             it = newton_v<DIM, EQ, SH, R>(hv, gR, R(a.Rfac), rf, R(a.tol), a.maxit, drho, du,
                                           EqGradShift2<DIM, R>{a.g});
         else

@@ -171,3 +171,28 @@ def test_server_rejects_what_it_cannot_serve():
         srv.submit(two_level, steps=10)
     assert ei.value.status == -1
     srv.close()
+
+
+@requires_gpu
+def test_serving_d3q19_equals_single_simulation():
+    """A D3Q19 FP32 server (2-level meshes of different sizes, background
+    flows): each served request equals the same workload stepped alone
+    through the single-simulation entry points, bit for bit."""
+    from paper_2004_14887_amd.server import Server
+    from paper_2004_14887_amd.sim import Simulation
+    reqs = [W.pulse_ring_3d(seed=s, n0=n0, steps=st) for s, n0, st in ((3, 32, 12), (4, 48, 7), (5, 40, 10))]
+    srv = Server(1 << 30, lattice="D3Q19", precision="fp32", max_levels=2, max_slots=2, steps_per_tick=3,
+                 max_probes=16, max_probe_steps=64, max_level_nodes=100 ** 3)
+    ids = [srv.submit(r) for r in reqs]
+    srv.drain()
+    for k, r in enumerate(reqs):
+        assert srv.poll(ids[k]) == "done"
+        got = srv.result(ids[k])[0]
+        sim = Simulation(r, "fp32", probe_capacity=r.steps)
+        sim.init_from_workload()
+        sim.step(r.steps)
+        sim.check()
+        ref = sim.probes().cpu().numpy()
+        sim.close()
+        assert np.array_equal(got, ref), f"request {k}: max diff {np.abs(got - ref).max()}"
+    srv.close()
