@@ -26,6 +26,7 @@
 //             rows per XCD, rows interleaved over the 8 XCDs.
 // Plus initialisation, conversion, probe and balance kernels.
 #pragma once
+#include <type_traits>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -324,8 +325,9 @@ __device__ __forceinline__ void role_capture(const LevelArgs& a, int b)
     }
 }
 
-template <int DIM, int EQ, int P>
-__device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typename Form<P>::R* lds)
+template <int DIM, int EQ, int P, bool ROLLED>
+__device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typename Form<P>::R* lds,
+                                             std::bool_constant<ROLLED> = {})
 {
     using F = Form<P>;
     using T = typename F::T;
@@ -369,15 +371,15 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
         auto hv = [&](int i) -> R { return col[i * TFM]; };
         R drho, du[3];
         int it;
-        // the constants table is indexed by a loop counter only in 3-D, where
-        // the Newton loop is not unrolled; a dynamic index into the serving
-        // kernel's register copy of the arguments would put it in scratch
-        if constexpr (SH && EQ == 2 && DIM == 2)
-            it = newton_v<DIM, EQ, SH, R>(hv, gR, R(a.Rfac), rf, R(a.tol), a.maxit, drho, du,
-                                          EqGradShift2<DIM, R>{a.g});
+        // the constants table is only used where the Newton loop is unrolled:
+        // a loop-counter index into the serving kernel's register copy of the
+        // arguments would put that copy in scratch
+        if constexpr (SH && EQ == 2 && !ROLLED)
+            it = newton_v<DIM, EQ, SH, R, decltype(hv), EqGradShift2<DIM, R>, ROLLED>(
+                hv, gR, R(a.Rfac), rf, R(a.tol), a.maxit, drho, du, EqGradShift2<DIM, R>{a.g});
         else
-            it = newton_v<DIM, EQ, SH, R>(hv, gR, R(a.Rfac), rf, R(a.tol), a.maxit, drho, du,
-                                          EqGrad<DIM, EQ, SH, R>{rf});
+            it = newton_v<DIM, EQ, SH, R, decltype(hv), EqGrad<DIM, EQ, SH, R>, ROLLED>(
+                hv, gR, R(a.Rfac), rf, R(a.tol), a.maxit, drho, du, EqGrad<DIM, EQ, SH, R>{rf});
         if (it < 0) {
             if (owned) atomicOr(a.flags, 1);
             R jj[3] = {R(0), R(0), R(0)};
@@ -558,7 +560,9 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
 // on XCD b' % 8 as TileMap assumes.  Every thread of the workgroup calls
 // this with the same arguments (the segment role synchronises).
 // Returns true when the workgroup used the LDS (segment role).
-template <int DIM, int EQ, int P>
+// ROLLED: Newton one direction at a time (3-D, and the serving kernel, whose
+// register budget the unrolled loop would set).
+template <int DIM, int EQ, int P, bool ROLLED = (DIM == 3)>
 __device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename Form<P>::R* lds)
 {
     if (b < a.nb_cap) {
@@ -570,7 +574,7 @@ __device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename 
     if (j < a.seg_groups && r < 8) {
         const int sg = 8 * j + r;
         if (sg < a.nb_seg) {
-            role_segment<DIM, EQ, P>(a, sg, lds);
+            role_segment<DIM, EQ, P, ROLLED>(a, sg, lds);
             return true;
         }
         return false;
@@ -811,7 +815,7 @@ __global__ __launch_bounds__(kBlock) void k_level_multi(MultiArgs m)
             // only a segment iteration leaves LDS behind; a barrier after
             // every iteration would also wait for each tile's stores.  Every
             // wave runs the same iterations, so the barriers still pair up.
-            if (level_block<DIM, EQ, P>(a, v - begin[lo], lds)) __syncthreads();
+            if (level_block<DIM, EQ, P, true>(a, v - begin[lo], lds)) __syncthreads();
         }
     }
 }

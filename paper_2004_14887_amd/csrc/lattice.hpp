@@ -302,7 +302,7 @@ struct EqGrad {
     }
 };
 
-template <int DIM, int EQ, bool SH, typename R, typename HV, typename EG>
+template <int DIM, int EQ, bool SH, typename R, typename HV, typename EG, bool ROLLED = (DIM == 3)>
 __device__ __forceinline__ int newton_v(const HV& hv, uint32_t gamma_R_mask, R Rfac, const Ref<R>& rf, R tol,
                                         int maxit, R& drho, R du[3], const EG& eqg)
 {
@@ -327,10 +327,11 @@ __device__ __forceinline__ int newton_v(const HV& hv, uint32_t gamma_R_mask, R R
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int c = 0; c < 4; ++c) J[r][c] = R(0);
-        // 3-D: one direction at a time (the index is uniform): unrolled, the
-        // interleaved equilibria and gradients of all 19 directions would set
-        // the register count of the whole level kernel
-        constexpr int UNROLL = DIM == 2 ? Q : 1;
+        // ROLLED (3-D, and the serving kernel): one direction at a time (the
+        // index is uniform): unrolled, the interleaved equilibria and
+        // gradients of all directions would set the register count of the
+        // whole level kernel
+        constexpr int UNROLL = ROLLED ? 1 : Q;
 #pragma unroll UNROLL
         for (int i = 0; i < Q; ++i) {
             const R G = ((gamma_R_mask >> i) & 1u) ? Rfac : R(1);

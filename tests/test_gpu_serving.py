@@ -5,7 +5,8 @@ many simulations through the C ABI.
   requests arrive while others run, queue for slots and memory, and share
   every launch with whatever else is resident.
 * A served request equals the same workload stepped alone through the
-  single-simulation entry points.
+  single-simulation entry points (within the FP32 form's own error in 2-D,
+  bit for bit in 3-D, where both kernels order Newton alike).
 * FP64 serving matches the FP64 oracle.
 * Admission never exceeds the arena: requests wait for memory and slots,
   and all complete.
@@ -81,21 +82,40 @@ def test_serving_alone_equals_mix():
 
 @requires_gpu
 def test_serving_equals_single_simulation():
+    """A served FP32 request against the same workload stepped alone through
+    the single-simulation entry points.  In 2-D the two kernels order the
+    Newton loop differently (rolled in the serving kernel, for its register
+    budget); FP32 Newton stops at |dX| < 2e-6, so the two may stop one
+    iteration apart and agree only within the FP32 form's own error: their
+    difference must stay within twice the single path's error against the
+    FP64 path (and is often zero)."""
     from paper_2004_14887_amd.sim import Simulation
     reqs = small_requests(n=6)
     srv = make_server(max_slots=6, steps_per_tick=2)
     ids = [srv.submit(r) for r in reqs]
     res = drain_all(srv, ids)
     srv.close()
-    for k, r in enumerate(reqs):
-        print(f"[gpu] single {r.name} steps={r.steps}", flush=True)
-        sim = Simulation(r, "fp32", probe_capacity=r.steps)
+
+    def single(r, prec):
+        sim = Simulation(r, prec, probe_capacity=r.steps)
         sim.init_from_workload()
         sim.step(r.steps)
         sim.check()
-        ref = sim.probes().cpu().numpy()
+        p = sim.probes().cpu().numpy()
         sim.close()
-        assert np.array_equal(res[ids[k]][0], ref), f"request {k}: max diff {np.abs(res[ids[k]][0] - ref).max()}"
+        return p
+
+    for k, r in enumerate(reqs):
+        print(f"[gpu] single {r.name} steps={r.steps}", flush=True)
+        ref32, ref64 = single(r, "fp32"), single(r, "fp64")
+        got = res[ids[k]][0]
+        peak = max(np.abs(ref64).max(), 1e-30)
+        d = float(np.abs(got - ref32).max() / peak)
+        e32 = float(np.abs(ref32 - ref64).max() / peak)
+        e_srv = float(np.abs(got - ref64).max() / peak)
+        print(f"  {r.name}: served vs single {d:.2e}; vs FP64: single {e32:.2e}, served {e_srv:.2e}", flush=True)
+        assert d <= max(2.0 * e32, 1e-6), f"request {k}"
+        assert e_srv <= max(2.0 * e32, 1e-6), f"request {k}"
 
 
 @requires_gpu
@@ -177,7 +197,8 @@ def test_server_rejects_what_it_cannot_serve():
 def test_serving_d3q19_equals_single_simulation():
     """A D3Q19 FP32 server (2-level meshes of different sizes, background
     flows): each served request equals the same workload stepped alone
-    through the single-simulation entry points, bit for bit."""
+    through the single-simulation entry points, bit for bit (in 3-D both
+    kernels run the same Newton loop)."""
     from paper_2004_14887_amd.server import Server
     from paper_2004_14887_amd.sim import Simulation
     reqs = [W.pulse_ring_3d(seed=s, n0=n0, steps=st) for s, n0, st in ((3, 32, 12), (4, 48, 7), (5, 40, 10))]
