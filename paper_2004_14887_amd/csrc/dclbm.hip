@@ -88,7 +88,13 @@ LevelArgs level_args(const Sim& s, int l, int substep, int first, unsigned* grid
     // launch's tail (spreading them over the grid measured slower).
     a.seg_groups = (a.nb_seg + 7) / 8;
     a.seg_period = 8;
-    *grid = (unsigned)(a.nb_cap + 8 * a.seg_groups + 8 * a.tm.per);
+    if (l == 0) {
+        a.nb_probe = 1;
+        a.probe = s.d_probe_args + L.parity;
+        a.series = s.d_series;
+        a.counter = s.d_counter;
+    }
+    *grid = (unsigned)(a.nb_probe + a.nb_cap + 8 * a.seg_groups + 8 * a.tm.per);
     return a;
 }
 
@@ -137,7 +143,7 @@ struct EngineImpl final : Engine {
     }
     void probe(Sim& s) override
     {
-        if (s.probes.empty()) return;
+        // the pending sample of the last coarse step (a no-op if none)
         const ProbeArgs a = probe_args(s);
         hipLaunchKernelGGL((k_probe<DIM, P>), dim3(1), dim3(64), 0, s.stream, a, s.d_series, s.d_counter);
     }
@@ -579,7 +585,8 @@ dclbm_status build_geometry(Sim& s)
         }
     }
     s.off_series = take(std::max<int64_t>(1, c.probe_capacity) * std::max(1, c.n_probes) * 8);
-    s.off_counter = take(8);
+    s.off_counter = take(16);
+    s.off_probe_args = take(2 * (int64_t)sizeof(ProbeArgs));
     s.off_flags = take(8);
     s.off_partial = take((int64_t)DCLBM_MAX_LEVELS * s.partial_blocks * 5 * 8);
     s.off_bal = take(DCLBM_MAX_LEVELS * 5 * 8);
@@ -620,12 +627,25 @@ dclbm_status sim_attach(Sim& s, void* d_workspace, size_t bytes, hipStream_t str
     }
     s.d_series = s.at<double>(s.off_series);
     s.d_counter = s.at<int64_t>(s.off_counter);
+    s.d_probe_args = s.at<ProbeArgs>(s.off_probe_args);
+    {
+        // probe buffers for either parity of level 0 (finer levels start every
+        // coarse step at parity 0)
+        const int p0 = s.lv[0].parity;
+        s.h_probe_args.resize(2);
+        for (int par = 0; par < 2; ++par) {
+            s.lv[0].parity = par;
+            s.h_probe_args[par] = probe_args(s);
+        }
+        s.lv[0].parity = p0;
+        HIPCHECK(upload(s, s.d_probe_args, s.h_probe_args));
+    }
     s.d_flags = s.at<int>(s.off_flags);
     s.d_partial = s.at<double>(s.off_partial);
     s.d_bal = s.at<double>(s.off_bal);
     s.eng.reset(make_engine(s.D, s.EQ, s.P));
     s.eng->fill_nan(s);
-    hipLaunchKernelGGL((k_fill<int64_t>), dim3(1), dim3(64), 0, s.stream, s.d_counter, (int64_t)1, (int64_t)0);
+    hipLaunchKernelGGL((k_fill<int64_t>), dim3(1), dim3(64), 0, s.stream, s.d_counter, (int64_t)2, (int64_t)0);
     hipLaunchKernelGGL((k_fill<int>), dim3(1), dim3(64), 0, s.stream, s.d_flags, (int64_t)2, 0);
     HIPCHECK(hipGetLastError());
     return DCLBM_OK;
@@ -677,10 +697,11 @@ static void advance_state(Sim& s)
     s.lv[0].parity ^= 1;
 }
 
+// The probes of a step are sampled by the next step's level-0 launch, or by
+// the flush before they are read.
 static void one_coarse_step(Sim& s)
 {
     advance(s, 0, 0);
-    s.eng->probe(s);
 }
 
 static dclbm_status coarse_step_eager(Sim& s)
@@ -790,6 +811,7 @@ dclbm_status dclbm_create(const dclbm_config* cfg, void* d_workspace, size_t byt
         s.need_bytes = tmp.need_bytes;
         s.off_series = tmp.off_series;
         s.off_counter = tmp.off_counter;
+        s.off_probe_args = tmp.off_probe_args;
         s.off_flags = tmp.off_flags;
         s.off_partial = tmp.off_partial;
         s.off_bal = tmp.off_bal;
@@ -917,6 +939,8 @@ dclbm_status dclbm_read_probes(const dclbm_sim* sim, double* d_out, int64_t* n_s
 {
     if (!sim || !n_steps) return fail(DCLBM_ERR_INVALID, "null argument");
     Sim& s = const_cast<Sim&>(sim->s);
+    s.eng->probe(s);
+    HIPCHECK(hipGetLastError());
     int64_t cnt = 0;
     HIPCHECK(hipMemcpyAsync(&cnt, s.d_counter, 8, hipMemcpyDeviceToHost, s.stream));
     HIPCHECK(hipStreamSynchronize(s.stream));

@@ -124,9 +124,11 @@ struct Sim {
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     size_t ws_bytes = 0, need_bytes = 0;
-    int64_t off_series = 0, off_counter = 0, off_flags = 0, off_partial = 0, off_bal = 0;
+    int64_t off_series = 0, off_counter = 0, off_flags = 0, off_partial = 0, off_bal = 0, off_probe_args = 0;
     double* d_series = nullptr;
-    int64_t* d_counter = nullptr;
+    int64_t* d_counter = nullptr;     // [0] steps sampled by the probes, [1] coarse steps started
+    ProbeArgs* d_probe_args = nullptr; // [2] by level-0 parity
+    std::vector<ProbeArgs> h_probe_args;
     int* d_flags = nullptr;
     double* d_partial = nullptr;
     double* d_bal = nullptr;

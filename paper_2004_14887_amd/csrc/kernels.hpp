@@ -250,6 +250,13 @@ struct TileMap {
     int per;         // workgroups per XCD: tx * ceil(nrows / 8)
 };
 
+struct ProbeArgs {
+    int n;
+    int64_t capacity;
+    const void* buf[32];   // storage buffer holding the probe's node
+    int64_t off[32];       // element offset of direction 0 of that node (directions 64 apart)
+};
+
 struct LevelArgs {
     LevelDev g;
     const void* src;
@@ -285,6 +292,13 @@ struct LevelArgs {
     void* dst_parent;
     const int4* tfc_meta; // parent coordinates of each co-located node (same order)
     double keep_parent;
+    // level 0 of a single simulation: one extra workgroup samples the probes
+    // of the previous coarse step (this launch only reads level 0's state and
+    // does not touch the finer levels), so a step needs no probe launch
+    int nb_probe;           // 0 or 1
+    const ProbeArgs* probe; // the probe buffers of the state this launch starts from
+    double* series;
+    int64_t* counter;       // [0] steps sampled, [1] coarse steps started
 };
 
 template <int DIM, int P>
@@ -553,6 +567,33 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
     for (int i = 0; i < Q; ++i) F::store(d + i * 64, s[i]);
 }
 
+// p' = (rho - 1)/3 in FP64 of every probe (thread p), appended to the series
+// at row *counter; thread 0 then advances the counter.  One workgroup.
+template <int DIM, int P>
+__device__ __forceinline__ void probe_sample(const ProbeArgs& a, double* series, int64_t* counter)
+{
+    using F = Form<P>;
+    constexpr int Q = Lat<DIM>::Q;
+    const int64_t step = *counter;
+    const int p = threadIdx.x;
+    if (p < a.n && step < a.capacity) {
+        const typename F::T* b = reinterpret_cast<const typename F::T*>(a.buf[p]) + a.off[p];
+        double r = F::rho0;
+        for (int i = 0; i < Q; ++i) r += (double)F::load(b + i * 64);
+        series[step * a.n + p] = (r - 1.0) / 3.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *counter = step + 1;
+}
+
+// Probes of a finished coarse step not sampled yet (counter[0] < counter[1]).
+template <int DIM, int P>
+__device__ __forceinline__ void probe_pending(const ProbeArgs& pa, double* series, int64_t* counter)
+{
+    const int64_t done = counter[0], started = counter[1];
+    if (done < started) probe_sample<DIM, P>(pa, series, counter);
+}
+
 // Workgroup b of a level substep.  Grid order: the capture workgroups, then
 // the interface-segment workgroups in groups of 8 (one per XCD) every
 // seg_period workgroups, bulk tiles in between (seg_period = 8 puts every
@@ -565,6 +606,15 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
 template <int DIM, int EQ, int P, bool ROLLED = (DIM == 3)>
 __device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename Form<P>::R* lds)
 {
+    if (b < a.nb_probe) {
+        // sample the previous step, then count this one as started
+        const int64_t started = a.counter[1];
+        probe_pending<DIM, P>(*a.probe, a.series, a.counter);
+        __syncthreads();
+        if (threadIdx.x == 0) a.counter[1] = started + 1;
+        return false;
+    }
+    b -= a.nb_probe;
     if (b < a.nb_cap) {
         role_capture<DIM, P>(a, b);
         return false;
@@ -708,37 +758,14 @@ static __global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__
 }
 
 // ---------------------------------------------------------------- probes
-struct ProbeArgs {
-    int n;
-    int64_t capacity;
-    const void* buf[32];   // storage buffer holding the probe's node
-    int64_t off[32];       // element offset of direction 0 of that node (directions 64 apart)
-};
 
-// p' = (rho - 1)/3 in FP64 of every probe (thread p), appended to the series
-// at row *counter; thread 0 then advances the counter.  One workgroup.
-template <int DIM, int P>
-__device__ __forceinline__ void probe_sample(const ProbeArgs& a, double* series, int64_t* counter)
-{
-    using F = Form<P>;
-    constexpr int Q = Lat<DIM>::Q;
-    const int64_t step = *counter;
-    const int p = threadIdx.x;
-    if (p < a.n && step < a.capacity) {
-        const typename F::T* b = reinterpret_cast<const typename F::T*>(a.buf[p]) + a.off[p];
-        double r = F::rho0;
-        for (int i = 0; i < Q; ++i) r += (double)F::load(b + i * 64);
-        series[step * a.n + p] = (r - 1.0) / 3.0;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *counter = step + 1;
-}
-
+// Standalone: the pending sample of the last coarse step (before the probes
+// are read).
 template <int DIM, int P>
 __global__ __launch_bounds__(64) void k_probe(ProbeArgs a, double* __restrict__ series,
                                               int64_t* __restrict__ counter)
 {
-    probe_sample<DIM, P>(a, series, counter);
+    probe_pending<DIM, P>(a, series, counter);
 }
 
 // ---------------------------------------------------------------- serving

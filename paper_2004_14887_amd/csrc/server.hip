@@ -355,6 +355,7 @@ dclbm_status admit(Server& sv, Request& r, int k, size_t off)
             if (next >= rec.size() || rec[next].level != sv.phases[p].first || rec[next].substep != sv.phases[p].second)
                 return fail(DCLBM_ERR_INVALID, "internal: phase order mismatch");
             ha[(size_t)var * sv.NPH + p] = rec[next].args;
+            ha[(size_t)var * sv.NPH + p].nb_probe = 0;   // the tail launch samples the probes
             ++next;
         }
     }
