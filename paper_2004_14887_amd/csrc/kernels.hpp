@@ -39,6 +39,10 @@ namespace dclbm {
 // P = 0: FP64, carried value s = f.
 // P = 1: FP32 arithmetic, stored s = f - w (deviation from rest).
 // P = 2: FP32 arithmetic, stored FP16(256 (f - w)).
+// Storage forms: load / store of the carried variable.  The bulk streams
+// with nontemporal stores; interface nodes, whose stores on some faces cover
+// a few bytes of each cache line, store through the cache (store_wb) so that
+// partial lines can merge before they are written back.
 template <int P>
 struct Form;
 template <>
@@ -49,6 +53,7 @@ struct Form<0> {
     static constexpr bool shifted = false;
     __device__ static __forceinline__ R load(const T* p) { return *p; }
     __device__ static __forceinline__ void store(T* p, R v) { __builtin_nontemporal_store(v, p); }
+    __device__ static __forceinline__ void store_wb(T* p, R v) { *p = v; }
     __device__ static __forceinline__ T nan() { return __builtin_nan(""); }
 };
 template <>
@@ -59,6 +64,7 @@ struct Form<1> {
     static constexpr bool shifted = true;
     __device__ static __forceinline__ R load(const T* p) { return *p; }
     __device__ static __forceinline__ void store(T* p, R v) { __builtin_nontemporal_store(v, p); }
+    __device__ static __forceinline__ void store_wb(T* p, R v) { *p = v; }
     __device__ static __forceinline__ T nan() { return __builtin_nanf(""); }
 };
 template <>
@@ -77,6 +83,10 @@ struct Form<2> {
     {
         const unsigned short b = __half_as_ushort(__float2half_rn(v * scale));
         __builtin_nontemporal_store(b, reinterpret_cast<unsigned short*>(p));
+    }
+    __device__ static __forceinline__ void store_wb(T* p, R v)
+    {
+        *reinterpret_cast<unsigned short*>(p) = __half_as_ushort(__float2half_rn(v * scale));
     }
     __device__ static __forceinline__ T nan() { return __ushort_as_half((unsigned short)0x7e00); }
 };
@@ -442,14 +452,14 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
                 for (int i = 0; i < Q; ++i) {
                     const R e0 = eq0(i);
                     const R c = e0 + invR * (col[i * TFM] - e0);
-                    F::store(dp + eoff<DIM>(a.gp, i, pm.x, pm.y, pm.z), e0 + keepp * (c - e0));
+                    F::store_wb(dp + eoff<DIM>(a.gp, i, pm.x, pm.y, pm.z), e0 + keepp * (c - e0));
                 }
             }
             const R keep = R(a.keep);
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const R e0 = eq0(i);
-                F::store(dst + eoff<DIM>(a.g, i, m.x, m.y, m.z), e0 + keep * (col[i * TFM] - e0));
+                F::store_wb(dst + eoff<DIM>(a.g, i, m.x, m.y, m.z), e0 + keep * (col[i * TFM] - e0));
             }
         }
     }
@@ -500,7 +510,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
         velocity<DIM, SH, R>(rf, drho, jj, du);
         bgk<DIM, EQ, SH, R>(s, rf, make_mac<DIM, SH, R>(rf, drho, du), R(a.keep));
 #pragma unroll
-        for (int i = 0; i < Q; ++i) F::store(dst + eoff<DIM>(a.g, i, m.x, m.y, m.z), s[i]);
+        for (int i = 0; i < Q; ++i) F::store_wb(dst + eoff<DIM>(a.g, i, m.x, m.y, m.z), s[i]);
     }
 }
 
