@@ -87,7 +87,6 @@ LevelArgs level_args(const Sim& s, int l, int substep, int first, unsigned* grid
     // the bulk tiles that start behind them, and none of it lands in the
     // launch's tail (spreading them over the grid measured slower).
     a.seg_groups = (a.nb_seg + 7) / 8;
-    a.seg_period = 8;
     if (l == 0) {
         a.nb_probe = 1;
         a.probe = s.d_probe_args + L.parity;

@@ -9,7 +9,8 @@
 // in one contiguous span, which keeps the pull stream's 3^D neighbouring row
 // blocks in few DRAM pages and translation entries.
 //
-// One launch per level substep (k_level) runs three kinds of workgroups:
+// One launch per level substep (k_level) runs these kinds of workgroups:
+//   probe     (level 0 only) samples the probes of the previous coarse step;
 //   capture   coarse co-located nodes store their streamed populations in a
 //             3-deep history ring (the input of Eq.(TempInt));
 //   segment   one tile of the fine interface line/face: Newton for the shared
@@ -24,7 +25,9 @@
 //   bulk      fused pull-stream + BGK of every other node (Eq.(LBMequation),
 //             Eq.(LBMscheme_reg) with BGK), 64 x 4 node tiles, whole tile
 //             rows per XCD, rows interleaved over the 8 XCDs.
-// Plus initialisation, conversion, probe and balance kernels.
+// The serving kernels (k_level_multi, k_server_tail) run the same workgroups
+// for many resident simulations from device work tables.  Plus
+// initialisation, conversion, probe and balance kernels.
 #pragma once
 #include <type_traits>
 #include <hip/hip_fp16.h>
@@ -274,8 +277,7 @@ struct LevelArgs {
     double keep;          // 1 - 1/tau_l
     TileMap tm;
     int nb_cap, nb_seg;   // workgroups of the capture and segment roles
-    int seg_groups;       // ceil(nb_seg / 8)
-    int seg_period;       // a group of 8 segment workgroups opens every seg_period workgroups
+    int seg_groups;       // ceil(nb_seg / 8): segment workgroups are padded to a multiple of 8
     // capture (level has a child): coarse co-located nodes of this level
     const int4* cap_meta; // (x, y, z, K^c mask)
     int n_cap;
@@ -604,15 +606,16 @@ __device__ __forceinline__ void probe_pending(const ProbeArgs& pa, double* serie
     if (done < started) probe_sample<DIM, P>(pa, series, counter);
 }
 
-// Workgroup b of a level substep.  Grid order: the capture workgroups, then
-// the interface-segment workgroups in groups of 8 (one per XCD) every
-// seg_period workgroups, bulk tiles in between (seg_period = 8 puts every
-// segment before the first bulk tile).  Groups of 8 keep bulk workgroup b'
-// on XCD b' % 8 as TileMap assumes.  Every thread of the workgroup calls
-// this with the same arguments (the segment role synchronises).
-// Returns true when the workgroup used the LDS (segment role).
-// ROLLED: Newton one direction at a time (3-D, and the serving kernel, whose
-// register budget the unrolled loop would set).
+// Workgroup b of a level substep.  Grid order: the probe workgroup (level 0
+// of a single simulation), the capture workgroups, the interface segments
+// (padded to a multiple of 8), then the bulk tiles.  Segment work is
+// latency-bound (Newton, gathers) and bulk work bandwidth-bound: placed first,
+// the segments overlap the bulk tiles that start behind them and stay out of
+// the launch's tail (spreading them over the grid, or placing them after the
+// bulk rows they touch, measured slower).  The padding keeps bulk workgroup
+// b' on XCD b' % 8 up to a fixed rotation, as TileMap assumes.  Every thread
+// of the workgroup calls this with the same arguments (the segment role
+// synchronises).  Returns true when the workgroup used the LDS (segment role).
 template <int DIM, int EQ, int P, bool ROLLED = (DIM == 3)>
 __device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename Form<P>::R* lds)
 {
@@ -630,17 +633,15 @@ __device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename 
         return false;
     }
     const int b2 = b - a.nb_cap;
-    const int j = b2 / a.seg_period, r = b2 - j * a.seg_period;
-    if (j < a.seg_groups && r < 8) {
-        const int sg = 8 * j + r;
-        if (sg < a.nb_seg) {
-            role_segment<DIM, EQ, P, ROLLED>(a, sg, lds);
+    const int nseg = 8 * a.seg_groups;
+    if (b2 < nseg) {
+        if (b2 < a.nb_seg) {
+            role_segment<DIM, EQ, P, ROLLED>(a, b2, lds);
             return true;
         }
         return false;
     }
-    const int before = 8 * (j < a.seg_groups ? j + 1 : a.seg_groups);
-    role_bulk<DIM, EQ, P>(a, b2 - before);
+    role_bulk<DIM, EQ, P>(a, b2 - nseg);
     return false;
 }
 
