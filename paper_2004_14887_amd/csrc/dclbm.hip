@@ -50,6 +50,7 @@ LevelArgs level_args(const Sim& s, int l, int substep, int first, unsigned* grid
     memset(&a, 0, sizeof(a));
     a.g = L.dev();
     a.src = L.f[L.parity];
+    a.par = L.parity;
     a.dst = L.f[L.parity ^ 1];
     a.keep = 1.0 - 1.0 / L.tau;
     a.tm = L.tiles();
@@ -104,9 +105,17 @@ ProbeArgs probe_args(const Sim& s)
     a.n = (int)s.probes.size();
     a.capacity = s.cfg.probe_capacity;
     for (int p = 0; p < a.n; ++p) {
-        const HostLevel& L = s.lv[s.probes[p].level];
-        a.buf[p] = L.f[L.parity];
-        a.off[p] = s.probes[p].off;
+        const ProbeLoc& pl = s.probes[p];
+        const HostLevel& L = s.lv[pl.level];
+        if (L.xface && (pl.x == 0 || pl.x == L.nx - 1)) {
+            a.buf[p] = L.xf[L.parity];
+            a.off[p] = ((int64_t)(pl.x == 0 ? 0 : 1) * s.Q * L.nz + pl.z) * L.ny + pl.y;
+            a.stride[p] = (int64_t)L.nz * L.ny;
+        } else {
+            a.buf[p] = L.f[L.parity];
+            a.off[p] = pl.off;
+            a.stride[p] = 64;
+        }
     }
     return a;
 }
@@ -150,7 +159,7 @@ struct EngineImpl final : Engine {
     {
         HostLevel& L = s.lv[l];
         hipLaunchKernelGGL((k_init<DIM, EQ, P>), dense_grid(L), dim3(64, 4, 1), 0, s.stream, L.dev(),
-                           (T*)L.f[L.parity], rho, u);
+                           (T*)L.f[L.parity], L.parity, rho, u);
     }
     void ring_init(Sim& s, int l) override
     {
@@ -169,8 +178,11 @@ struct EngineImpl final : Engine {
             } else {
                 nanv = (T)NAN;
             }
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < 2; ++b) {
                 hipLaunchKernelGGL((k_fill<T>), dim3(2048), dim3(256), 0, s.stream, (T*)L.f[b], L.elems, nanv);
+                if (L.xface)
+                    hipLaunchKernelGGL((k_fill<T>), dim3(256), dim3(256), 0, s.stream, (T*)L.xf[b], L.xf_elems, nanv);
+            }
             if (L.X)
                 hipLaunchKernelGGL((k_fill<R>), dim3(256), dim3(256), 0, s.stream, (R*)L.X,
                                    4 * (int64_t)L.tf_meta.size(), (R)NAN);
@@ -183,7 +195,7 @@ struct EngineImpl final : Engine {
     {
         HostLevel& L = s.lv[l];
         hipLaunchKernelGGL((k_read<DIM, EQ, P>), dense_grid(L), dim3(64, 4, 1), 0, s.stream, L.dev(),
-                           (const T*)L.f[L.parity], f, rho, u);
+                           (const T*)L.f[L.parity], L.parity, f, rho, u);
     }
     void read_shared(Sim& s, int l, double* out) override
     {
@@ -200,7 +212,7 @@ struct EngineImpl final : Engine {
         HostLevel& L = s.lv[l];
         const double vol = std::ldexp(1.0, -DIM * l);
         hipLaunchKernelGGL((k_balance<DIM, EQ, P>), dim3(nblocks), dim3(256), 0, s.stream, L.dev(),
-                           (const T*)L.f[L.parity], vol, partial, s.d_flags);
+                           (const T*)L.f[L.parity], L.parity, vol, partial, s.d_flags);
     }
     void launch_multi(hipStream_t st, const MultiArgs& m, unsigned grid) override
     {
@@ -541,7 +553,7 @@ dclbm_status build_geometry(Sim& s)
             fine[a] = (int64_t)v << Lm;   // in units of the finest spacing
         }
         int64_t org[3] = {0, 0, 0};
-        ProbeLoc best{0, 0};
+        ProbeLoc best{0, 0, 0, 0, 0};
         for (int l = 0; l <= Lm; ++l) {
             if (l > 0)
                 for (int a = 0; a < D; ++a) org[a] += (int64_t)s.lv[l].plo[a] << (Lm - l + 1);
@@ -554,7 +566,7 @@ dclbm_status build_geometry(Sim& s)
                 if (d < 0 || (d >> sh) > n[a] - 1 || (d & ((1LL << sh) - 1))) inside = false;
                 else k[a] = (int)(d >> sh);
             }
-            if (inside) best = ProbeLoc{l, s.lv[l].elem0(Q, k[0], k[1], k[2])};
+            if (inside) best = ProbeLoc{l, s.lv[l].elem0(Q, k[0], k[1], k[2]), k[0], k[1], k[2]};
         }
         s.probes.push_back(best);
     }
@@ -567,6 +579,12 @@ dclbm_status build_geometry(Sim& s)
     };
     for (auto& L : s.lv) {
         for (int b = 0; b < 2; ++b) L.off_f[b] = take(L.elems * (int64_t)s.tsize);
+        if (D == 3 && L.boundary) {
+            // the two x faces in their own y-fastest buffers, [2][Q][nz][ny]
+            L.xface = 1;
+            L.xf_elems = 2 * (int64_t)Q * L.nz * L.ny;
+            for (int b = 0; b < 2; ++b) L.off_xf[b] = take(L.xf_elems * (int64_t)s.tsize);
+        }
         if (!L.tf_meta.empty()) {
             L.off_tf = take((int64_t)L.tf_meta.size() * 16);
             L.off_X = take((int64_t)L.tf_meta.size() * 4 * (int64_t)s.rsize);
@@ -600,7 +618,10 @@ dclbm_status sim_attach(Sim& s, void* d_workspace, size_t bytes, hipStream_t str
     s.ws_bytes = bytes;
     s.stream = stream;
     for (auto& L : s.lv) {
-        for (int b = 0; b < 2; ++b) L.f[b] = s.ws + L.off_f[b];
+        for (int b = 0; b < 2; ++b) {
+            L.f[b] = s.ws + L.off_f[b];
+            L.xf[b] = L.xface ? s.ws + L.off_xf[b] : nullptr;
+        }
         if (!L.tf_meta.empty()) {
             L.d_tf = s.at<int4>(L.off_tf);
             L.X = s.ws + L.off_X;

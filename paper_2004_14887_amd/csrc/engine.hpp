@@ -33,6 +33,8 @@ struct HostLevel {
     int plo[3] = {0, 0, 0};
     double ur[3] = {0.0, 0.0, 0.0};   // reference velocity of the carried variable (shifted forms)
     float k1[19] = {}, k2[19] = {};   // per-direction constants of the shifted equilibrium
+    int xface = 0;                    // x-face nodes live in xf[2] (3-D refined levels)
+    int64_t xf_elems = 0;
     double tau = 0.0;
     int64_t n_active = 0;
     // interface with the parent (level >= 1)
@@ -44,10 +46,11 @@ struct HostLevel {
     // interface with the child (coarse co-located nodes, child's order)
     std::vector<int4> tfc_meta;
     // workspace offsets
-    int64_t off_f[2] = {0, 0}, off_tf = 0, off_ie = 0, off_X = 0, off_tfc = 0, off_H = 0, off_seg_info = 0,
+    int64_t off_f[2] = {0, 0}, off_xf[2] = {0, 0}, off_tf = 0, off_ie = 0, off_X = 0, off_tfc = 0, off_H = 0, off_seg_info = 0,
             off_seg_tf = 0, off_seg_ie = 0, off_seg_sten = 0;
     // device pointers
     void* f[2] = {nullptr, nullptr};
+    void* xf[2] = {nullptr, nullptr};
     int4 *d_tf = nullptr, *d_ie = nullptr, *d_tfc = nullptr, *d_seg_info = nullptr;
     int *d_seg_tf = nullptr, *d_seg_ie = nullptr, *d_seg_sten = nullptr;
     void *X = nullptr, *H = nullptr;
@@ -73,6 +76,9 @@ struct HostLevel {
             g.k1[i] = k1[i];
             g.k2[i] = k2[i];
         }
+        g.xface = xface;
+        g.xf[0] = xf[0];
+        g.xf[1] = xf[1];
         return g;
     }
     int64_t n_dense() const { return (int64_t)nx * ny * nz; }
@@ -111,7 +117,8 @@ struct Engine {
 
 struct ProbeLoc {
     int level;
-    int64_t off;
+    int64_t off;   // element of direction 0 in the main buffer
+    int x, y, z;   // node in level coordinates
 };
 
 struct Sim {

@@ -106,6 +106,11 @@ struct LevelDev {
     // per direction, for the second-order shifted equilibrium (host-computed
     // from ur, the same for every node): w_i (1 + B_i(ur)) and 3 + 9 xi_i.ur
     float k1[19], k2[19];
+    // 3-D refined levels: the x-face nodes (x = 0 and nx - 1) live in their
+    // own y-fastest buffers xf[parity], [2][Q][nz][ny] (face x = 0 first), so
+    // that the interface tiles of those faces read and write whole lines
+    int xface;
+    void* xf[2];
 };
 
 template <typename R>
@@ -197,6 +202,27 @@ __device__ __forceinline__ int64_t eoff(const LevelDev& g, int i, int x, int y, 
     return (((int64_t)z * g.ny + y) * g.nxb + (x >> 6)) * (Lat<DIM>::Q * 64) + i * 64 + (x & 63);
 }
 
+template <int DIM>
+__device__ __forceinline__ bool on_xface(const LevelDev& g, int x)
+{
+    return DIM == 3 && g.xface && (x == 0 || x == g.nx - 1);
+}
+
+// Element index of direction i at x-face node (x, y, z) in the face buffer.
+template <int DIM>
+__device__ __forceinline__ int64_t xfoff(const LevelDev& g, int x, int i, int y, int z)
+{
+    return (((int64_t)(x == 0 ? 0 : 1) * Lat<DIM>::Q + i) * g.nz + z) * g.ny + y;
+}
+
+// Direction i of node (x, y, z) in the state of parity par (base = f[par]).
+template <int DIM, typename T>
+__device__ __forceinline__ T* node_elem(const LevelDev& g, T* base, int par, int i, int x, int y, int z)
+{
+    if (on_xface<DIM>(g, x)) return reinterpret_cast<T*>(g.xf[par]) + xfoff<DIM>(g, x, i, y, z);
+    return base + eoff<DIM>(g, i, x, y, z);
+}
+
 // Pull-stream source of direction i: node (x, y, z) - xi_i, periodic on level 0.
 template <int DIM>
 __device__ __forceinline__ int64_t src_off(const LevelDev& g, int x, int y, int z, int i)
@@ -208,6 +234,19 @@ __device__ __forceinline__ int64_t src_off(const LevelDev& g, int x, int y, int 
         if (DIM == 3) sz = sz < 0 ? sz + g.nz : (sz >= g.nz ? sz - g.nz : sz);
     }
     return eoff<DIM>(g, i, sx, sy, sz);
+}
+
+// The same source as an element pointer of the state of parity par.
+template <int DIM, typename T>
+__device__ __forceinline__ const T* pull_elem(const LevelDev& g, const T* src, int par, int x, int y, int z, int i)
+{
+    int sx = x - cdir<DIM>(i, 0), sy = y - cdir<DIM>(i, 1), sz = z - cdir<DIM>(i, 2);
+    if (g.periodic) {
+        sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
+        sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
+        if (DIM == 3) sz = sz < 0 ? sz + g.nz : (sz >= g.nz ? sz - g.nz : sz);
+    }
+    return node_elem<DIM>(g, const_cast<T*>(src), par, i, sx, sy, sz);
 }
 
 template <int DIM>
@@ -267,13 +306,15 @@ struct ProbeArgs {
     int n;
     int64_t capacity;
     const void* buf[32];   // storage buffer holding the probe's node
-    int64_t off[32];       // element offset of direction 0 of that node (directions 64 apart)
+    int64_t off[32];       // element offset of direction 0 of that node
+    int64_t stride[32];    // element distance between directions (64, or nz * ny in a face buffer)
 };
 
 struct LevelArgs {
     LevelDev g;
-    const void* src;
-    void* dst;
+    const void* src;      // f[par]
+    void* dst;            // f[par ^ 1]
+    int par;
     double keep;          // 1 - 1/tau_l
     TileMap tm;
     int nb_cap, nb_seg;   // workgroups of the capture and segment roles
@@ -390,7 +431,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
                 else
                     v = R(-0.125) * Hm + R(0.75) * H0 + R(0.375) * Hp;
             } else {
-                v = F::load(src + src_off<DIM>(a.g, m.x, m.y, m.z, i));
+                v = F::load(pull_elem<DIM>(a.g, src, a.par, m.x, m.y, m.z, i));
             }
             col[i * TFM] = v;
         }
@@ -461,7 +502,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const R e0 = eq0(i);
-                F::store_wb(dst + eoff<DIM>(a.g, i, m.x, m.y, m.z), e0 + keep * (col[i * TFM] - e0));
+                F::store_wb(node_elem<DIM>(a.g, dst, a.par ^ 1, i, m.x, m.y, m.z), e0 + keep * (col[i * TFM] - e0));
             }
         }
     }
@@ -496,7 +537,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
         R s[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            s[i] = ((miss >> i) & 1u) ? R(0) : F::load(src + src_off<DIM>(a.g, m.x, m.y, m.z, i));
+            s[i] = ((miss >> i) & 1u) ? R(0) : F::load(pull_elem<DIM>(a.g, src, a.par, m.x, m.y, m.z, i));
 #pragma unroll
         for (int q = 0; q < (DIM == 2 ? 4 : 16); ++q) {
             if (q < ns) {
@@ -512,7 +553,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
         velocity<DIM, SH, R>(rf, drho, jj, du);
         bgk<DIM, EQ, SH, R>(s, rf, make_mac<DIM, SH, R>(rf, drho, du), R(a.keep));
 #pragma unroll
-        for (int i = 0; i < Q; ++i) F::store_wb(dst + eoff<DIM>(a.g, i, m.x, m.y, m.z), s[i]);
+        for (int i = 0; i < Q; ++i) F::store_wb(node_elem<DIM>(a.g, dst, a.par ^ 1, i, m.x, m.y, m.z), s[i]);
     }
 }
 
@@ -563,6 +604,19 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
     for (int i = 0; i < Q; ++i)
         s[i] = F::load(src + (e0 + dx[cdir<DIM>(i, 0) + 1] + dy[cdir<DIM>(i, 1) + 1] +
                               (DIM == 3 ? dz[cdir<DIM>(i, 2) + 1] : 0) + i * 64));
+    if constexpr (DIM == 3) {
+        // next to an x face the +x (x = 1) or -x (x = nx - 2) directions
+        // come from the face buffer
+        if (g.xface && (x == 1 || x == g.nx - 2)) {
+            const int c = x == 1 ? 1 : -1;
+            const int fx = x == 1 ? 0 : g.nx - 1;
+            const T* xs = reinterpret_cast<const T*>(g.xf[a.par]);
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                if (cdir<DIM>(i, 0) == c)
+                    s[i] = F::load(xs + xfoff<DIM>(g, fx, i, y - cdir<DIM>(i, 1), z - cdir<DIM>(i, 2)));
+        }
+    }
     constexpr bool SH = F::shifted;
     const Ref<R> rf = ref_of<R>(g);
     R drho, j[3], du[3];
@@ -591,7 +645,7 @@ __device__ __forceinline__ void probe_sample(const ProbeArgs& a, double* series,
     if (p < a.n && step < a.capacity) {
         const typename F::T* b = reinterpret_cast<const typename F::T*>(a.buf[p]) + a.off[p];
         double r = F::rho0;
-        for (int i = 0; i < Q; ++i) r += (double)F::load(b + i * 64);
+        for (int i = 0; i < Q; ++i) r += (double)F::load(b + i * a.stride[p]);
         series[step * a.n + p] = (r - 1.0) / 3.0;
     }
     __syncthreads();
@@ -674,7 +728,7 @@ __global__ __launch_bounds__(128) void k_ring_init(LevelDev g, const typename Fo
 // ---------------------------------------------------------------- init / conversion
 // Dense [n] / [D][n] arrays are indexed d = (z*ny + y)*nx + x.
 template <int DIM, int EQ, int P>
-__global__ __launch_bounds__(256) void k_init(LevelDev g, typename Form<P>::T* __restrict__ dst,
+__global__ __launch_bounds__(256) void k_init(LevelDev g, typename Form<P>::T* __restrict__ dst, int par,
                                               const double* __restrict__ rho, const double* __restrict__ u)
 {
     using F = Form<P>;
@@ -699,11 +753,12 @@ __global__ __launch_bounds__(256) void k_init(LevelDev g, typename Form<P>::T* _
                           SH ? uu3[2] - rf.ur[2] : uu3[2]};
     const Mac<double> mc = make_mac<DIM, SH, double>(rf, rho[d] - F::rho0, du);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) F::store(dst + eoff<DIM>(g, i, x, y, z), R(eq_s<DIM, EQ, SH, double>(i, rf, mc)));
+    for (int i = 0; i < Q; ++i)
+        F::store(node_elem<DIM>(g, dst, par, i, x, y, z), R(eq_s<DIM, EQ, SH, double>(i, rf, mc)));
 }
 
 template <int DIM, int EQ, int P>
-__global__ __launch_bounds__(256) void k_read(LevelDev g, const typename Form<P>::T* __restrict__ src,
+__global__ __launch_bounds__(256) void k_read(LevelDev g, const typename Form<P>::T* __restrict__ src, int par,
                                               double* __restrict__ fout, double* __restrict__ rho,
                                               double* __restrict__ u)
 {
@@ -719,7 +774,7 @@ __global__ __launch_bounds__(256) void k_read(LevelDev g, const typename Form<P>
     double r = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const double s = hole ? __builtin_nan("") : (double)F::load(src + eoff<DIM>(g, i, x, y, z));
+        const double s = hole ? __builtin_nan("") : (double)F::load(node_elem<DIM>(g, src, par, i, x, y, z));
         const double f = s + F::rho0 * ref_pop<DIM, EQ>(i, g);
         if (fout) fout[(int64_t)i * n + d] = f;
         r += f;
@@ -887,7 +942,7 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 template <int DIM, int EQ, int P>
-__global__ __launch_bounds__(256) void k_balance(LevelDev g, const typename Form<P>::T* __restrict__ src,
+__global__ __launch_bounds__(256) void k_balance(LevelDev g, const typename Form<P>::T* __restrict__ src, int par,
                                                  double vol, double* __restrict__ partial,
                                                  int* __restrict__ flags)
 {
@@ -907,7 +962,8 @@ __global__ __launch_bounds__(256) void k_balance(LevelDev g, const typename Form
             continue;   // hole or owned by the finer level
         double r = 0.0, j[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < Q; ++i) {
-            const double f = (double)F::load(src + eoff<DIM>(g, i, x, y, z)) + F::rho0 * ref_pop<DIM, EQ>(i, g);
+            const double f =
+                (double)F::load(node_elem<DIM>(g, src, par, i, x, y, z)) + F::rho0 * ref_pop<DIM, EQ>(i, g);
             r += f;
             j[0] += cdir<DIM>(i, 0) * f;
             j[1] += cdir<DIM>(i, 1) * f;
