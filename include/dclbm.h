@@ -138,6 +138,39 @@ dclbm_status dclbm_read_probes(const dclbm_sim* sim, double* d_out, int64_t* n_s
  * Synchronises; also latches DCLBM_ERR_UNSTABLE on a non-finite density. */
 dclbm_status dclbm_balance(dclbm_sim* sim, double h_out[5]);
 
+/* Checkpoint and resume.  The state that the sub-cycling of Sec. 3.5
+ * carries from one coarse step to the next:
+ *   - the current populations of every level;
+ *   - the coarse history rings that feed Eq.(TempInt);
+ *   - the shared states X;
+ *   - the probe series and the latched error flags;
+ *   - on the host: the A/B parity, the capture count of every level, and
+ *     the number of coarse steps done.
+ * The interface tables and the other A/B buffer are not part of it: create
+ * rebuilds the tables from the configuration, and the next step writes the
+ * other buffer.
+ *
+ * dclbm_checkpoint_bytes: size of the checkpoint of this simulation.
+ *
+ * dclbm_save: writes the checkpoint into the caller's device buffer d_blob
+ * (256-byte aligned, at least dclbm_checkpoint_bytes long).  It first
+ * samples the probes of the last step if they are pending.  Copies run on
+ * the simulation's stream; the call synchronises before it returns.
+ *
+ * dclbm_load: restores a checkpoint into a simulation of the same
+ * configuration: same lattice, precision, mesh, tau0, coupling, equilibrium
+ * order, probes, probe capacity, Newton settings and u_ref.  The target may
+ * be the simulation that wrote it, or another one created from the same
+ * configuration.  Stepping on from the restored state gives results
+ * identical, bit for bit, to stepping on from the saved one.  Synchronises.
+ *
+ * Errors (DCLBM_ERR_INVALID, nothing changed): a null or misaligned
+ * buffer, bytes below the checkpoint size, a blob that is not a checkpoint,
+ * or a checkpoint written for another configuration. */
+dclbm_status dclbm_checkpoint_bytes(const dclbm_sim* sim, size_t* bytes);
+dclbm_status dclbm_save(dclbm_sim* sim, void* d_blob, size_t bytes);
+dclbm_status dclbm_load(dclbm_sim* sim, const void* d_blob, size_t bytes);
+
 /* Instrumentation: when on, steps run without graphs and every level-substep
  * launch carries start/stop events in its dispatch; dclbm_bulk_time returns
  * the summed milliseconds, the launch count and the nodes one launch of that

@@ -773,6 +773,99 @@ static dclbm_status check_level_impl(const dclbm_sim* sim, int32_t level)
     return DCLBM_OK;
 }
 
+// ------------------------------------------------------------------ checkpoints
+// A checkpoint is a 256-byte header followed by the state regions, each at a
+// 256-byte aligned offset, in the order state_regions lists them.
+static constexpr uint64_t kCkptMagic = 0x3130544b504c4344ull;   // "DCLPKT01"
+static constexpr int64_t kCkptHeader = 256;
+
+struct CkptHeader {
+    uint64_t magic, fingerprint, bytes;
+    int64_t steps_done;
+    int64_t captures[DCLBM_MAX_LEVELS];
+    int32_t parity[DCLBM_MAX_LEVELS];
+    int32_t n_levels, reserved;
+};
+static_assert(sizeof(CkptHeader) <= (size_t)kCkptHeader, "checkpoint header exceeds its slot");
+
+// 64-bit FNV-1a over the configuration fields that fix the layout and the
+// arithmetic of a simulation.
+struct Fnv1a {
+    uint64_t h = 14695981039346656037ull;
+    template <typename V>
+    void add(const V& v)
+    {
+        const unsigned char* p = reinterpret_cast<const unsigned char*>(&v);
+        for (size_t k = 0; k < sizeof(V); ++k) {
+            h ^= p[k];
+            h *= 1099511628211ull;
+        }
+    }
+};
+
+static uint64_t config_fingerprint(const Sim& s)
+{
+    const dclbm_config& c = s.cfg;
+    Fnv1a f;
+    f.add(c.lattice);
+    f.add(c.precision);
+    f.add(c.coupling);
+    f.add(c.eq_order);
+    f.add(c.n_levels);
+    for (int a = 0; a < s.D; ++a) f.add(c.n0[a]);
+    for (int k = 0; k + 1 < c.n_levels; ++k)
+        for (int a = 0; a < s.D; ++a) {
+            f.add(c.box_lo[k][a]);
+            f.add(c.box_hi[k][a]);
+        }
+    f.add(c.tau0);
+    f.add(c.probe_capacity);
+    f.add(s.newton_maxit);
+    f.add(s.newton_tol);
+    for (int a = 0; a < s.D; ++a) f.add(c.u_ref[a]);
+    f.add((uint64_t)s.need_bytes);
+    f.add((uint64_t)s.probe_xyz.size());
+    for (int32_t v : s.probe_xyz) f.add(v);
+    return f.h;
+}
+
+// The device state carried from one coarse step to the next, for the
+// current parities: (pointer, bytes) in checkpoint order.
+template <class Fn>
+static void state_regions(const Sim& s, Fn&& fn)
+{
+    for (const HostLevel& L : s.lv) {
+        fn(L.f[L.parity], L.elems * (int64_t)s.tsize);
+        if (L.xface) fn(L.xf[L.parity], L.xf_elems * (int64_t)s.tsize);
+        if (!L.tf_meta.empty()) fn(L.X, (int64_t)L.tf_meta.size() * 4 * (int64_t)s.rsize);
+        if (!L.tfc_meta.empty()) fn(L.H, (int64_t)L.tfc_meta.size() * 3 * s.Q * (int64_t)s.rsize);
+    }
+    fn((void*)s.d_series, std::max<int64_t>(1, s.cfg.probe_capacity) * std::max(1, s.cfg.n_probes) * 8);
+    fn((void*)s.d_counter, (int64_t)16);
+    fn((void*)s.d_flags, (int64_t)8);
+}
+
+static int64_t checkpoint_size(const Sim& s)
+{
+    int64_t n = kCkptHeader;
+    state_regions(s, [&](void*, int64_t b) { n += round_up(b, 256); });
+    return n;
+}
+
+// Copies every state region between the simulation and a checkpoint body
+// (to_blob: simulation -> checkpoint), enqueued on the stream.
+static hipError_t copy_regions(const Sim& s, char* body, bool to_blob)
+{
+    hipError_t e = hipSuccess;
+    state_regions(s, [&](void* p, int64_t b) {
+        if (e == hipSuccess)
+            e = to_blob ? hipMemcpyAsync(body, p, (size_t)b, hipMemcpyDeviceToDevice, s.stream)
+                        : hipMemcpyAsync(p, body, (size_t)b, hipMemcpyDeviceToDevice, s.stream);
+        body += round_up(b, 256);
+    });
+    return e;
+}
+
 extern "C" {
 
 const char* dclbm_last_error(void) { return g_err.c_str(); }
@@ -991,6 +1084,70 @@ dclbm_status dclbm_balance(dclbm_sim* sim, double h_out[5])
         for (size_t l = 0; l < s.lv.size(); ++l) h_out[k] += res[l][k];
     }
     return read_flags(s);
+}
+
+dclbm_status dclbm_checkpoint_bytes(const dclbm_sim* sim, size_t* bytes)
+{
+    if (!sim || !bytes) return fail(DCLBM_ERR_INVALID, "null argument");
+    *bytes = (size_t)checkpoint_size(sim->s);
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_save(dclbm_sim* sim, void* d_blob, size_t bytes)
+{
+    if (!sim || !d_blob) return fail(DCLBM_ERR_INVALID, "null argument");
+    if ((uintptr_t)d_blob & 255) return fail(DCLBM_ERR_INVALID, "checkpoint buffer must be 256-byte aligned");
+    Sim& s = sim->s;
+    const int64_t need = checkpoint_size(s);
+    if ((int64_t)bytes < need)
+        return fail(DCLBM_ERR_INVALID, "checkpoint buffer %zu bytes, need %lld", bytes, (long long)need);
+    s.eng->probe(s);   // the last step's probes, if still pending, go into the saved series
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(copy_regions(s, (char*)d_blob + kCkptHeader, true));
+    CkptHeader h;
+    memset(&h, 0, sizeof(h));
+    h.magic = kCkptMagic;
+    h.fingerprint = config_fingerprint(s);
+    h.bytes = (uint64_t)need;
+    h.steps_done = s.steps_done;
+    h.n_levels = (int32_t)s.lv.size();
+    for (size_t l = 0; l < s.lv.size(); ++l) {
+        h.captures[l] = s.lv[l].captures;
+        h.parity[l] = s.lv[l].parity;
+    }
+    HIPCHECK(hipMemcpyAsync(d_blob, &h, sizeof(h), hipMemcpyHostToDevice, s.stream));
+    HIPCHECK(hipStreamSynchronize(s.stream));
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_load(dclbm_sim* sim, const void* d_blob, size_t bytes)
+{
+    if (!sim || !d_blob) return fail(DCLBM_ERR_INVALID, "null argument");
+    if ((uintptr_t)d_blob & 255) return fail(DCLBM_ERR_INVALID, "checkpoint buffer must be 256-byte aligned");
+    if (bytes < (size_t)kCkptHeader) return fail(DCLBM_ERR_INVALID, "not a checkpoint: %zu bytes", bytes);
+    Sim& s = sim->s;
+    CkptHeader h;
+    HIPCHECK(hipMemcpyAsync(&h, d_blob, sizeof(h), hipMemcpyDeviceToHost, s.stream));
+    HIPCHECK(hipStreamSynchronize(s.stream));
+    if (h.magic != kCkptMagic) return fail(DCLBM_ERR_INVALID, "not a checkpoint");
+    if (h.fingerprint != config_fingerprint(s) || h.n_levels != (int32_t)s.lv.size())
+        return fail(DCLBM_ERR_INVALID, "checkpoint written for another configuration");
+    const int64_t need = checkpoint_size(s);
+    if ((int64_t)h.bytes != need || (int64_t)bytes < need)
+        return fail(DCLBM_ERR_INVALID, "checkpoint of %llu bytes in a %zu-byte buffer, expected %lld",
+                    (unsigned long long)h.bytes, bytes, (long long)need);
+    if (h.steps_done < 0) return fail(DCLBM_ERR_INVALID, "corrupt checkpoint header");
+    for (size_t l = 0; l < s.lv.size(); ++l)
+        if ((h.parity[l] & ~1) || h.captures[l] < 0) return fail(DCLBM_ERR_INVALID, "corrupt checkpoint header");
+    // host state first: the regions are those of the saved parities
+    for (size_t l = 0; l < s.lv.size(); ++l) {
+        s.lv[l].parity = h.parity[l];
+        s.lv[l].captures = h.captures[l];
+    }
+    s.steps_done = h.steps_done;
+    HIPCHECK(copy_regions(s, (char*)d_blob + kCkptHeader, false));
+    HIPCHECK(hipStreamSynchronize(s.stream));
+    return DCLBM_OK;
 }
 
 dclbm_status dclbm_copy_calibration(void* d_dst, const void* d_src, size_t bytes, void* stream, int32_t repeats,

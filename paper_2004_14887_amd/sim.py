@@ -177,6 +177,35 @@ class Simulation:
         _lib.check(self.lib.dclbm_balance(self.h, out))
         return list(out)
 
+    # ---------------------------------------------------------------- checkpoints
+    def checkpoint_bytes(self) -> int:
+        n = C.c_size_t()
+        _lib.check(self.lib.dclbm_checkpoint_bytes(self.h, C.byref(n)))
+        return n.value
+
+    def save(self) -> torch.Tensor:
+        """Checkpoint of the current state as a uint8 device tensor."""
+        n = self.checkpoint_bytes()
+        raw = torch.empty(n + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        blob = raw[off:off + n]
+        self._sync_torch()
+        _lib.check(self.lib.dclbm_save(self.h, C.c_void_p(blob.data_ptr()), n))
+        return blob
+
+    def load(self, blob: torch.Tensor):
+        """Restore a checkpoint written by save() for the same configuration
+        (here or by another Simulation); a host tensor is copied over."""
+        assert blob.dtype == torch.uint8 and blob.dim() == 1
+        if blob.device != self.device or blob.data_ptr() % 256 or not blob.is_contiguous():
+            raw = torch.empty(blob.numel() + 256, dtype=torch.uint8, device=self.device)
+            off = (-raw.data_ptr()) % 256
+            aligned = raw[off:off + blob.numel()]
+            aligned.copy_(blob)
+            blob = aligned
+        self._sync_torch()
+        _lib.check(self.lib.dclbm_load(self.h, C.c_void_p(blob.data_ptr()), blob.numel()))
+
     def set_timing(self, on: bool):
         _lib.check(self.lib.dclbm_set_timing(self.h, 1 if on else 0))
 

@@ -111,3 +111,13 @@ def test_server_workspace_bytes_and_validation():
         st, _ = total(0, **bad)
         assert st == -1, bad
     assert L.REQ_STATE[2] == "done"
+
+
+def test_checkpoint_entry_points_reject_null_arguments():
+    import ctypes as C
+    lib = _lib()
+    n = C.c_size_t(7)
+    assert lib.dclbm_checkpoint_bytes(None, C.byref(n)) == -1 and n.value == 7
+    assert lib.dclbm_save(None, None, 0) == -1
+    assert lib.dclbm_load(None, None, 0) == -1
+    assert "null" in lib.dclbm_last_error().decode()
