@@ -172,7 +172,9 @@ dclbm_status dclbm_save(dclbm_sim* sim, void* d_blob, size_t bytes);
 dclbm_status dclbm_load(dclbm_sim* sim, const void* d_blob, size_t bytes);
 
 /* Instrumentation: when on, steps run without graphs and every level-substep
- * launch carries start/stop events in its dispatch; dclbm_bulk_time returns
+ * launch carries start/stop events in its dispatch (a 3-D FP16 substep, which
+ * runs as two kernels side by side, is timed from the fork to the join by
+ * events on the stream); dclbm_bulk_time returns
  * the summed milliseconds, the launch count and the nodes one launch of that
  * level updates (active nodes minus the coarse co-located nodes, which the
  * child's synchronous substep updates). */

@@ -707,6 +707,25 @@ __global__ __launch_bounds__(kBlock) void k_level(LevelArgs a)
     level_block<DIM, EQ, P>(a, blockIdx.x, lds);
 }
 
+// The same level substep as two kernels that run side by side (3-D, FP16
+// storage): the bulk tiles alone, which then run at the occupancy of their
+// own register demand, and the probe, capture and interface-segment
+// workgroups.  The two write disjoint nodes and read only the source
+// buffers, so neither waits for the other.
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(kBlock) void k_bulk(LevelArgs a)
+{
+    role_bulk<DIM, EQ, P>(a, blockIdx.x);
+}
+
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(kBlock) void k_iface(LevelArgs a)
+{
+    using R = typename Form<P>::R;
+    __shared__ R lds[Lat<DIM>::Q * SegLimits<DIM>::TF];
+    level_block<DIM, EQ, P>(a, blockIdx.x, lds);   // the grid ends before the bulk tiles
+}
+
 // ---------------------------------------------------------------- history ring init
 template <int DIM, int P>
 __global__ __launch_bounds__(128) void k_ring_init(LevelDev g, const typename Form<P>::T* __restrict__ src,
