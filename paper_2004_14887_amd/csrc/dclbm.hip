@@ -310,11 +310,16 @@ static std::tuple<int, int, int> segment_key(int D, const int k[3], const int n[
         if (k[a] == 0) face = 2 * a;
         else if (k[a] == n[a] - 1) face = 2 * a + 1;
     }
+    // tiles of 256 positions on a 2-D interface line; 32 x 16 positions on a
+    // 3-D face, the longer side along the face's faster storage axis
     const int ax = face / 2;
     int t[2] = {0, 0}, no = 0;
-    const int T = D == 2 ? 256 : 16;
+    const int T[2] = {D == 2 ? 256 : 32, 16};
     for (int a = 0; a < D; ++a)
-        if (a != ax) t[no++] = k[a] / T;
+        if (a != ax) {
+            t[no] = k[a] / T[no];
+            ++no;
+        }
     return std::make_tuple(face, t[0], t[1]);
 }
 
@@ -388,7 +393,7 @@ static dclbm_status build_segments(Sim& s, int l)
             }
             L.seg_ie.push_back(e);
         }
-        if ((int)list.size() > TFM || (int)list.size() > kBlock || (int)sg.ie.size() > kBlock)
+        if ((int)list.size() > TFM || (int)list.size() > kBlock || (int)sg.ie.size() > 2 * kBlock)
             return fail(DCLBM_ERR_INVALID, "level %d: interface segment too large (%zu co-located, %zu hanging)", l,
                         list.size(), sg.ie.size());
         L.seg_info.push_back(make_int4((int)L.seg_tf.size(), (int)list.size(), ie_off, (int)sg.ie.size()));

@@ -285,7 +285,7 @@ __device__ __forceinline__ void line_weights(int k, int N, float w[4])
 // runs in workgroups of kBlock threads.
 template <int DIM>
 struct SegLimits {
-    static constexpr int TF = DIM == 2 ? 136 : 144;
+    static constexpr int TF = DIM == 2 ? 136 : 224;
     static constexpr int IE = 256;
 };
 constexpr int kBlock = 256;
@@ -508,8 +508,8 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
     }
     __syncthreads();
     // ---- phase 2: hanging nodes
-    if (j < info.w) {
-        const int q0 = info.z + j;
+    for (int je = j; je < info.w; je += kBlock) {
+        const int q0 = info.z + je;
         const int4 m = a.ie_meta[a.seg_ie[q0]];
         const int k[3] = {m.x, m.y, m.z};
         const int N[3] = {a.g.nx - 1, a.g.ny - 1, a.g.nz - 1};
