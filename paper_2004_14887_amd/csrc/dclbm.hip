@@ -310,11 +310,12 @@ static std::tuple<int, int, int> segment_key(int D, const int k[3], const int n[
         if (k[a] == 0) face = 2 * a;
         else if (k[a] == n[a] - 1) face = 2 * a + 1;
     }
-    // tiles of 256 positions on a 2-D interface line; 32 x 16 positions on a
-    // 3-D face, the longer side along the face's faster storage axis
+    // tiles of 256 positions on a 2-D interface line; 32 x 20 positions on a
+    // 3-D face, the longer side along the face's faster storage axis (160
+    // own co-located nodes plus an 87-node stencil halo fit one workgroup)
     const int ax = face / 2;
     int t[2] = {0, 0}, no = 0;
-    const int T[2] = {D == 2 ? 256 : 32, 16};
+    const int T[2] = {D == 2 ? 256 : 32, D == 2 ? 16 : 20};
     for (int a = 0; a < D; ++a)
         if (a != ax) {
             t[no] = k[a] / T[no];

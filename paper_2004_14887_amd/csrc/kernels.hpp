@@ -285,7 +285,7 @@ __device__ __forceinline__ void line_weights(int k, int N, float w[4])
 // runs in workgroups of kBlock threads.
 template <int DIM>
 struct SegLimits {
-    static constexpr int TF = DIM == 2 ? 136 : 224;
+    static constexpr int TF = DIM == 2 ? 136 : 256;
     static constexpr int IE = 256;
 };
 constexpr int kBlock = 256;
