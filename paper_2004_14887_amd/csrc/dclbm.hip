@@ -169,6 +169,10 @@ struct EngineImpl final : Engine {
                 return;
             }
         }
+        // level 0 (no segments) of a 2-D FP16 mesh: the kernel without the
+        // segment role, 38 VGPRs and 8 waves/SIMD instead of 78 and 6
+        // (measured 11% faster on that launch; FP32 and FP64 gain nothing)
+        const bool top = DIM == 2 && P == 2 && a.nb_seg == 0;
         if (s.timing) {
             // start/stop events travel in the dispatch packet of the kernel
             // itself; without the system-scope fence the stop stamp is not
@@ -176,8 +180,13 @@ struct EngineImpl final : Engine {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             (void)hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
             (void)hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
-            hipExtLaunchKernelGGL((k_level<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, e0, e1, 0, a);
+            if (top)
+                hipExtLaunchKernelGGL((k_level_top<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, e0, e1, 0, a);
+            else
+                hipExtLaunchKernelGGL((k_level<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, e0, e1, 0, a);
             s.tev[l].push_back({e0, e1});
+        } else if (top) {
+            hipLaunchKernelGGL((k_level_top<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, a);
         } else {
             hipLaunchKernelGGL((k_level<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, a);
         }

@@ -674,7 +674,7 @@ __device__ __forceinline__ void probe_pending(const ProbeArgs& pa, double* serie
 // register demand the segment role imposes on the whole kernel: 3-D 110
 // VGPRs, 4 waves/SIMD; 2-D FP16 78 VGPRs, 6 waves/SIMD instead of 91 and 5,
 // measured 2.4% faster.  2-D FP32/FP64 keep the unrolled loop.
-template <int DIM, int EQ, int P, bool ROLLED = (DIM == 3 || P == 2)>
+template <int DIM, int EQ, int P, bool ROLLED = (DIM == 3 || P == 2), bool SEG = true>
 __device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename Form<P>::R* lds)
 {
     if (b < a.nb_probe) {
@@ -693,9 +693,11 @@ __device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename 
     const int b2 = b - a.nb_cap;
     const int nseg = 8 * a.seg_groups;
     if (b2 < nseg) {
-        if (b2 < a.nb_seg) {
-            role_segment<DIM, EQ, P, ROLLED>(a, b2, lds);
-            return true;
+        if constexpr (SEG) {
+            if (b2 < a.nb_seg) {
+                role_segment<DIM, EQ, P, ROLLED>(a, b2, lds);
+                return true;
+            }
         }
         return false;
     }
@@ -728,6 +730,15 @@ __global__ __launch_bounds__(kBlock) void k_iface(LevelArgs a)
     using R = typename Form<P>::R;
     __shared__ R lds[Lat<DIM>::Q * SegLimits<DIM>::TF];
     level_block<DIM, EQ, P>(a, blockIdx.x, lds);   // the grid ends before the bulk tiles
+}
+
+// Level 0 has no parent interface, so its launch has no segment workgroups:
+// compiled without the segment role, the kernel needs only the bulk's
+// registers and runs at a higher occupancy (used for 2-D FP16 storage).
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(kBlock) void k_level_top(LevelArgs a)
+{
+    level_block<DIM, EQ, P, true, false>(a, blockIdx.x, nullptr);
 }
 
 // ---------------------------------------------------------------- history ring init
