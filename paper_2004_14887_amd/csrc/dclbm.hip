@@ -1005,13 +1005,7 @@ dclbm_status dclbm_destroy(dclbm_sim* sim)
             (void)hipEventDestroy(e.second);
         }
     }
-    if (s.side) {
-        (void)hipStreamSynchronize(s.side);
-        (void)hipStreamDestroy(s.side);
-        (void)hipEventDestroy(s.ev_fork);
-        (void)hipEventDestroy(s.ev_join);
-    }
-    delete sim;
+    delete sim;   // releases the side stream and its events
     return DCLBM_OK;
 }
 

@@ -159,6 +159,16 @@ struct Sim {
     {
         return reinterpret_cast<T*>(ws + off);
     }
+
+    ~Sim()
+    {
+        if (side) {
+            (void)hipStreamSynchronize(side);
+            (void)hipStreamDestroy(side);
+        }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+    }
 };
 
 template <typename V>
