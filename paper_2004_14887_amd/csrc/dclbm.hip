@@ -403,7 +403,7 @@ static dclbm_status build_segments(Sim& s, int l)
             }
             L.seg_ie.push_back(e);
         }
-        if ((int)list.size() > TFM || (int)list.size() > kBlock || (int)sg.ie.size() > 2 * kBlock)
+        if ((int)list.size() > TFM || (int)list.size() > kBlock || (int)sg.ie.size() > SegLimits<3>::IE)
             return fail(DCLBM_ERR_INVALID, "level %d: interface segment too large (%zu co-located, %zu hanging)", l,
                         list.size(), sg.ie.size());
         L.seg_info.push_back(make_int4((int)L.seg_tf.size(), (int)list.size(), ie_off, (int)sg.ie.size()));

@@ -281,14 +281,15 @@ __device__ __forceinline__ void line_weights(int k, int N, float w[4])
 }
 
 // ---------------------------------------------------------------- the level-substep kernel
-// Maximum co-located nodes a segment holds in LDS (own + halo); every role
-// runs in workgroups of kBlock threads.
+// Every role runs in workgroups of kBlock threads.  A segment holds at most
+// TF co-located nodes in LDS (own + halo, one per thread) and IE hanging
+// nodes (two passes of the workgroup).
+constexpr int kBlock = 256;
 template <int DIM>
 struct SegLimits {
     static constexpr int TF = DIM == 2 ? 136 : 256;
-    static constexpr int IE = 256;
+    static constexpr int IE = 2 * kBlock;
 };
-constexpr int kBlock = 256;
 
 // Bulk tiles are 64 x 4 nodes.  A tile row is the tx tiles sharing one
 // (4-row group, z).  Workgroups are dealt round-robin to the 8 XCDs, so
