@@ -887,6 +887,20 @@ struct SlotDev {
 // Phase table p at ptab + p * (3 + 2 M): n, total, slot[M], begin[M + 1]
 // (begin[k] = first virtual workgroup of item k, multiples of 8; begin[n] =
 // total).  The tail list follows the last phase: n, slot[M].
+//
+// Item k's virtual workgroups: its capture and segment workgroups (padded to
+// a multiple of 8), then multi_groups(DIM, per) bulk workgroups.  Bulk
+// workgroup u runs the tiles 8 (c K + r) + (u & 7), r < K, c = u >> 3, with
+// K = multi_tiles(DIM): the item lookup and argument load of a serving
+// workgroup are paid once per K tiles (measured +5% capacity in 2-D), and
+// every tile keeps the XCD (u & 7) of a plain launch.  3-D keeps K = 1: the
+// tile loop compiles the bulk arithmetic differently, and 3-D served results
+// equal those of a single simulation bit for bit only with one tile.
+__host__ __device__ constexpr int multi_tiles(int dim) { return dim == 2 ? 4 : 1; }
+__host__ __device__ constexpr int multi_groups(int dim, int per)
+{
+    return 8 * ((per + multi_tiles(dim) - 1) / multi_tiles(dim));
+}
 struct MultiArgs {
     const SlotDev* slots;
     const int* ptab;
@@ -940,10 +954,18 @@ __global__ __launch_bounds__(kBlock) void k_level_multi(MultiArgs m)
         if (step < sd->target) {
             const int var = step == 0 ? 0 : 1 + (int)(step & 1);
             const LevelArgs a = load_const(sd->args + var * m.n_phases + m.phase);
-            // only a segment iteration leaves LDS behind; a barrier after
-            // every iteration would also wait for each tile's stores.  Every
-            // wave runs the same iterations, so the barriers still pair up.
-            if (level_block<DIM, EQ, P, true>(a, v - begin[lo], lds)) __syncthreads();
+            const int b = v - begin[lo];
+            const int na = a.nb_probe + a.nb_cap + 8 * a.seg_groups, nap = (na + 7) & ~7;
+            if (b < nap) {
+                // only a segment iteration leaves LDS behind; a barrier after
+                // every iteration would also wait for each tile's stores.
+                // Every wave runs the same iterations, so the barriers pair up.
+                if (b < na && level_block<DIM, EQ, P, true>(a, b, lds)) __syncthreads();
+            } else {
+                constexpr int K = multi_tiles(DIM);
+                const int u = b - nap, c0 = (u >> 3) * K;
+                for (int r = 0; r < K && c0 + r < a.tm.per; ++r) role_bulk<DIM, EQ, P>(a, 8 * (c0 + r) + (u & 7));
+            }
         }
     }
 }

@@ -294,10 +294,10 @@ dclbm_status upload_tables(Server& sv)
             const LevelArgs& a = sv.h_args[((size_t)k * 3 + 1) * sv.NPH + p];
             const Request& r = *sv.reqs[sv.slot_req[k]];
             if (sv.phases[p].first >= (int)r.sim->lv.size()) continue;
-            const unsigned grid = (unsigned)(a.nb_cap + 8 * a.seg_groups + 8 * a.tm.per);
+            const int na = a.nb_probe + a.nb_cap + 8 * a.seg_groups;
             pt[2 + n] = k;
             pt[2 + M + n] = total;
-            total += (int)round_up(grid, 8);
+            total += (int)round_up(na, 8) + multi_groups(sv.D, a.tm.per);
             ++n;
         }
         pt[2 + M + n] = total;
