@@ -42,8 +42,10 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP16 side runs")
-    ap.add_argument("--workload", default="pulse_vortices_3level", choices=["pulse_vortices_3level", "pulse_ring_3d"],
-                    help="3-level 2048^2 D2Q9 (default) or 2-level 256^3 D3Q19")
+    ap.add_argument("--workload", default="pulse_vortices_3level",
+                    choices=["pulse_vortices_3level", "pulse_ring_3d", "rings_4level_uniform"],
+                    help="3-level 2048^2 D2Q9 (default), 2-level 256^3 D3Q19, or the 4-level 512^3 D3Q19 mesh at "
+                         "full size (FP16 storage only, about 194 GB) carrying a uniform flow")
     ap.add_argument("--copy-only", action="store_true", help="only run the plain copy kernel (counter calibration)")
     ap.add_argument("--serving-requests", type=int, default=256, help="requests in the serving run (0: skip it)")
     ap.add_argument("--serving-only", action="store_true", help="only the serving run")
@@ -70,7 +72,20 @@ def run_form(wl, prec, steps, warmup, latency_steps, timing_steps):
 
     log(f"{prec}: create + init ({wl.name})")
     sim = Simulation(wl, prec, probe_capacity=warmup + steps + latency_steps + timing_steps + 2)
-    sim.init_from_workload()
+    if getattr(wl, "device_uniform", False):
+        # a uniform (rho = 1, u = background) state built on the device, level
+        # by level: host-side fields of the 1.1e9-node finest level would not pay
+        for l in range(wl.n_levels):
+            n = sim.n_dense(l)
+            rho = torch.ones(n, dtype=torch.float64, device=sim.device)
+            u = torch.empty((3, n), dtype=torch.float64, device=sim.device)
+            for a in range(3):
+                u[a].fill_(wl.background[a])
+            sim.init(l, rho, u)
+            del rho, u
+            torch.cuda.empty_cache()
+    else:
+        sim.init_from_workload()
     sim.step(warmup)
     sim.synchronize()
     sim.check()
@@ -329,6 +344,18 @@ def main():
         n0 = args.n0 if args.n0 != 2048 else 256
         wl = W.pulse_ring_3d(seed=3, n0=n0, steps=args.steps)
         mk = lambda steps: W.pulse_ring_3d(seed=3, n0=n0, steps=steps)
+    elif args.workload == "rings_4level_uniform":
+        # only FP16 storage fits one GPU at this size; no FP64 side run, no
+        # oracle baseline (its FP64 state would need about 0.8 TB)
+        if args.precision != "fp16":
+            sys.exit("rings_4level_uniform: only --precision fp16 fits one GPU")
+        wl = W.rings_4level(seed=5, steps=args.steps)
+        wl.rings, wl.pulses = [], []
+        wl.background = (0.03, -0.02, 0.01)
+        wl.name = "rings_4level_512_uniform"
+        wl.device_uniform = True
+        args.no_compare, args.no_cpu_baseline, args.serving_requests = True, True, 0
+        mk = None
     else:
         wl = W.pulse_vortices_3level(seed=2, n0=args.n0, steps=args.steps)
         mk = lambda steps: W.pulse_vortices_3level(seed=2, n0=args.n0, steps=steps)
