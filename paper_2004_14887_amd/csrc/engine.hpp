@@ -153,6 +153,14 @@ struct Sim {
     int64_t tlaunch[DCLBM_MAX_LEVELS] = {0, 0, 0, 0};
     double newton_tol = 1e-12;
     int newton_maxit = 20;
+    // first failed HIP call of the launch sequence of a step (event records
+    // and waits of the split substeps, timing events); checked after the
+    // eager launches or the capture of every coarse step
+    hipError_t launch_err = hipSuccess;
+    void note(hipError_t e)
+    {
+        if (launch_err == hipSuccess && e != hipSuccess) launch_err = e;
+    }
 
     template <typename T>
     T* at(int64_t off) const

@@ -1,0 +1,162 @@
+// Launchers of one (lattice, equilibrium order, storage form) class: the
+// engine that a simulation drives.  Each lattice/order pair is compiled in a
+// translation unit of its own (engine_d*_eq*.hip), so the device code of the
+// twelve classes builds in parallel.
+#pragma once
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "engine.hpp"
+
+namespace dclbm {
+
+// ------------------------------------------------------------------ engine implementation
+template <int DIM, int EQ, int P>
+struct EngineImpl final : Engine {
+    using F = Form<P>;
+    using T = typename F::T;
+    using R = typename F::R;
+
+    static dim3 dense_grid(const HostLevel& L)
+    {
+        return dim3((unsigned)((L.nx + 63) / 64), (unsigned)((L.ny + 3) / 4), (unsigned)L.nz);
+    }
+
+    void level_step(Sim& s, int l, int substep, int first) override
+    {
+        unsigned grid = 0;
+        const LevelArgs a = level_args(s, l, substep, first, &grid);
+        if constexpr (DIM == 3 && P == 2) {
+            if (s.side) {
+                // 3-D FP16 storage: the bulk on the simulation's stream, the
+                // interface workgroups beside it on the side stream (fork,
+                // launch both, join).  Alone, the bulk kernel needs 46 VGPRs
+                // instead of 110 and runs at 8 waves per SIMD instead of 4,
+                // which the 2-byte loads need to keep enough bytes in flight
+                // (measured 4% faster).  The FP32/FP64 bulk and every 2-D
+                // form measured slower split, so they stay one launch.
+                const unsigned g_bulk = 8u * (unsigned)a.tm.per, g_if = grid - g_bulk;
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (s.timing) {
+                    s.note(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+                    s.note(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+                    s.note(hipEventRecord(e0, s.stream));
+                }
+                if (g_if > 0) {
+                    s.note(hipEventRecord(s.ev_fork, s.stream));
+                    s.note(hipStreamWaitEvent(s.side, s.ev_fork, 0));
+                    hipLaunchKernelGGL((k_iface<DIM, EQ, P>), dim3(g_if), dim3(kBlock), 0, s.side, a);
+                }
+                if (g_bulk > 0) hipLaunchKernelGGL((k_bulk<DIM, EQ, P>), dim3(g_bulk), dim3(kBlock), 0, s.stream, a);
+                if (g_if > 0) {
+                    s.note(hipEventRecord(s.ev_join, s.side));
+                    s.note(hipStreamWaitEvent(s.stream, s.ev_join, 0));
+                }
+                if (s.timing) {
+                    s.note(hipEventRecord(e1, s.stream));
+                    s.tev[l].push_back({e0, e1});
+                }
+                return;
+            }
+        }
+        // level 0 (no segments) of a 2-D FP16 mesh: the kernel without the
+        // segment role, 38 VGPRs and 8 waves/SIMD instead of 78 and 6
+        // (measured 11% faster on that launch; FP32 and FP64 gain nothing)
+        const bool top = DIM == 2 && P == 2 && a.nb_seg == 0;
+        if (s.timing) {
+            // start/stop events travel in the dispatch packet of the kernel
+            // itself; without the system-scope fence the stop stamp is not
+            // delayed by a cache write-back the next launch does not need
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            s.note(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+            s.note(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+            if (top)
+                hipExtLaunchKernelGGL((k_level_top<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, e0, e1, 0, a);
+            else
+                hipExtLaunchKernelGGL((k_level<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, e0, e1, 0, a);
+            s.tev[l].push_back({e0, e1});
+        } else if (top) {
+            hipLaunchKernelGGL((k_level_top<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, a);
+        } else {
+            hipLaunchKernelGGL((k_level<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, a);
+        }
+    }
+    void probe(Sim& s) override
+    {
+        // the pending sample of the last coarse step (a no-op if none)
+        const ProbeArgs a = probe_args(s);
+        hipLaunchKernelGGL((k_probe<DIM, P>), dim3(1), dim3(64), 0, s.stream, a, s.d_series, s.d_counter);
+    }
+    void init(Sim& s, int l, const double* rho, const double* u) override
+    {
+        HostLevel& L = s.lv[l];
+        hipLaunchKernelGGL((k_init<DIM, EQ, P>), dense_grid(L), dim3(64, 4, 1), 0, s.stream, L.dev(),
+                           (T*)L.f[L.parity], L.parity, rho, u);
+    }
+    void ring_init(Sim& s, int l) override
+    {
+        HostLevel& L = s.lv[l];
+        const int n = (int)L.tfc_meta.size();
+        hipLaunchKernelGGL((k_ring_init<DIM, P>), dim3((n + 127) / 128), dim3(128), 0, s.stream, L.dev(),
+                           (const T*)L.f[L.parity], L.d_tfc, n, (R*)L.H);
+    }
+    void fill_nan(Sim& s) override
+    {
+        for (auto& L : s.lv) {
+            T nanv;
+            if constexpr (P == 2) {
+                unsigned short b = 0x7e00;
+                memcpy(&nanv, &b, 2);
+            } else {
+                nanv = (T)NAN;
+            }
+            for (int b = 0; b < 2; ++b) {
+                hipLaunchKernelGGL((k_fill<T>), dim3(2048), dim3(256), 0, s.stream, (T*)L.f[b], L.elems, nanv);
+                if (L.xface)
+                    hipLaunchKernelGGL((k_fill<T>), dim3(256), dim3(256), 0, s.stream, (T*)L.xf[b], L.xf_elems, nanv);
+            }
+            if (L.X)
+                hipLaunchKernelGGL((k_fill<R>), dim3(256), dim3(256), 0, s.stream, (R*)L.X,
+                                   4 * (int64_t)L.tf_meta.size(), (R)NAN);
+            if (L.H)
+                hipLaunchKernelGGL((k_fill<R>), dim3(256), dim3(256), 0, s.stream, (R*)L.H,
+                                   3 * (int64_t)Lat<DIM>::Q * (int64_t)L.tfc_meta.size(), (R)NAN);
+        }
+    }
+    void read(Sim& s, int l, double* f, double* rho, double* u) override
+    {
+        HostLevel& L = s.lv[l];
+        hipLaunchKernelGGL((k_read<DIM, EQ, P>), dense_grid(L), dim3(64, 4, 1), 0, s.stream, L.dev(),
+                           (const T*)L.f[L.parity], L.parity, f, rho, u);
+    }
+    void read_shared(Sim& s, int l, double* out) override
+    {
+        HostLevel& L = s.lv[l];
+        const int64_t n = L.n_dense();
+        hipLaunchKernelGGL(k_fill_nan_f64, dim3(1024), dim3(256), 0, s.stream, out, 4 * n);
+        const int ntf = (int)L.tf_meta.size();
+        if (ntf)
+            hipLaunchKernelGGL((k_read_shared<P>), dim3((ntf + 127) / 128), dim3(128), 0, s.stream, L.d_tf, ntf,
+                               L.dev(), n, (const R*)L.X, out);
+    }
+    void balance(Sim& s, int l, double* partial, int nblocks) override
+    {
+        HostLevel& L = s.lv[l];
+        const double vol = std::ldexp(1.0, -DIM * l);
+        hipLaunchKernelGGL((k_balance<DIM, EQ, P>), dim3(nblocks), dim3(256), 0, s.stream, L.dev(),
+                           (const T*)L.f[L.parity], L.parity, vol, partial, s.d_flags);
+    }
+    void launch_multi(hipStream_t st, const MultiArgs& m, unsigned grid) override
+    {
+        hipLaunchKernelGGL((k_level_multi<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, st, m);
+    }
+    void launch_tail(hipStream_t st, const MultiArgs& m, unsigned grid) override
+    {
+        hipLaunchKernelGGL((k_server_tail<DIM, P>), dim3(grid), dim3(64), 0, st, m);
+    }
+};
+
+}  // namespace dclbm

@@ -340,7 +340,7 @@ struct LevelArgs {
     int maxit;
     double Rfac;          // tau_l / (2 tau_{l-1}), Eq.(fneqResc)
     double tol;
-    int* flags;
+    int* flags;           // bit 0: Newton failure, bit 1: non-finite or non-positive density (every level)
     // restriction into the parent at synchronous substeps
     LevelDev gp;
     void* dst_parent;
@@ -354,6 +354,15 @@ struct LevelArgs {
     double* series;
     int64_t* counter;       // [0] steps sampled, [1] coarse steps started
 };
+
+// A non-finite or non-positive density (a run that has become unstable)
+// latches flag bit 2.  The test costs a compare per node; the atomic runs
+// only on a wave that holds such a node, so every step checks every node.
+template <typename R>
+__device__ __forceinline__ void flag_unstable(R rho, int* flags)
+{
+    if (!(rho > R(0) && rho < R(1e30))) atomicOr(flags, 2);
+}
 
 template <int DIM, int P>
 __device__ __forceinline__ void role_capture(const LevelArgs& a, int b)
@@ -449,7 +458,6 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
             it = newton_v<DIM, EQ, SH, R, decltype(hv), EqGrad<DIM, EQ, SH, R>, ROLLED>(
                 hv, gR, R(a.Rfac), rf, R(a.tol), a.maxit, drho, du, EqGrad<DIM, EQ, SH, R>{rf});
         if (it < 0) {
-            if (owned) atomicOr(a.flags, 1);
             R jj[3] = {R(0), R(0), R(0)};
             drho = R(0);
 #pragma unroll
@@ -461,6 +469,12 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
                 jj[2] += R(cdir<DIM>(i, 2)) * v;
             }
             velocity<DIM, SH, R>(rf, drho, jj, du);
+            // non-convergence on finite inputs is a Newton failure (bit 1);
+            // non-finite inputs are an instability (bit 2)
+            if (owned) {
+                const R rho = (SH ? R(1) : R(0)) + drho;
+                atomicOr(a.flags, (rho > R(0) && rho < R(1e30)) ? 1 : 2);
+            }
         }
         const Mac<R> mx = make_mac<DIM, SH, R>(rf, drho, du);
         auto eq0 = [&](int i) -> R {
@@ -551,6 +565,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
         }
         R drho, jj[3], du[3];
         moments<DIM, R>(s, drho, jj);
+        flag_unstable((SH ? R(1) : R(0)) + drho, a.flags);
         velocity<DIM, SH, R>(rf, drho, jj, du);
         bgk<DIM, EQ, SH, R>(s, rf, make_mac<DIM, SH, R>(rf, drho, du), R(a.keep));
 #pragma unroll
@@ -622,7 +637,9 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
     const Ref<R> rf = ref_of<R>(g);
     R drho, j[3], du[3];
     moments<DIM, R>(s, drho, j);
-    const R inv = recip<R>((SH ? R(1) : R(0)) + drho);
+    const R rho = (SH ? R(1) : R(0)) + drho;
+    flag_unstable(rho, a.flags);
+    const R inv = recip<R>(rho);
 #pragma unroll
     for (int c = 0; c < 3; ++c) du[c] = c < DIM ? (SH ? j[c] - drho * rf.ur[c] : j[c]) * inv : R(0);
     if constexpr (SH && EQ == 2)

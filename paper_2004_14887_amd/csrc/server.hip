@@ -395,7 +395,7 @@ dclbm_status retire(Server& sv)
         r.probes.assign((const double*)res, (const double*)res + nser);
         int flags[2];
         memcpy(flags, res + (size_t)sv.cfg.max_probe_steps * std::max(1, sv.cfg.max_probes) * sizeof(double), sizeof(flags));
-        r.status = (flags[0] & 1) ? DCLBM_ERR_NEWTON : (flags[0] & 2) ? DCLBM_ERR_UNSTABLE : DCLBM_OK;
+        r.status = (flags[0] & 2) ? DCLBM_ERR_UNSTABLE : (flags[0] & 1) ? DCLBM_ERR_NEWTON : DCLBM_OK;
         r.state = r.status == DCLBM_OK ? DCLBM_REQ_DONE : DCLBM_REQ_FAILED;
         r.t_done = sv.now();
         sv.arena.release(r.off, r.bytes);

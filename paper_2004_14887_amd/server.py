@@ -81,9 +81,11 @@ class Server:
         except Exception:
             pass
 
-    def submit(self, wl: Workload, steps: Optional[int] = None, fields: Optional[Sequence] = None) -> int:
+    def submit(self, wl: Workload, steps: Optional[int] = None, fields: Optional[Sequence] = None,
+               newton_max_iter: int = 0, newton_tol: float = 0.0) -> int:
         steps = int(steps if steps is not None else wl.steps)
-        cfg, keep = make_config(wl, self.precision, probe_capacity=steps)
+        cfg, keep = make_config(wl, self.precision, probe_capacity=steps, newton_max_iter=newton_max_iter,
+                                newton_tol=newton_tol)
         if fields is None:
             fields = request_fields(wl)
         L = wl.n_levels
