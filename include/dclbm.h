@@ -138,6 +138,20 @@ dclbm_status dclbm_read_probes(const dclbm_sim* sim, double* d_out, int64_t* n_s
  * Synchronises; also latches DCLBM_ERR_UNSTABLE on a non-finite density. */
 dclbm_status dclbm_balance(dclbm_sim* sim, double h_out[5]);
 
+/* For callers that cannot allocate or synchronise, such as code under HIP
+ * graph capture or a serving loop that must not block: the balances of
+ * dclbm_balance, enqueued on the simulation's stream and written to the
+ * caller's device buffer d_out (5 FP64: mass, momentum[3], kinetic energy),
+ * bit-identical to dclbm_balance's.  It allocates nothing, copies nothing to
+ * the host and does not synchronise; a non-finite density latches
+ * DCLBM_ERR_UNSTABLE for the next dclbm_check.  Its block partial sums live
+ * in a static device array of the library (each GPU's copy holds 4 levels x
+ * 1024 blocks x 5 doubles plus 4 x 5 totals, about 160 KB, until the process
+ * ends); a simulation needing more is rejected (DCLBM_ERR_INVALID).  Calls
+ * on one GPU share that array: calls that overlap on one GPU (two streams)
+ * race, so serialise them.  The simulation's device must be current. */
+dclbm_status dclbm_balance_static(dclbm_sim* sim, double* d_out);
+
 /* Checkpoint and resume.  The state that the sub-cycling of Sec. 3.5
  * carries from one coarse step to the next:
  *   - the current populations of every level;

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <tuple>
@@ -40,6 +41,51 @@ dclbm_status fail(dclbm_status s, const char* fmt, ...)
     va_end(ap);
     g_err = buf;
     return s;
+}
+
+// ------------------------------------------------------------------ static scratch
+// Block partial sums of dclbm_balance_static, for callers that cannot
+// allocate: every level's kBalanceBlocks partials (5 doubles each), then the
+// per-level totals.  Each GPU holds its own copy of the array (about 160 KB)
+// until the process ends; host code uses the address that
+// hipGetSymbolAddress returned for the current device, never the array's
+// name.  Calls on one GPU share the array: calls that overlap on one GPU
+// race.
+constexpr int kBalanceBlocks = 1024;   // partial blocks per level (the same as dclbm_balance)
+constexpr int64_t kScratchDoubles = (int64_t)DCLBM_MAX_LEVELS * kBalanceBlocks * 5 + DCLBM_MAX_LEVELS * 5;
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+static std::mutex g_scratch_mu;
+static std::map<int, double*> g_scratch_ptr;   // device -> device address of its scratch array
+
+// Device address of the current device's scratch array, resolved once per
+// device (at dclbm_create, with the simulation's device current).
+static dclbm_status scratch_address(int device, double** out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return DCLBM_OK;
+    }
+    double* p = nullptr;
+    HIPCHECK(hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(DCLBM_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[device] = p;
+    *out = p;
+    return DCLBM_OK;
+}
+
+// Sum of the per-level totals (level order, from zero, as dclbm_balance sums
+// them on the host) into the caller's five doubles.
+static __global__ __launch_bounds__(64) void k_balance_levels(const double* __restrict__ totals, int n_levels,
+                                                              double* __restrict__ out)
+{
+    const int k = threadIdx.x;
+    if (k >= 5) return;
+    double v = 0.0;
+    for (int l = 0; l < n_levels; ++l) v += totals[5 * l + k];
+    out[k] = v;
 }
 
 // ------------------------------------------------------------------ launch arguments
@@ -856,6 +902,9 @@ dclbm_status dclbm_create(const dclbm_config* cfg, void* d_workspace, size_t byt
     }
     dclbm_status st = sim_attach(s, d_workspace, bytes, (hipStream_t)stream);
     if (st != DCLBM_OK) return st;
+    HIPCHECK(hipGetDevice(&s.device));
+    st = scratch_address(s.device, &s.d_scratch);
+    if (st != DCLBM_OK) return st;
     if (s.D == 3 && s.P == 2) {
         // side stream (default priority) for the interface half of the split substeps
         HIPCHECK(hipStreamCreateWithFlags(&s.side, hipStreamNonBlocking));
@@ -1016,6 +1065,31 @@ dclbm_status dclbm_balance(dclbm_sim* sim, double h_out[5])
         for (size_t l = 0; l < s.lv.size(); ++l) h_out[k] += res[l][k];
     }
     return read_flags(s);
+}
+
+dclbm_status dclbm_balance_static(dclbm_sim* sim, double* d_out)
+{
+    if (!sim || !d_out) return fail(DCLBM_ERR_INVALID, "null argument");
+    Sim& s = sim->s;
+    const int L = (int)s.lv.size();
+    if (s.partial_blocks != kBalanceBlocks || (int64_t)L * kBalanceBlocks * 5 + (int64_t)L * 5 > kScratchDoubles)
+        return fail(DCLBM_ERR_INVALID, "balance of %d levels x %d blocks exceeds the static scratch (%d levels x %d)",
+                    L, s.partial_blocks, DCLBM_MAX_LEVELS, kBalanceBlocks);
+    if (!s.d_scratch) return fail(DCLBM_ERR_HIP, "static scratch not resolved for this simulation's device");
+    int dev = -1;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev != s.device)
+        return fail(DCLBM_ERR_INVALID, "device %d is current, the simulation lives on device %d", dev, s.device);
+    double* part = s.d_scratch;
+    double* totals = s.d_scratch + (int64_t)DCLBM_MAX_LEVELS * kBalanceBlocks * 5;
+    for (int l = 0; l < L; ++l) {
+        double* pl = part + (int64_t)l * kBalanceBlocks * 5;
+        s.eng->balance(s, l, pl, kBalanceBlocks);
+        hipLaunchKernelGGL(k_balance_final, dim3(1), dim3(64), 0, s.stream, pl, kBalanceBlocks, totals + 5 * l);
+    }
+    hipLaunchKernelGGL(k_balance_levels, dim3(1), dim3(64), 0, s.stream, totals, L, d_out);
+    HIPCHECK(hipGetLastError());
+    return DCLBM_OK;
 }
 
 dclbm_status dclbm_checkpoint_bytes(const dclbm_sim* sim, size_t* bytes)

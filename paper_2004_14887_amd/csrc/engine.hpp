@@ -143,6 +143,8 @@ struct Sim {
     double* d_partial = nullptr;
     double* d_bal = nullptr;
     int partial_blocks = 1024;
+    int device = -1;                  // device current at creation
+    double* d_scratch = nullptr;      // that device's static scratch array (dclbm_balance_static)
     std::unique_ptr<Engine> eng;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
