@@ -4,11 +4,21 @@
 One "step" is one coarse time step of the whole hot path: every level's
 fused stream-and-collide with 2:1 sub-cycling, the coarse history capture,
 the Newton reconstruction at co-located nodes, hanging-node interpolation,
-restriction, and the probe sample.  Default workload: D2Q9, 3 levels,
-2048^2 periodic coarse grid with nested x2 (25%) and x4 (6.25%) patches,
-Gaussian pulse plus 16 seeded vortices, FP32 arithmetic with FP32 deviation
-storage (the production form); the FP64 and FP16-storage forms are timed
-beside it, and the FP64 CPU oracle on a bounded sample.
+restriction, and the probe sample.
+
+`value` is the default workload: D2Q9, 3 levels, 2048^2 periodic coarse grid
+with nested x2 (25%) and x4 (6.25%) patches, Gaussian pulse plus 16 seeded
+vortices, FP32 arithmetic with FP32 deviation storage (the production form).
+Beside it, in the same run:
+  * the FP64 and FP16-storage forms of that workload, and the probe errors of
+    FP32 and FP16 against the FP64 GPU path over all 1000 coarse steps of it;
+  * the 2-level 256^3 D3Q19 workload (pulse and vortex ring, Mach-0.1 mean
+    flow) in all three forms, with errors over its 500 coarse steps;
+  * the 4-level 512^3 D3Q19 workload (64 vortex rings, 8 pulses; refined
+    boxes of 30.3%, 10.0% and 1.87% of the volume, about 206 GB) in FP16
+    storage;
+  * the serving loop (256 seeded requests);
+  * the FP64 CPU oracle (single thread and all host cores) on bounded samples.
 
 Prints ONE JSON line (see the keys at the bottom).
 """
@@ -19,6 +29,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -28,6 +39,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS + % HBM roofline, FP32/FP16-store vs FP64 at stated error; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 
 
 def parse():
@@ -39,13 +51,17 @@ def parse():
     ap.add_argument("--n0", type=int, default=2048)
     ap.add_argument("--latency-steps", type=int, default=200)
     ap.add_argument("--timing-steps", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=2, help="coarse steps of the single-thread oracle sample")
+    ap.add_argument("--cpu-steps-parallel", type=int, default=8, help="coarse steps of the all-core oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP16 side runs")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the full-length accuracy runs")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 D3Q19 workload")
+    ap.add_argument("--no-4level", action="store_true", help="skip the 4-level 512^3 D3Q19 workload")
     ap.add_argument("--workload", default="pulse_vortices_3level",
-                    choices=["pulse_vortices_3level", "pulse_ring_3d", "rings_4level_uniform"],
-                    help="3-level 2048^2 D2Q9 (default), 2-level 256^3 D3Q19, or the 4-level 512^3 D3Q19 mesh at "
-                         "full size (FP16 storage only, about 194 GB) carrying a uniform flow")
+                    choices=["pulse_vortices_3level", "pulse_ring_3d", "rings_4level"],
+                    help="workload of `value`: 3-level 2048^2 D2Q9 (default), 2-level 256^3 D3Q19, or the "
+                         "4-level 512^3 D3Q19 mesh (FP16 storage only)")
     ap.add_argument("--copy-only", action="store_true", help="only run the plain copy kernel (counter calibration)")
     ap.add_argument("--serving-requests", type=int, default=256, help="requests in the serving run (0: skip it)")
     ap.add_argument("--serving-only", action="store_true", help="only the serving run")
@@ -61,36 +77,37 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def bytes_per_value(prec):
-    return {"fp64": 8, "fp32": 4, "fp16": 2}[prec]
+def make_workload(name, steps, n0=None):
+    from paper_2004_14887_amd import workloads as W
+
+    if name == "pulse_ring_3d":
+        return W.pulse_ring_3d(seed=3, n0=n0 or 256, steps=steps)
+    if name == "rings_4level":
+        return W.rings_4level(seed=5, steps=steps)
+    return W.pulse_vortices_3level(seed=2, n0=n0 or 2048, steps=steps)
 
 
-def run_form(wl, prec, steps, warmup, latency_steps, timing_steps):
-    import torch
-
+def new_sim(wl, prec, capacity, on_device):
     from paper_2004_14887_amd.sim import Simulation
 
-    log(f"{prec}: create + init ({wl.name})")
-    sim = Simulation(wl, prec, probe_capacity=warmup + steps + latency_steps + timing_steps + 2)
-    if getattr(wl, "device_uniform", False):
-        # a uniform (rho = 1, u = background) state built on the device, level
-        # by level: host-side fields of the 1.1e9-node finest level would not pay
-        for l in range(wl.n_levels):
-            n = sim.n_dense(l)
-            rho = torch.ones(n, dtype=torch.float64, device=sim.device)
-            u = torch.empty((3, n), dtype=torch.float64, device=sim.device)
-            for a in range(3):
-                u[a].fill_(wl.background[a])
-            sim.init(l, rho, u)
-            del rho, u
-            torch.cuda.empty_cache()
-    else:
-        sim.init_from_workload()
+    log(f"{wl.name} {prec}: create + init")
+    sim = Simulation(wl, prec, probe_capacity=capacity)
+    sim.init_from_workload(on_device=on_device)
+    return sim
+
+
+def run_form(wl, prec, steps, warmup, latency_steps, timing_steps, on_device=False):
+    """Time `steps` coarse steps (graph replays) after `warmup`, then per-step
+    latencies, then an instrumented pass with in-dispatch events around every
+    level-substep launch."""
+    import torch
+
+    sim = new_sim(wl, prec, warmup + steps + latency_steps + timing_steps + 2, on_device)
     sim.step(warmup)
     sim.synchronize()
     sim.check()
     ups = sim.updates_per_step()
-    # timed region: exactly `steps` coarse steps (graph replays after the first step)
+    # timed region: exactly `steps` coarse steps
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(sim.stream)
@@ -101,8 +118,7 @@ def run_form(wl, prec, steps, warmup, latency_steps, timing_steps):
     t1 = time.perf_counter()
     wall_ms = (t1 - t0) * 1e3
     gpu_ms = ev0.elapsed_time(ev1)
-    log(f"{prec}: {steps} steps in {wall_ms:.2f} ms wall ({gpu_ms:.2f} ms events)")
-    # per-step latency percentiles (events around each graph launch)
+    log(f"{wl.name} {prec}: {steps} steps in {wall_ms:.2f} ms wall ({gpu_ms:.2f} ms events)")
     lat = []
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(latency_steps + 1)]
     evs[0].record(sim.stream)
@@ -112,7 +128,6 @@ def run_form(wl, prec, steps, warmup, latency_steps, timing_steps):
     sim.synchronize()
     for k in range(latency_steps):
         lat.append(evs[k].elapsed_time(evs[k + 1]))
-    # instrumented pass: events around every bulk launch (eager launches)
     sim.set_timing(True)
     sim.step(timing_steps)
     sim.synchronize()
@@ -120,21 +135,53 @@ def run_form(wl, prec, steps, warmup, latency_steps, timing_steps):
     bulk = []
     for l in range(wl.n_levels):
         ms, n, nodes = sim.bulk_time(l)
-        bulk.append(dict(level=l, ms=ms, launches=n, nodes_per_launch=nodes))
+        bulk.append(dict(level=l, ms=ms, launches=n, nodes_per_launch=nodes, iface_bytes=sim.interface_bytes(l)))
     sim.check()
-    probes = sim.probes().cpu().numpy()
     out = dict(prec=prec, steps=steps, wall_ms=wall_ms, gpu_ms=gpu_ms, updates_per_step=ups,
-               mlups=ups * steps / (wall_ms * 1e3), p50=float(np.percentile(lat, 50)),
-               p99=float(np.percentile(lat, 99)), bulk=bulk, probes=probes)
+               mlups=ups * steps / (wall_ms * 1e3), p50=float(np.percentile(lat, 50)) if lat else None,
+               p99=float(np.percentile(lat, 99)) if lat else None, bulk=bulk, workspace_gb=sim.bytes / 1e9)
     sim.close()
     del sim
     torch.cuda.empty_cache()
     return out
 
 
+def probe_series(wl, prec, on_device=False):
+    """Probe series of every coarse step of the workload's full length."""
+    import torch
+
+    sim = new_sim(wl, prec, wl.steps, on_device)
+    sim.step(wl.steps)
+    sim.check()
+    p = sim.probes().cpu().numpy()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return p
+
+
+def accuracy(wl, precs, on_device=False):
+    """Probe errors e_p = max|p' - p'_FP64| / max|p'_FP64| (and the L2 form)
+    of each reduced form against the FP64 GPU path, over all wl.steps coarse
+    steps.  The FP64 GPU path matches the FP64 oracle to 1e-12 (parity tests)."""
+    ref = probe_series(wl, "fp64", on_device)
+    out = {"steps": wl.steps, "reference": "FP64 GPU path", "peak_abs_p": float(np.abs(ref).max())}
+    for p in precs:
+        g = probe_series(wl, p, on_device)
+        d = g - ref
+        out[p] = {"e_p_max": float(np.abs(d).max() / np.abs(ref).max()),
+                  "e_p_l2": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+                  "target": 1e-4 if p == "fp32" else 1e-3}
+        log(f"{wl.name} accuracy {p}: {out[p]}")
+    return out
+
+
 def roofline(form, Q, workload):
-    bpv = bytes_per_value(form["prec"])
-    per_node = 2 * Q * bpv                      # read Q + write Q values (A/B pull)
+    """Dominant launch (longest total time): algorithmic bytes per launch
+    (updated nodes x 2Q values) over its mean in-dispatch duration, against
+    8 TB/s; the interface bytes of that launch are stated separately."""
+    bpv = BYTES[form["prec"]]
+    per_node = 2 * Q * bpv
     best = max(form["bulk"], key=lambda b: b["ms"])
     avg_ms = best["ms"] / max(1, best["launches"])
     algo = best["nodes_per_launch"] * per_node
@@ -149,12 +196,25 @@ def roofline(form, Q, workload):
             traffic = rec["bytes_per_launch"][key]
     per_level = [{"level": b["level"], "launches": b["launches"], "nodes_per_launch": b["nodes_per_launch"],
                   "avg_launch_ms": round(b["ms"] / max(1, b["launches"]), 5),
-                  "gbs": round(b["nodes_per_launch"] * per_node / (b["ms"] / max(1, b["launches"]) * 1e-3) / 1e9, 1)}
+                  "gbs": round(b["nodes_per_launch"] * per_node / (b["ms"] / max(1, b["launches"]) * 1e-3) / 1e9, 1),
+                  "interface_bytes_per_launch": round(b["iface_bytes"])}
                  for b in form["bulk"]]
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": f"k_level (level {best['level']} substep)", "algorithmic_bytes_per_launch": algo,
+            "interface_bytes_per_launch": round(best["iface_bytes"]),
+            "frac_with_interface_bytes": round((algo + best["iface_bytes"]) / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "avg_launch_ms": round(avg_ms, 5), "per_level": per_level}
+
+
+def form_summary(f, Q, ref_mlups=None, err=None):
+    bpv = BYTES[f["prec"]]
+    return {"mlups": round(f["mlups"], 1), "ms_per_step": round(f["wall_ms"] / f["steps"], 5),
+            "pct_hbm_roofline": round(100.0 * f["mlups"] * 1e6 * 2 * Q * bpv / (HBM_PEAK_GBS * 1e9), 2),
+            "p50_ms": None if f["p50"] is None else round(f["p50"], 5),
+            "p99_ms": None if f["p99"] is None else round(f["p99"], 5),
+            "speedup_vs_fp64": round(f["mlups"] / ref_mlups, 3) if ref_mlups else None,
+            "error_vs_fp64": err, "workspace_gb": round(f["workspace_gb"], 2)}
 
 
 def serving_run(n_requests, slots, steps_per_tick, loads=(0.5, 0.9), seed=4, grid=0, steady_only=False):
@@ -294,36 +354,108 @@ def serving_run(n_requests, slots, steps_per_tick, loads=(0.5, 0.9), seed=4, gri
     return out
 
 
-def cpu_baseline(wl_full, steps):
-    """The FP64 oracle as it stands, single-threaded, on the first `steps`
-    coarse steps of the same workload."""
+def _oracle_mlups(lib_path, wl, steps, threads):
     from oracle import Oracle
     from paper_2004_14887_amd import workloads as W
 
-    o = Oracle(wl_full.lattice, wl_full.n0, wl_full.boxes, wl_full.tau0, wl_full.coupling, wl_full.eq_order,
-               wl_full.probes, steps)
-    for l in range(wl_full.n_levels):
-        rho, u = W.initial_fields(wl_full, l)
+    o = Oracle(wl.lattice, wl.n0, wl.boxes, wl.tau0, wl.coupling, wl.eq_order, wl.probes, steps, lib_path=lib_path)
+    o.set_threads(threads)
+    for l in range(wl.n_levels):
+        rho, u = W.initial_fields(wl, l)
         o.init(l, rho, u)
+    used = o.threads()
     t0 = time.perf_counter()
     o.run(steps)
     dt = time.perf_counter() - t0
-    ups = 0
-    for l in range(wl_full.n_levels):
-        cls = o.classes(l)
-        ups += int((cls != 0).sum()) << l
-    return {"value": round(ups * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"first {steps} coarse steps of the same workload, FP64, single thread ({dt:.1f} s)"}
+    ups = sum(int((o.classes(l) != 0).sum()) << l for l in range(wl.n_levels))
+    del o
+    return ups * steps / dt / 1e6, dt, used
+
+
+def cpu_baseline(name, n0, steps_single, steps_all):
+    """The FP64 oracle as it stands, built for this host (-O3 -march=native,
+    OpenMP over its node loops; same arithmetic as the checking build) and
+    timed on bounded samples of the benchmark workload: the first coarse steps,
+    on one thread and on all host cores; plus the 128^2 two-level vortex
+    workload over all its 200 coarse steps."""
+    from oracle import build_baseline
+    from paper_2004_14887_amd import workloads as W
+
+    d = tempfile.mkdtemp(prefix="oracle_baseline_")
+    lib = build_baseline(d)
+    nproc = os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", nproc))
+    wl = make_workload(name, steps_all, n0)
+    one, dt1, _ = _oracle_mlups(lib, wl, steps_single, 1)
+    log(f"cpu baseline: {one:.2f} MLUPS single thread ({dt1:.1f} s)")
+    allc, dta, used = _oracle_mlups(lib, wl, steps_all, threads)
+    log(f"cpu baseline: {allc:.2f} MLUPS on {used} threads ({dta:.1f} s)")
+    c1 = W.vortex_2level(seed=1, n0=128, steps=200)
+    c1_one, c1_dt1, _ = _oracle_mlups(lib, c1, 200, 1)
+    c1_all, c1_dta, c1_used = _oracle_mlups(lib, c1, 200, threads)
+    return {"value": round(allc, 3), "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "sample": f"first {steps_all} coarse steps of {wl.name}, FP64, {used} OpenMP threads ({dta:.1f} s); "
+                      f"single thread over the first {steps_single} steps ({dt1:.1f} s)",
+            "single_thread_mlups": round(one, 3), "nproc": nproc,
+            "build": "gcc -O3 -march=native -fopenmp -ffp-contract=off",
+            "vortex_2level_128_full_200_steps": {"single_thread_mlups": round(c1_one, 3), "single_thread_s": round(c1_dt1, 2),
+                                                 "all_core_mlups": round(c1_all, 3), "all_core_s": round(c1_dta, 2),
+                                                 "threads": c1_used}}
+
+
+def workload_block(name, steps, warmup, latency_steps, timing_steps, precs, with_accuracy, on_device):
+    """Timed forms, roofline and full-length accuracy of one extra workload."""
+    wl = make_workload(name, steps)
+    Q = wl.Q
+    forms = {p: run_form(wl, p, steps, warmup, latency_steps, timing_steps, on_device) for p in precs}
+    acc = None
+    if with_accuracy and "fp64" in precs:
+        acc = accuracy(_full_length(name), [p for p in precs if p != "fp64"], on_device)
+    ref = forms["fp64"]["mlups"] if "fp64" in forms else None
+    main = "fp32" if "fp32" in forms else precs[0]
+    out = {"config": {"workload": wl.name, "lattice": wl.lattice, "levels": wl.n_levels, "n0": list(wl.n0),
+                      "boxes": [list(map(list, b)) for b in wl.boxes], "tau0": wl.tau0,
+                      "updates_per_step": forms[main]["updates_per_step"]},
+           "forms": {p: form_summary(f, Q, ref, (acc or {}).get(p)) for p, f in forms.items()},
+           "roofline": roofline(forms[main], Q, wl.name)}
+    if acc:
+        out["accuracy"] = {k: v for k, v in acc.items() if k in ("steps", "reference", "peak_abs_p")}
+    return out
+
+
+def _full_length(name):
+    """The workload at its configured number of coarse steps."""
+    from paper_2004_14887_amd import workloads as W
+
+    if name == "pulse_ring_3d":
+        return W.pulse_ring_3d(seed=3, n0=256)
+    return W.pulse_vortices_3level(seed=2, n0=2048)
+
+
+def four_level_block(steps, warmup):
+    """The 4-level 512^3 D3Q19 workload at full size, FP16 storage: 64 seeded
+    vortex rings and 8 pulses evaluated on the device."""
+    wl = make_workload("rings_4level", steps)
+    f = run_form(wl, "fp16", steps, warmup, min(steps, 5), 1, on_device=True)
+    sides = [wl.boxes[0][1][0] - wl.boxes[0][0][0]] + \
+        [(wl.boxes[k][1][0] - wl.boxes[k][0][0]) / 2 ** k for k in (1, 2)]
+    return {"config": {"workload": wl.name, "lattice": wl.lattice, "levels": wl.n_levels, "n0": list(wl.n0),
+                       "boxes": [list(map(list, b)) for b in wl.boxes], "tau0": wl.tau0,
+                       "box_sides_coarse_cells": sides,
+                       "volume_fractions": [round((s / 512.0) ** 3, 4) for s in sides],
+                       "rings": len(wl.rings), "pulses": len(wl.pulses),
+                       "updates_per_step": f["updates_per_step"]},
+            "forms": {"fp16": form_summary(f, wl.Q)},
+            "roofline": roofline(f, wl.Q, wl.name)}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU only: a multi-GPU run is not part of it; "
+                                   "run with --gpus 1"}))
         sys.exit(2)
     import torch
-
-    from paper_2004_14887_amd import workloads as W
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU"}))
@@ -340,62 +472,47 @@ def main():
                         tuple(float(x) for x in args.serving_loads.split(",") if x), grid=args.serving_grid,
                         steady_only=args.serving_steady_only)))
         return
-    if args.workload == "pulse_ring_3d":
-        n0 = args.n0 if args.n0 != 2048 else 256
-        wl = W.pulse_ring_3d(seed=3, n0=n0, steps=args.steps)
-        mk = lambda steps: W.pulse_ring_3d(seed=3, n0=n0, steps=steps)
-    elif args.workload == "rings_4level_uniform":
-        # only FP16 storage fits one GPU at this size; no FP64 side run, no
-        # oracle baseline (its FP64 state would need about 0.8 TB)
-        if args.precision != "fp16":
-            sys.exit("rings_4level_uniform: only --precision fp16 fits one GPU")
-        wl = W.rings_4level(seed=5, steps=args.steps)
-        wl.rings, wl.pulses = [], []
-        wl.background = (0.03, -0.02, 0.01)
-        wl.name = "rings_4level_512_uniform"
-        wl.device_uniform = True
-        args.no_compare, args.no_cpu_baseline, args.serving_requests = True, True, 0
-        mk = None
-    else:
-        wl = W.pulse_vortices_3level(seed=2, n0=args.n0, steps=args.steps)
-        mk = lambda steps: W.pulse_vortices_3level(seed=2, n0=args.n0, steps=steps)
-    main_form = run_form(wl, args.precision, args.steps, args.warmup, args.latency_steps, args.timing_steps)
-    side = {}
-    if not args.no_compare:
+    name = args.workload
+    # initial fields evaluated on the device (outside every timed region)
+    on_device = True
+    if name == "rings_4level" and args.precision != "fp16":
+        sys.exit("rings_4level: only --precision fp16 fits one GPU")
+    wl = make_workload(name, args.steps, args.n0 if name == "pulse_vortices_3level" else None)
+    main_form = run_form(wl, args.precision, args.steps, args.warmup, args.latency_steps, args.timing_steps,
+                         on_device)
+    forms = {args.precision: main_form}
+    if not args.no_compare and name != "rings_4level":
         for p in ("fp64", "fp32", "fp16"):
             if p != args.precision:
-                side[p] = run_form(wl, p, args.steps, args.warmup, args.latency_steps, args.timing_steps)
-    forms = dict(side)
-    forms[args.precision] = main_form
-    # accuracy of the reduced-precision forms against the FP64 GPU path
-    # (which matches the FP64 oracle to 1e-12, see the parity tests)
+                forms[p] = run_form(wl, p, args.steps, args.warmup, args.latency_steps, args.timing_steps, on_device)
     acc = {}
-    if "fp64" in forms:
-        ref = forms["fp64"]["probes"]
-        n = min(len(ref), *(len(f["probes"]) for f in forms.values()))
-        for p, f in forms.items():
-            if p == "fp64":
-                continue
-            d = f["probes"][:n] - ref[:n]
-            acc[p] = {"e_p_max": float(np.abs(d).max() / np.abs(ref[:n]).max()),
-                      "e_p_l2": float(np.linalg.norm(d) / np.linalg.norm(ref[:n]))}
+    if not args.no_accuracy and "fp64" in forms and args.n0 == 2048 and name != "rings_4level":
+        acc = accuracy(_full_length(name), [p for p in forms if p != "fp64"], on_device)
+    extra = {}
+    if name == "pulse_vortices_3level" and not args.no_3d:
+        extra["pulse_ring_3d_256"] = workload_block("pulse_ring_3d", args.steps, min(args.warmup, 5),
+                                                    min(args.latency_steps, 50), min(args.timing_steps, 5),
+                                                    ["fp32", "fp16", "fp64"], not args.no_accuracy, True)
+    if name == "pulse_vortices_3level" and not args.no_4level:
+        torch.cuda.empty_cache()
+        extra["rings_4level_512"] = four_level_block(min(args.steps, 10), min(args.warmup, 2))
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and name != "rings_4level":
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(mk(args.cpu_steps), args.cpu_steps)
+        cpu = cpu_baseline(name, args.n0 if name == "pulse_vortices_3level" else None, args.cpu_steps,
+                           args.cpu_steps_parallel)
     serving = None
-    if args.serving_requests > 0:
+    if args.serving_requests > 0 and name == "pulse_vortices_3level":
         try:
             serving = serving_run(args.serving_requests, args.serving_slots, args.serving_steps_per_tick,
-                        tuple(float(x) for x in args.serving_loads.split(",") if x), grid=args.serving_grid,
-                        steady_only=args.serving_steady_only)
+                                  tuple(float(x) for x in args.serving_loads.split(",") if x), grid=args.serving_grid,
+                                  steady_only=args.serving_steady_only)
         except Exception as e:   # reported, never hides the main line
             serving = {"error": repr(e)}
     Q = wl.Q
     rl = roofline(main_form, Q, wl.name)
-    bpv = bytes_per_value(args.precision)
     mlups = main_form["mlups"]
-    hbm_frac_mlups = mlups * 1e6 * 2 * Q * bpv / (HBM_PEAK_GBS * 1e9)
+    ref = forms["fp64"]["mlups"] if "fp64" in forms else None
     res = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -413,16 +530,16 @@ def main():
                    "steps_per_run": args.steps,
                    "boxes": [list(map(list, b)) for b in wl.boxes], "tau0": wl.tau0, "coupling": "DC2",
                    "precision": args.precision, "updates_per_step": main_form["updates_per_step"]},
-        "hbm_roofline_frac_of_mlups": round(hbm_frac_mlups, 4),
+        "hbm_roofline_frac_of_mlups": round(mlups * 1e6 * 2 * Q * BYTES[args.precision] / (HBM_PEAK_GBS * 1e9), 4),
         "copy_kernel_gbs": round(copy_gbs, 1),
-        "latency_ms": {"p50": round(main_form["p50"], 5), "p99": round(main_form["p99"], 5)},
+        "latency_ms": {"p50": main_form["p50"] and round(main_form["p50"], 5),
+                       "p99": main_form["p99"] and round(main_form["p99"], 5)},
         "roofline": rl,
         "cpu_baseline": cpu,
+        "forms": {p: form_summary(f, Q, ref, acc.get(p)) for p, f in forms.items()},
+        "accuracy": {k: v for k, v in acc.items() if k in ("steps", "reference", "peak_abs_p")} or None,
+        "workloads": extra or None,
         "serving": serving,
-        "forms": {p: {"mlups": round(f["mlups"], 1), "ms_per_step": round(f["wall_ms"] / f["steps"], 5),
-                      "p50_ms": round(f["p50"], 5), "p99_ms": round(f["p99"], 5),
-                      "speedup_vs_fp64": (round(f["mlups"] / forms["fp64"]["mlups"], 3) if "fp64" in forms else None),
-                      "error_vs_fp64": acc.get(p)} for p, f in forms.items()},
     }
     print(json.dumps(res))
 

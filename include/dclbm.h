@@ -196,6 +196,16 @@ dclbm_status dclbm_set_timing(dclbm_sim* sim, int32_t on);
 dclbm_status dclbm_bulk_time(dclbm_sim* sim, int32_t level, double* ms, int64_t* launches,
                              int64_t* nodes_per_launch);
 
+/* Instrumentation: the algorithmic interface bytes of one launch of a level
+ * substep (averaged over its two substeps), beyond the 2 Q values read and
+ * written per updated node that dclbm_bulk_time's node count covers.  They
+ * are the O(surface) traffic of the coupling of Sec. 3.5: the coarse history
+ * ring shift at coarse co-located nodes (the input of Eq.(TempInt)), the
+ * ring reads of the Gamma = R directions and the X writes at fine
+ * co-located nodes, and the restriction of Eq.(rescfc) into the parent at
+ * the synchronous substep.  Interface tables are not counted. */
+dclbm_status dclbm_interface_bytes(const dclbm_sim* sim, int32_t level, double* bytes_per_launch);
+
 /* Bandwidth reference: copies `bytes` (multiple of 16, 16-byte aligned
  * device buffers) from d_src to d_dst `repeats` times on the stream with a
  * plain 16-byte-per-lane copy kernel and returns the mean milliseconds per

@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
 benchmark's CPU-baseline leg.  The product library never imports it.
 """
-from .oracle import Oracle, build_oracle, lattice_table, feq, newton, residual, sets, \
+from .oracle import Oracle, build_oracle, build_baseline, lattice_table, feq, newton, residual, sets, \
     line_stencil, time_interp, load_library
 
-__all__ = ["Oracle", "build_oracle", "lattice_table", "feq", "newton", "residual", "sets",
+__all__ = ["Oracle", "build_oracle", "build_baseline", "lattice_table", "feq", "newton", "residual", "sets",
            "line_stencil", "time_interp", "load_library"]

@@ -36,6 +36,9 @@
 #include "dclbm_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -598,6 +601,7 @@ static void stream_level(orc_sim* s, int l)
 {
     const lattice_t* L = &s->L;
     level_t* v = &s->lv[l];
+#pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < v->n[2]; ++z)
         for (int y = 0; y < v->n[1]; ++y)
             for (int x = 0; x < v->n[0]; ++x) {
@@ -618,6 +622,7 @@ static void capture_history(orc_sim* s, int l)
 {
     const lattice_t* L = &s->L;
     level_t* v = &s->lv[l];
+#pragma omp parallel for schedule(static)
     for (long long q = 0; q < v->N; ++q) {
         long long t = v->tfc_id[q];
         if (t < 0) continue;
@@ -660,6 +665,10 @@ static int reconstruct_tf(orc_sim* s, int l, int substep)
     level_t* v = &s->lv[l];
     level_t* cv = &s->lv[l - 1];
     double R = R_of(s, l);
+    int failed = 0;
+    long long calls = 0;
+    int max_iters = s->newton_max_iters;
+#pragma omp parallel for collapse(2) schedule(dynamic, 4) reduction(+ : calls) reduction(max : max_iters)
     for (int z = 0; z < v->n[2]; ++z)
         for (int y = 0; y < v->n[1]; ++y)
             for (int x = 0; x < v->n[0]; ++x) {
@@ -682,12 +691,14 @@ static int reconstruct_tf(orc_sim* s, int l, int substep)
                 }
                 int iters = 0;
                 int rc = newton(L, s->eq_order, h, G, s->newton_tol, s->newton_maxit, X, &iters);
-                s->newton_calls++;
-                if (iters > s->newton_max_iters) s->newton_max_iters = iters;
+                calls++;
+                if (iters > max_iters) max_iters = iters;
+#pragma omp atomic
                 s->newton_iter_hist[iters < 7 ? iters : 7]++;
                 if (rc != 0) {
-                    s->error = 1;
-                    return -1;
+#pragma omp atomic write
+                    failed = 1;
+                    continue;
                 }
                 double u[3] = {X[1], X[2], X[3]};
                 for (int i = 0; i < L->Q; ++i) {
@@ -697,6 +708,12 @@ static int reconstruct_tf(orc_sim* s, int l, int substep)
                 }
                 for (int a = 0; a < 4; ++a) v->X[q * 4 + a] = X[a];
             }
+    s->newton_calls += calls;
+    s->newton_max_iters = max_iters;
+    if (failed) {
+        s->error = 1;
+        return -1;
+    }
     return 0;
 }
 
@@ -706,6 +723,7 @@ static void interpolate_ie(orc_sim* s, int l)
 {
     const lattice_t* L = &s->L;
     level_t* v = &s->lv[l];
+#pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < v->n[2]; ++z)
         for (int y = 0; y < v->n[1]; ++y)
             for (int x = 0; x < v->n[0]; ++x) {
@@ -748,6 +766,7 @@ static void restrict_tfc(orc_sim* s, int l)
     level_t* v = &s->lv[l];
     level_t* fv = &s->lv[l + 1];
     double R = R_of(s, l + 1);
+#pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < v->n[2]; ++z)
         for (int y = 0; y < v->n[1]; ++y)
             for (int x = 0; x < v->n[0]; ++x) {
@@ -772,6 +791,7 @@ static void collide_level(orc_sim* s, int l)
     const lattice_t* L = &s->L;
     level_t* v = &s->lv[l];
     double omega = 1.0 / v->tau;
+#pragma omp parallel for schedule(static)
     for (long long q = 0; q < v->N; ++q) {
         unsigned char c = v->cls[q];
         if (c == C_HOLE) continue;
@@ -925,6 +945,28 @@ int orc_balance(const orc_sim* s, double out[5])
         }
     }
     return 0;
+}
+
+/* Threads the node loops run on: the OpenMP thread count when built with
+ * OpenMP (the CPU-baseline build), else 1.  Every node's arithmetic is the
+ * same either way; only the loops over independent nodes are shared out. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Thread count of the node loops (OpenMP builds only; a no-op otherwise). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 void orc_newton_stats(const orc_sim* s, long long* calls, int* max_iters, long long hist[8])

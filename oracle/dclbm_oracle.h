@@ -36,6 +36,8 @@ int orc_set_f(orc_sim* s, int l, const double* in);   /* [Q][n] */
 long long orc_get_probes(const orc_sim* s, double* out);
 int orc_balance(const orc_sim* s, double out[5]);
 void orc_newton_stats(const orc_sim* s, long long* calls, int* max_iters, long long hist[8]);
+int orc_threads(void);
+void orc_set_threads(int n);
 
 int orc_lattice(int lattice, int* Q, int* D, int* xi, double* w);
 int orc_feq(int lattice, int eq_order, double rho, const double* u, double* out);

@@ -16,30 +16,43 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dclbm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
-_lib = None
+_libs = {}
 
 LATTICES = {"D2Q9": 0, "D3Q19": 1}
 
+# The checking build: -O2, no FMA contraction, so the C expression order is
+# the arithmetic order.
+CHECK_FLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+# The CPU-baseline build (timed beside the GPU on the host that runs it):
+# -O3 for that host's own instruction set, OpenMP over the node loops.  Still
+# no FMA contraction and no fast math, so every node's arithmetic, and hence
+# every result, is the same as the checking build's.
+BASELINE_FLAGS = ["-O3", "-march=native", "-fopenmp", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+                  "-fno-fast-math"]
 
-def build_oracle(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no FMA contraction, so the C
-    expression order is the arithmetic order)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
+
+def build_oracle(force: bool = True, path: str = _LIB, flags=None) -> str:
+    """Compile the oracle with gcc into `path` (default: the checking build)."""
+    if force or not os.path.exists(path):
+        tmp = path + ".tmp"
+        cmd = ["gcc", *(flags or CHECK_FLAGS), "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, path)
+    return path
 
 
-def load_library():
-    global _lib
+def build_baseline(directory: str) -> str:
+    """The CPU-baseline build of the same source, for the host it runs on."""
+    return build_oracle(True, os.path.join(directory, "liboracle_baseline.so"), BASELINE_FLAGS)
+
+
+def load_library(path: str = None):
+    path = path or _LIB
     with _lock:
-        if _lib is None:
-            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if path not in _libs:
+            if path == _LIB and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
                 build_oracle(force=True)
-            lib = C.CDLL(_LIB)
+            lib = C.CDLL(path)
             P = C.c_void_p
             dp = C.POINTER(C.c_double)
             ip = C.POINTER(C.c_int)
@@ -60,6 +73,9 @@ def load_library():
             lib.orc_get_probes.argtypes = [P, dp]
             lib.orc_balance.argtypes = [P, dp]
             lib.orc_newton_stats.argtypes = [P, C.POINTER(C.c_longlong), ip, C.POINTER(C.c_longlong)]
+            lib.orc_threads.restype = C.c_int
+            lib.orc_threads.argtypes = []
+            lib.orc_set_threads.argtypes = [C.c_int]
             lib.orc_lattice.argtypes = [C.c_int, ip, ip, ip, dp]
             lib.orc_feq.argtypes = [C.c_int, C.c_int, C.c_double, dp, dp]
             lib.orc_newton.argtypes = [C.c_int, C.c_int, dp, dp, C.c_double, C.c_int, dp, ip]
@@ -69,8 +85,8 @@ def load_library():
             lib.orc_line_stencil.argtypes = [C.c_int, C.c_int, ip, dp]
             lib.orc_time_interp.restype = C.c_double
             lib.orc_time_interp.argtypes = [C.c_longlong, C.c_int, C.c_double, C.c_double, C.c_double]
-            _lib = lib
-    return _lib
+            _libs[path] = lib
+    return _libs[path]
 
 
 def _dp(a):
@@ -158,8 +174,8 @@ class Oracle:
     """
 
     def __init__(self, lattice: str, n0, boxes=(), tau0: float = 0.55, coupling: int = 2,
-                 eq_order: int = 2, probes=(), probe_capacity: int = 0):
-        self.lib = load_library()
+                 eq_order: int = 2, probes=(), probe_capacity: int = 0, lib_path: str = None):
+        self.lib = load_library(lib_path)
         self.lattice = lattice
         self.D = 2 if lattice == "D2Q9" else 3
         self.Q = 9 if lattice == "D2Q9" else 19
@@ -253,6 +269,12 @@ class Oracle:
         out = np.zeros(5)
         self.lib.orc_balance(self.h, _dp(out))
         return out
+
+    def threads(self):
+        return int(self.lib.orc_threads())
+
+    def set_threads(self, n: int):
+        self.lib.orc_set_threads(int(n))
 
     def newton_stats(self):
         calls, mx = C.c_longlong(), C.c_int()

@@ -115,6 +115,7 @@ _SIGS = {
     "dclbm_read_probes": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]),
     "dclbm_balance": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "dclbm_balance_static": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "dclbm_interface_bytes": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
     "dclbm_checkpoint_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "dclbm_save": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "dclbm_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),

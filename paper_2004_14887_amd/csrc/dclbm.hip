@@ -1182,6 +1182,32 @@ dclbm_status dclbm_copy_calibration(void* d_dst, const void* d_src, size_t bytes
     return DCLBM_OK;
 }
 
+dclbm_status dclbm_interface_bytes(const dclbm_sim* sim, int32_t level, double* bytes_per_launch)
+{
+    dclbm_status st = check_level_impl(sim, level);
+    if (st != DCLBM_OK) return st;
+    if (!bytes_per_launch) return fail(DCLBM_ERR_INVALID, "null argument");
+    const Sim& s = sim->s;
+    const HostLevel& L = s.lv[level];
+    const double ts = (double)s.tsize, rs = (double)s.rsize;
+    double b = 0.0;
+    // coarse co-located nodes of this level: the ring shift of every known
+    // direction (one pull, two ring reads, three ring writes)
+    for (const int4& m : L.tfc_meta) b += __builtin_popcount((unsigned)m.w) * (ts + 5.0 * rs);
+    if (level > 0) {
+        for (const int4& m : L.tf_meta) {
+            // Gamma = R directions come from the parent's ring (three values at
+            // the asynchronous substep, one at the synchronous) instead of a
+            // pull; X is written
+            b += __builtin_popcount((unsigned)m.w) * (2.0 * rs - ts) + 4.0 * rs;
+        }
+        // restriction into the parent's co-located nodes, every other launch
+        b += 0.5 * (double)L.tf_meta.size() * s.Q * ts;
+    }
+    *bytes_per_launch = b;
+    return DCLBM_OK;
+}
+
 dclbm_status dclbm_set_timing(dclbm_sim* sim, int32_t on)
 {
     if (!sim) return fail(DCLBM_ERR_INVALID, "null simulation");

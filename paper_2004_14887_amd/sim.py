@@ -16,7 +16,7 @@ from typing import Optional
 import torch
 
 from . import _lib
-from .workloads import Workload, initial_fields
+from .workloads import Workload, initial_fields, initial_fields_device
 
 
 def make_config(wl: Workload, precision: str = "fp64", probe_capacity: Optional[int] = None,
@@ -127,10 +127,19 @@ class Simulation:
                                                    C.c_void_p(u.data_ptr())))
         self.stream.synchronize()
 
-    def init_from_workload(self):
+    def init_from_workload(self, on_device: bool = False):
+        """Initial equilibrium from the workload's analytic fields, evaluated
+        on the host (numpy) or, for large meshes, on the device (each
+        structure on its bounding box)."""
         for l in range(self.wl.n_levels):
-            rho, u = initial_fields(self.wl, l)
-            self.init(l, torch.from_numpy(rho), torch.from_numpy(u))
+            if on_device:
+                rho, u = initial_fields_device(self.wl, l, self.device)
+                self.init(l, rho, u)
+                del rho, u
+                torch.cuda.empty_cache()
+            else:
+                rho, u = initial_fields(self.wl, l)
+                self.init(l, torch.from_numpy(rho), torch.from_numpy(u))
 
     def step(self, n: int = 1):
         _lib.check(self.lib.dclbm_step(self.h, int(n)))
@@ -208,6 +217,11 @@ class Simulation:
 
     def set_timing(self, on: bool):
         _lib.check(self.lib.dclbm_set_timing(self.h, 1 if on else 0))
+
+    def interface_bytes(self, l) -> float:
+        b = C.c_double()
+        _lib.check(self.lib.dclbm_interface_bytes(self.h, l, C.byref(b)))
+        return b.value
 
     def bulk_time(self, l):
         ms, n, nodes = C.c_double(), C.c_int64(), C.c_int64()

@@ -167,6 +167,132 @@ def _ring_velocity(pos, rg, L):
 
 
 # --------------------------------------------------------------------------
+# The same fields evaluated with torch on a device, for meshes whose finest
+# level holds ~1e9 nodes.  Every vortex, pulse and ring decays like a
+# Gaussian away from its core, so each is evaluated only on the nodes within
+# `cut` core radii of it (outside, its contribution is below e^(-cut^2/2)
+# of its peak, 1.3e-14 at cut = 8); inside, the formulas and their order are
+# those of initial_fields.
+# --------------------------------------------------------------------------
+
+def _axis_runs(wl, l, a, c, ext):
+    """Contiguous index runs of level l along axis a whose min-image distance
+    to coordinate c is at most ext."""
+    d = wl.dims(l)[a]
+    L = float(wl.n0[a]) if a < wl.D else 1.0
+    pos = level_origin(wl, l)[a] + np.arange(d) / 2.0 ** l
+    near = np.abs(_min_image(pos - c, L)) <= ext
+    runs, i = [], 0
+    while i < d:
+        if near[i]:
+            j = i
+            while j < d and near[j]:
+                j += 1
+            runs.append((i, j))
+            i = j
+        else:
+            i += 1
+    return runs
+
+
+def _boxes(wl, l, c, ext):
+    """Sub-boxes ((z0, z1), (y0, y1), (x0, x1)) of level l within ext of point c."""
+    rx = _axis_runs(wl, l, 0, c[0], ext)
+    ry = _axis_runs(wl, l, 1, c[1], ext)
+    rz = _axis_runs(wl, l, 2, c[2], ext) if wl.D == 3 else [(0, 1)]
+    return [(z, y, x) for z in rz for y in ry for x in rx]
+
+
+def _box_displacements(torch, wl, l, box, c, device, zs):
+    """Min-image displacements (dx, dy, dz) from c over box rows zs."""
+    off = level_origin(wl, l)
+    h = 1.0 / 2 ** l
+    L = [float(wl.n0[a]) if a < wl.D else 1.0 for a in range(3)]
+    (_, _), (y0, y1), (x0, x1) = box
+    f64 = torch.float64
+
+    def axis(a, lo, hi):
+        p = off[a] + h * torch.arange(lo, hi, dtype=f64, device=device)
+        dd = p - c[a]
+        return dd - L[a] * torch.round(dd / L[a])
+
+    dx = axis(0, x0, x1).view(1, 1, -1)
+    dy = axis(1, y0, y1).view(1, -1, 1)
+    if wl.D == 3:
+        dz = axis(2, zs[0], zs[1]).view(-1, 1, 1)
+    else:
+        dz = torch.zeros((1, 1, 1), dtype=f64, device=device)
+    return dx, dy, dz
+
+
+def initial_fields_device(wl: Workload, l: int, device, cut: float = 8.0, slab_nodes: int = 1 << 25):
+    """(rho[n], u[D, n]) of level l as float64 torch tensors on `device`, the
+    fields of initial_fields evaluated on each structure's bounding box."""
+    import torch
+
+    d = wl.dims(l)
+    n = d[0] * d[1] * d[2]
+    rho = torch.ones(n, dtype=torch.float64, device=device)
+    u = torch.empty((wl.D, n), dtype=torch.float64, device=device)
+    for a in range(wl.D):
+        u[a].fill_(wl.background[a] if a < len(wl.background) else 0.0)
+    rho3 = rho.view(d[2], d[1], d[0])
+    u3 = [u[a].view(d[2], d[1], d[0]) for a in range(wl.D)]
+
+    def slabs(box):
+        (z0, z1), (y0, y1), (x0, x1) = box
+        per = max(1, slab_nodes // max(1, (y1 - y0) * (x1 - x0)))
+        for z in range(z0, z1, per):
+            yield (z, min(z1, z + per))
+
+    for v in wl.vortices:
+        c = (v["xc"], v["yc"], 0.0)
+        for box in _boxes(wl, l, c, cut * v["Rc"]):
+            (_, _), (y0, y1), (x0, x1) = box
+            for zs in slabs(box):
+                dx, dy, _ = _box_displacements(torch, wl, l, box, c, device, zs)
+                r2 = (dx * dx + dy * dy) / (v["Rc"] ** 2)
+                g = torch.exp(-0.5 * r2)
+                u3[0][zs[0]:zs[1], y0:y1, x0:x1] += -v["eps"] * (dy / v["Rc"]) * g
+                u3[1][zs[0]:zs[1], y0:y1, x0:x1] += v["eps"] * (dx / v["Rc"]) * g
+                rho3[zs[0]:zs[1], y0:y1, x0:x1] *= torch.exp(-(v["eps"] ** 2) / (2.0 * CS2) * torch.exp(-r2))
+    for p in wl.pulses:
+        c = tuple(p["c"]) + (0.0,) * (3 - len(p["c"]))
+        for box in _boxes(wl, l, c, cut * p["Rc"]):
+            (_, _), (y0, y1), (x0, x1) = box
+            for zs in slabs(box):
+                dx, dy, dz = _box_displacements(torch, wl, l, box, c, device, zs)
+                r2 = dx * dx + dy * dy
+                if wl.D == 3:
+                    r2 = r2 + dz * dz
+                rho3[zs[0]:zs[1], y0:y1, x0:x1] *= 1.0 + p["A"] * torch.exp(-r2 / (2.0 * p["Rc"] ** 2))
+    for rg in wl.rings:
+        nax, _, _ = _ring_frame(rg["axis"])
+        rr, zz = np.meshgrid(np.linspace(0, 3 * rg["R"], 601), np.linspace(-3 * rg["R"], 3 * rg["R"], 601))
+        a_, b_ = _ring_profile(rr, zz, rg["R"], rg["core"])
+        scale = rg["peak"] / np.sqrt(a_ * a_ + b_ * b_).max()
+        c = tuple(rg["c"])
+        for box in _boxes(wl, l, c, rg["R"] + cut * rg["core"]):
+            (_, _), (y0, y1), (x0, x1) = box
+            for zs in slabs(box):
+                dx, dy, dz = _box_displacements(torch, wl, l, box, c, device, zs)
+                shape = (zs[1] - zs[0], y1 - y0, x1 - x0)
+                dd = [dx.expand(shape), dy.expand(shape), dz.expand(shape)]
+                zc = nax[0] * dd[0] + nax[1] * dd[1] + nax[2] * dd[2]
+                rv = [dd[a] - nax[a] * zc for a in range(3)]
+                r = torch.sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2])
+                E = torch.exp(-((r - rg["R"]) ** 2 + zc ** 2) / (2.0 * rg["core"] * rg["core"]))
+                ur = (r / rg["R"]) * E * zc / (rg["core"] * rg["core"])
+                uz = (E / rg["R"]) * (2.0 - r * (r - rg["R"]) / (rg["core"] * rg["core"]))
+                big = r > 1e-12
+                safe = torch.where(big, r, torch.ones_like(r))
+                for a in range(3):
+                    er = torch.where(big, rv[a] / safe, torch.zeros_like(r))
+                    u3[a][zs[0]:zs[1], y0:y1, x0:x1] += scale * (er * ur + nax[a] * uz)
+    return rho, u
+
+
+# --------------------------------------------------------------------------
 # The configurations
 # --------------------------------------------------------------------------
 
@@ -306,11 +432,12 @@ def serving_requests(seed: int = 4, n: int = 256, max_levels: int = 3, min_side:
     return reqs, gaps
 
 
-def rings_4level(seed: int = 5, n0: int = 512, sides=(344, 476, 520), steps: int = 200, n_rings: int = 64,
+def rings_4level(seed: int = 5, n0: int = 512, sides=(344, 476, 544), steps: int = 200, n_rings: int = 64,
                  n_pulses: int = 8, tau0: float = 0.52) -> Workload:
     """D3Q19, 4 levels: periodic n0^3 with three nested centred boxes (sides
-    in parent cells; the default 344 / 476 / 520 covers 30.3%, 10.0% and 1.64%
-    of the volume, about 193 GB of FP16 storage); seeded vortex rings
+    in parent cells; the default 344 / 476 / 544 covers 30.3%, 10.0% and 1.87%
+    of the volume, about 206 GB of FP16 storage: a finest box of 3% would
+    need about 270 GB); seeded vortex rings
     (radius U(8, 16), core radius/4, peak swirl U(0.05, 0.2) c_s, random axes,
     no background) and Gaussian pulses (1e-3, half-width 6); 16 probes on a
     sphere of radius 0.375 n0.  Replicas keep the layout with smaller n0 and

@@ -193,16 +193,20 @@ def test_fp32_probe_error_within_1e_4():
     assert e <= 1e-4
 
 
+FP16_FLOOR = ("binary16 storage of 256 (f - E) misses the 1e-3 target where a probe sits near a Mach-0.05-0.2 "
+              "vortex: the probe density sums nine stored values whose rounding step is 2^-11 of |f - E| ~ 0.02; "
+              "about 14 mantissa bits would be needed")
+
+
 @requires_gpu
-def test_fp16_storage_probe_error_is_bounded():
-    """FP16 storage of 256 (f - w): the stated target 1e-3 is NOT met (FP16's
-    2^-11 relative step accumulates like sqrt(steps) where vortices make
-    f - w large); this pins the measured level (about 3e-3 on this replica)
-    so that a regression shows."""
+@pytest.mark.xfail(strict=True, reason="measured about 3e-3 on this replica; " + FP16_FLOOR)
+def test_fp16_storage_probe_error_within_1e_3():
+    """FP16 storage of 256 (f - w) against the FP64 oracle on the three-level
+    replica: probe error within 1e-3 of the signal peak (not met)."""
     wl = _three_level_replica(400)
     e = _probe_error(wl, wl.steps, "fp16")
     print(f"fp16 probe error {e:.3e}")
-    assert e <= 6e-3
+    assert e <= 1e-3
 
 
 @requires_gpu
@@ -222,11 +226,23 @@ def test_reduced_precision_with_background_flow():
 
     e32 = err("fp32", None)
     e32_rest = err("fp32", (0.0, 0.0))
-    e16 = err("fp16", None)
-    print(f"background flow: fp32 {e32:.3e} (rest reference {e32_rest:.3e}), fp16 {e16:.3e}")
+    print(f"background flow: fp32 {e32:.3e} (rest reference {e32_rest:.3e})")
     assert e32 <= 1e-4
     assert e32 < e32_rest
-    assert e16 <= 2.5e-2   # measured 1.25e-2: FP16 storage misses 1e-3 here (small probe signal)
+
+
+@requires_gpu
+@pytest.mark.xfail(strict=True, reason="measured about 1.25e-2 (small probe signal); " + FP16_FLOOR)
+def test_fp16_with_background_flow_within_1e_3():
+    """FP16 storage on the vortex pair with a Mach-0.1 mean flow and a pulse,
+    against the FP64 oracle: within 1e-3 (not met)."""
+    wl = W.vortex_2level(seed=1, n0=128, steps=200)
+    wl.pulses = [dict(c=(64.0, 64.0, 0.0), A=1e-3, Rc=6.0)]
+    r = oracle_run(wl, wl.steps).probes()
+    g = gpu_run(wl, wl.steps, "fp16").probes().cpu().numpy()
+    e16 = float(np.abs(g - r).max() / np.abs(r).max())
+    print(f"background flow: fp16 {e16:.3e}")
+    assert e16 <= 1e-3
 
 
 @requires_gpu
@@ -306,16 +322,17 @@ def test_four_levels_d3q19_fp64_parity():
 
 
 @requires_gpu
+@pytest.mark.xfail(strict=True, reason="measured about 1.3e-3; " + FP16_FLOOR)
 def test_four_levels_fp16_storage_against_fp64():
     """FP16 storage on the 4-level replica, 60 coarse steps (480 finest
     substeps), probe error against the FP64 GPU path (which the previous test
-    ties to the oracle): measured and bounded."""
+    ties to the oracle): within 1e-3 (not met)."""
     wl = _four_level_replica(60)
     ref = gpu_run(wl, wl.steps, "fp64").probes().cpu().numpy()
     got = gpu_run(wl, wl.steps, "fp16").probes().cpu().numpy()
     e = float(np.abs(got - ref).max() / np.abs(ref).max())
     print(f"4-level fp16 probe error {e:.3e}")
-    assert e <= 1e-2
+    assert e <= 1e-3
 
 
 @requires_gpu
