@@ -140,7 +140,7 @@ LevelArgs level_args(const Sim& s, int l, int substep, int first, unsigned* grid
         a.series = s.d_series;
         a.counter = s.d_counter;
     }
-    *grid = (unsigned)(a.nb_probe + a.nb_cap + 8 * a.seg_groups + 8 * a.tm.per);
+    *grid = (unsigned)(a.nb_probe + a.nb_cap + 8 * a.seg_groups + bulk_groups(a.tm.per));
     return a;
 }
 
@@ -160,7 +160,7 @@ ProbeArgs probe_args(const Sim& s)
         } else {
             a.buf[p] = L.f[L.parity];
             a.off[p] = pl.off;
-            a.stride[p] = 64;
+            a.stride[p] = (int64_t)1 << L.xsh;
         }
     }
     return a;
@@ -322,6 +322,16 @@ static dclbm_status build_segments(Sim& s, int l)
     return DCLBM_OK;
 }
 
+// Width of a level's row blocks (log2): 64 nodes, one wavefront.  Blocks of
+// 128 and 256 nodes (longer contiguous runs per direction) measured no
+// faster on the 256^3 D3Q19 levels, and waste memory on odd extents.
+static int row_block_shift(int D, const HostLevel& L)
+{
+    (void)D;
+    (void)L;
+    return 6;
+}
+
 dclbm_status build_geometry(Sim& s)
 {
     const dclbm_config& c = s.cfg;
@@ -397,11 +407,12 @@ dclbm_status build_geometry(Sim& s)
         L.tau = tau;
         tau = 2.0 * tau - 0.5;
     }
-    // storage layout per level: 64-node row blocks, Q directions per block
+    // storage layout per level: row blocks of 2^xsh nodes, Q directions per block
     for (int l = 0; l < c.n_levels; ++l) {
         HostLevel& L = s.lv[l];
-        L.nxb = (L.nx + 63) / 64;
-        L.elems = (int64_t)L.nz * L.ny * L.nxb * Q * 64;
+        L.xsh = row_block_shift(D, L);
+        L.nxb = (L.nx + (1 << L.xsh) - 1) >> L.xsh;
+        L.elems = ((int64_t)L.nz * L.ny * L.nxb * Q) << L.xsh;
         int64_t hole = 0;
         if (L.has_child) {
             hole = 1;

@@ -27,6 +27,7 @@ inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 struct HostLevel {
     int nx = 1, ny = 1, nz = 1, nxb = 1;
+    int xsh = 6;                // row blocks of 2^xsh nodes
     int64_t elems = 0;          // storage elements per buffer (Q per node slot, 64-node row blocks)
     int periodic = 0, boundary = 0, has_child = 0;
     int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
@@ -64,6 +65,7 @@ struct HostLevel {
         g.ny = ny;
         g.nz = nz;
         g.nxb = nxb;
+        g.xsh = xsh;
         g.periodic = periodic;
         g.boundary = boundary;
         g.has_child = has_child;
@@ -82,18 +84,21 @@ struct HostLevel {
         return g;
     }
     int64_t n_dense() const { return (int64_t)nx * ny * nz; }
+    // Bulk tiles: 64 x 4 nodes, covering the nodes that can be bulk nodes
+    // (a refined level's own boundary is all interface, so its last x tile
+    // or row group may hold none: a 257-node row needs 4 tiles, not 5)
     TileMap tiles() const
     {
         TileMap m;
-        m.tx = (nx + 63) / 64;
-        m.ty = (ny + 3) / 4;
+        m.tx = ((boundary ? nx - 2 : nx - 1) >> 6) + 1;
+        m.ty = ((boundary ? ny - 2 : ny - 1) >> 2) + 1;
         m.nrows = m.ty * nz;
         m.per = m.tx * ((m.nrows + 7) / 8);
         return m;
     }
     int64_t elem0(int Q, int x, int y, int z) const
     {
-        return (((int64_t)z * ny + y) * nxb + (x >> 6)) * (Q * 64) + (x & 63);
+        return (((int64_t)z * ny + y) * nxb + (x >> xsh)) * ((int64_t)Q << xsh) + (x & ((1 << xsh) - 1));
     }
 };
 

@@ -38,7 +38,7 @@ struct EngineImpl final : Engine {
                 // which the 2-byte loads need to keep enough bytes in flight
                 // (measured 4% faster).  The FP32/FP64 bulk and every 2-D
                 // form measured slower split, so they stay one launch.
-                const unsigned g_bulk = 8u * (unsigned)a.tm.per, g_if = grid - g_bulk;
+                const unsigned g_bulk = (unsigned)bulk_groups(a.tm.per), g_if = grid - g_bulk;
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (s.timing) {
                     s.note(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));

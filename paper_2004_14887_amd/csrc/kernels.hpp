@@ -1,13 +1,14 @@
 // HIP kernels (gfx950) of the direct-coupling refined LBM step.
 //
 // Layout.  Each level keeps two population buffers (A/B).  A buffer is a
-// sequence of 64-node row blocks; inside a block the Q directions follow each
-// other, 64 contiguous values each:
-//     element(i, x, y, z) = ((z*ny + y)*nxb + x/64)*Q*64 + i*64 + x%64
-// A wavefront (64 lanes, one per node of a row block) reads every direction
-// as one coalesced 64-element run, and all Q directions of one row block sit
-// in one contiguous span, which keeps the pull stream's 3^D neighbouring row
-// blocks in few DRAM pages and translation entries.
+// sequence of row blocks of B = 2^xsh nodes (B >= 64, per level); inside a
+// block the Q directions follow each other, B contiguous values each:
+//     element(i, x, y, z) = ((z*ny + y)*nxb + x/B)*Q*B + i*B + x%B
+// A wavefront (64 lanes, one per node of a 64-node piece of a row block)
+// reads every direction as one coalesced 64-element run, and all Q
+// directions of one row block sit in one contiguous span, which keeps the
+// pull stream's 3^D neighbouring row blocks in few DRAM pages and
+// translation entries.
 //
 // One launch per level substep (k_level) runs these kinds of workgroups:
 //   probe     (level 0 only) samples the probes of the previous coarse step;
@@ -97,7 +98,8 @@ struct Form<2> {
 // ---------------------------------------------------------------- level geometry
 struct LevelDev {
     int nx, ny, nz;
-    int nxb;           // 64-node row blocks per row
+    int nxb;           // row blocks per row
+    int xsh;           // a row block holds 2^xsh nodes (>= 64)
     int periodic;      // level 0
     int boundary;      // own box faces are interfaces (level >= 1)
     int has_child;
@@ -199,7 +201,8 @@ __device__ __forceinline__ R recip(R x)
 template <int DIM>
 __device__ __forceinline__ int64_t eoff(const LevelDev& g, int i, int x, int y, int z)
 {
-    return (((int64_t)z * g.ny + y) * g.nxb + (x >> 6)) * (Lat<DIM>::Q * 64) + i * 64 + (x & 63);
+    return (((int64_t)z * g.ny + y) * g.nxb + (x >> g.xsh)) * ((int64_t)Lat<DIM>::Q << g.xsh) +
+           ((int64_t)i << g.xsh) + (x & ((1 << g.xsh) - 1));
 }
 
 template <int DIM>
@@ -300,15 +303,18 @@ struct SegLimits {
 struct TileMap {
     int tx, ty;      // tiles per tile row, 4-row groups per plane
     int nrows;       // tile rows: ty * nz
-    int per;         // workgroups per XCD: tx * ceil(nrows / 8)
+    int per;         // tiles per XCD: tx * ceil(nrows / 8)
 };
+
+// Bulk workgroups of a level: one per tile.
+__host__ __device__ constexpr int bulk_groups(int per) { return 8 * per; }
 
 struct ProbeArgs {
     int n;
     int64_t capacity;
     const void* buf[32];   // storage buffer holding the probe's node
     int64_t off[32];       // element offset of direction 0 of that node
-    int64_t stride[32];    // element distance between directions (64, or nz * ny in a face buffer)
+    int64_t stride[32];    // element distance between directions (the row-block width, or nz * ny in a face buffer)
 };
 
 struct LevelArgs {
@@ -356,12 +362,17 @@ struct LevelArgs {
 };
 
 // A non-finite or non-positive density (a run that has become unstable)
-// latches flag bit 2.  The test costs a compare per node; the atomic runs
-// only on a wave that holds such a node, so every step checks every node.
+// latches flag bit 2.  The test costs a compare per node, so every step
+// checks every node; a wave holding such a node sets the flag from one lane,
+// and only if it is not set yet (a diverged state is NaN everywhere: one
+// atomic per lane would serialise the whole launch on one address).
 template <typename R>
 __device__ __forceinline__ void flag_unstable(R rho, int* flags)
 {
-    if (!(rho > R(0) && rho < R(1e30))) atomicOr(flags, 2);
+    const unsigned long long bad = __ballot(!(rho > R(0) && rho < R(1e30)));
+    if (bad != 0ull && __lane_id() == (unsigned)(__ffsll((unsigned long long)bad) - 1)) {
+        if (!(__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2)) atomicOr(flags, 2);
+    }
 }
 
 template <int DIM, int P>
@@ -573,30 +584,34 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
     }
 }
 
-template <int DIM, int EQ, int P>
-__device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
+// Bulk tile bb (64 x 4 nodes), first half: the node's pull-stream loads.
+// Returns false for lanes without a bulk node (beyond the level, interface
+// nodes, holes), which load nothing.
+template <int DIM, int P>
+__device__ __forceinline__ bool bulk_load(const LevelArgs& a, int bb, typename Form<P>::R s[], int64_t& e0)
 {
     using F = Form<P>;
     using T = typename F::T;
-    using R = typename F::R;
     constexpr int Q = Lat<DIM>::Q;
     const TileMap& tm = a.tm;
     const int m = bb >> 3;
     const int rr = m / tm.tx;
     const int row = (bb & 7) + 8 * rr;
-    if (row >= tm.nrows) return;
+    if (row >= tm.nrows) return false;
     const int z = row / tm.ty;
     const int ty = row - z * tm.ty;
     const int x = (m - rr * tm.tx) * 64 + (threadIdx.x & 63);
     const int y = ty * 4 + (threadIdx.x >> 6);
     const LevelDev& g = a.g;
-    if (x >= g.nx || y >= g.ny) return;
-    if (is_interface_or_hole<DIM>(g, x, y, z)) return;
+    if (x >= g.nx || y >= g.ny) return false;
+    if (is_interface_or_hole<DIM>(g, x, y, z)) return false;
     const T* src = (const T*)a.src;
     // pull sources: the node's element plus per-axis neighbour deltas (the
-    // 64-node x blocks and the periodic wrap of level 0 resolved once per
-    // node), so each direction costs one add
-    constexpr int64_t XQ = (int64_t)Q * 64;
+    // x blocks and the periodic wrap of level 0 resolved once per node), so
+    // each direction costs one add
+    const int xsh = g.xsh, xm1 = (1 << xsh) - 1;
+    const int64_t BX = (int64_t)1 << xsh;
+    const int64_t XQ = (int64_t)Q << xsh;
     const int64_t rowe = (int64_t)g.nxb * XQ, plane = rowe * g.ny;
     int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1, zm = z - 1, zp = z + 1;
     if (g.periodic) {
@@ -609,17 +624,16 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
             zp = zp >= g.nz ? zp - g.nz : zp;
         }
     }
-    const int64_t ex = (int64_t)(x >> 6) * XQ + (x & 63);
+    const int64_t ex = (int64_t)(x >> xsh) * XQ + (x & xm1);
     // index c + 1 for xi component c: the source is at coordinate - c
-    const int64_t dx[3] = {(int64_t)(xp >> 6) * XQ + (xp & 63) - ex, 0, (int64_t)(xm >> 6) * XQ + (xm & 63) - ex};
+    const int64_t dx[3] = {(int64_t)(xp >> xsh) * XQ + (xp & xm1) - ex, 0, (int64_t)(xm >> xsh) * XQ + (xm & xm1) - ex};
     const int64_t dy[3] = {(int64_t)(yp - y) * rowe, 0, (int64_t)(ym - y) * rowe};
     const int64_t dz[3] = {(int64_t)(zp - z) * plane, 0, (int64_t)(zm - z) * plane};
-    const int64_t e0 = (int64_t)z * plane + (int64_t)y * rowe + ex;
-    R s[Q];
+    e0 = (int64_t)z * plane + (int64_t)y * rowe + ex;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         s[i] = F::load(src + (e0 + dx[cdir<DIM>(i, 0) + 1] + dy[cdir<DIM>(i, 1) + 1] +
-                              (DIM == 3 ? dz[cdir<DIM>(i, 2) + 1] : 0) + i * 64));
+                              (DIM == 3 ? dz[cdir<DIM>(i, 2) + 1] : 0) + i * BX));
     if constexpr (DIM == 3) {
         // next to an x face the +x (x = 1) or -x (x = nx - 2) directions
         // come from the face buffer
@@ -633,6 +647,19 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
                     s[i] = F::load(xs + xfoff<DIM>(g, fx, i, y - cdir<DIM>(i, 1), z - cdir<DIM>(i, 2)));
         }
     }
+    return true;
+}
+
+// Second half: moments, BGK collision and the store of the node's element e0.
+template <int DIM, int EQ, int P>
+__device__ __forceinline__ void bulk_update(const LevelArgs& a, int64_t e0, typename Form<P>::R s[])
+{
+    using F = Form<P>;
+    using T = typename F::T;
+    using R = typename F::R;
+    constexpr int Q = Lat<DIM>::Q;
+    const LevelDev& g = a.g;
+    const int64_t BX = (int64_t)1 << g.xsh;
     constexpr bool SH = F::shifted;
     const Ref<R> rf = ref_of<R>(g);
     R drho, j[3], du[3];
@@ -648,7 +675,16 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
         bgk<DIM, EQ, SH, R>(s, rf, make_mac<DIM, SH, R>(rf, drho, du), R(a.keep));
     T* d = (T*)a.dst + e0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) F::store(d + i * 64, s[i]);
+    for (int i = 0; i < Q; ++i) F::store(d + i * BX, s[i]);
+}
+
+// Fused pull-stream + BGK of bulk tile bb.
+template <int DIM, int EQ, int P>
+__device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
+{
+    typename Form<P>::R s[Lat<DIM>::Q];
+    int64_t e0 = 0;
+    if (bulk_load<DIM, P>(a, bb, s, e0)) bulk_update<DIM, EQ, P>(a, e0, s);
 }
 
 // p' = (rho - 1)/3 in FP64 of every probe (thread p), appended to the series
