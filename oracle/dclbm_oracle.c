@@ -320,6 +320,9 @@ struct orc_sim {
     double newton_tol;
     int newton_maxit;
     double R_override; /* planted-mistake hook for tests; 0 = off */
+    int collision;     /* 0: BGK; 1: H-RR (single periodic level) */
+    double hrr_sigma;  /* weight of the projected part of a_1^(2), Eq.(a12_HRR) */
+    int hrr_psi;       /* cubic Mach correction psi_i of App. A on (1) or off (0) */
     long long newton_calls;
     int newton_max_iters;
     long long newton_iter_hist[8];
@@ -563,6 +566,21 @@ void orc_set_newton(orc_sim* s, double tol, int maxit)
 
 void orc_plant_R(orc_sim* s, double R) { s->R_override = R; }
 
+/* Collision model: 0 BGK, 1 H-RR with weight sigma of the projected part and
+ * the cubic Mach correction on or off.  H-RR is defined here for a single
+ * periodic level (its interface gradients of Sec. 3.3 are not part of the
+ * oracle): returns -1 on a refined mesh. */
+int orc_set_collision(orc_sim* s, int kind, double sigma, int psi_on)
+{
+    if (kind != 0 && kind != 1) return -1;
+    if (kind == 1 && s->nlev != 1) return -1;
+    if (!(sigma >= 0.0 && sigma <= 1.0)) return -1;
+    s->collision = kind;
+    s->hrr_sigma = sigma;
+    s->hrr_psi = psi_on ? 1 : 0;
+    return 0;
+}
+
 /* rescaling factor between level l (fine) and l-1 (coarse), Eq.(fneqResc) */
 static double R_of(const orc_sim* s, int l)
 {
@@ -785,9 +803,131 @@ static void restrict_tfc(orc_sim* s, int l)
             }
 }
 
+/* ------------------------------------------------------------------------- */
+/* H-RR collision, Sec. 2 (one periodic level).  For every node, from the     */
+/* post-streaming populations of the level and its macroscopic fields:       */
+/*   psi_i = w_i/(2c^4) H2_i:(div Psi)            (App. A, Eq.(psi))          */
+/*   a1PR  = sum_i H2_i (f_i - f0_i + psi_i/2)    (Eq.(a1Proj))               */
+/*   a1FD  = -tau rho c^2 (d_b u_a + d_a u_b)     (Eq.(a1FD_scheme))          */
+/*   a1    = sigma a1PR + (1 - sigma) a1FD        (Eq.(a12_HRR))              */
+/*   a1^(3)_aab = 2 u_a a1_ab + u_b a1_aa         (Eq.(a13RR))                */
+/*   f1reg_i = w_i [H2_i:a1/(2c^4) + sum_{a!=b} H3_{i,aab} a1^(3)_aab/(2c^6)] */
+/*   f*_i  = f0_i + (1 - 1/tau) f1reg_i + psi_i/2 (Eq.(LBMscheme_reg))        */
+/* with centred differences over the periodic neighbours (Eq.(PSI_FD)) and   */
+/* Psi the third-order moments of the Maxwell-Boltzmann distribution minus   */
+/* those of the lattice equilibrium: rho u_a^3 on aaa, and in D3Q19          */
+/* rho u_b u_g^2 / 2 on aab (g the third axis) and rho u_x u_y u_z on xyz.   */
+/* ------------------------------------------------------------------------- */
+static double H2(const lattice_t* L, int i, int a, int b)
+{
+    return (double)(L->xi[i][a] * L->xi[i][b]) - (a == b ? L->cs2 : 0.0);
+}
+
+/* Psi_abg at one node from its macroscopic state (symmetric in a, b, g). */
+static double Psi(const lattice_t* L, double rho, const double u[3], int a, int b, int g)
+{
+    int n[3] = {0, 0, 0};
+    n[a]++;
+    n[b]++;
+    n[g]++;
+    if (n[0] == 3 || n[1] == 3 || n[2] == 3) return rho * u[a] * u[a] * u[a];
+    if (L->D == 2) return 0.0;
+    if (n[0] == 1 && n[1] == 1 && n[2] == 1) return rho * u[0] * u[1] * u[2];
+    /* two equal indices: Psi_aab = rho u_b u_g^2 / 2, g the axis not in {a, b} */
+    int dbl = n[0] == 2 ? 0 : (n[1] == 2 ? 1 : 2);
+    int sgl = n[0] == 1 ? 0 : (n[1] == 1 ? 1 : 2);
+    int third = 3 - dbl - sgl;
+    return 0.5 * rho * u[sgl] * u[third] * u[third];
+}
+
+static void collide_level_hrr(orc_sim* s, int l)
+{
+    const lattice_t* L = &s->L;
+    level_t* v = &s->lv[l];
+    const int D = L->D, Q = L->Q;
+    const double c2 = L->cs2, tau = v->tau;
+    double* rho = (double*)malloc(sizeof(double) * v->N);
+    double* u = (double*)malloc(sizeof(double) * v->N * 3);
+    for (long long q = 0; q < v->N; ++q) {
+        const double* pre = v->pre + q * Q;
+        double r = 0.0, j[3] = {0, 0, 0};
+        for (int i = 0; i < Q; ++i) {
+            r += pre[i];
+            for (int a = 0; a < D; ++a) j[a] += L->xi[i][a] * pre[i];
+        }
+        rho[q] = r;
+        for (int a = 0; a < 3; ++a) u[q * 3 + a] = a < D ? j[a] / r : 0.0;
+    }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < v->n[2]; ++z)
+        for (int y = 0; y < v->n[1]; ++y)
+            for (int x = 0; x < v->n[0]; ++x) {
+                const int k[3] = {x, y, z};
+                const long long q = nid(v, x, y, z);
+                const double* pre = v->pre + q * Q;
+                const double* uq = u + q * 3;
+                /* neighbours at -e_g (index 0) and +e_g (index 1), periodic */
+                long long nb[3][2];
+                for (int g = 0; g < 3; ++g)
+                    for (int sgn = 0; sgn < 2; ++sgn) {
+                        int d[3] = {0, 0, 0};
+                        if (g < D) d[g] = sgn ? 1 : -1;
+                        nb[g][sgn] = active_at(L, v, k, d);
+                    }
+                /* velocity gradients du[a][b] = d_b u_a */
+                double du[3][3] = {{0}};
+                for (int a = 0; a < D; ++a)
+                    for (int b = 0; b < D; ++b)
+                        du[a][b] = 0.5 * (u[nb[b][1] * 3 + a] - u[nb[b][0] * 3 + a]);
+                /* divergence of Psi: dPsi[a][b] = sum_g d_g Psi_abg */
+                double dPsi[3][3] = {{0}};
+                if (s->hrr_psi)
+                    for (int a = 0; a < D; ++a)
+                        for (int b = 0; b < D; ++b)
+                            for (int g = 0; g < D; ++g)
+                                dPsi[a][b] += 0.5 * (Psi(L, rho[nb[g][1]], u + nb[g][1] * 3, a, b, g) -
+                                                     Psi(L, rho[nb[g][0]], u + nb[g][0] * 3, a, b, g));
+                double f0[MAXQ], psi[MAXQ], a1[3][3] = {{0}};
+                for (int i = 0; i < Q; ++i) {
+                    f0[i] = feq_i(L, s->eq_order, i, rho[q], uq);
+                    double t = 0.0;
+                    for (int a = 0; a < D; ++a)
+                        for (int b = 0; b < D; ++b) t += H2(L, i, a, b) * dPsi[a][b];
+                    psi[i] = -L->w[i] / (2.0 * c2 * c2) * t;
+                }
+                for (int a = 0; a < D; ++a)
+                    for (int b = 0; b < D; ++b) {
+                        double pr = 0.0;
+                        for (int i = 0; i < Q; ++i) pr += H2(L, i, a, b) * (pre[i] - f0[i] + 0.5 * psi[i]);
+                        const double fd = -tau * rho[q] * c2 * (du[a][b] + du[b][a]);
+                        a1[a][b] = s->hrr_sigma * pr + (1.0 - s->hrr_sigma) * fd;
+                    }
+                for (int i = 0; i < Q; ++i) {
+                    double t2 = 0.0, t3 = 0.0;
+                    for (int a = 0; a < D; ++a)
+                        for (int b = 0; b < D; ++b) t2 += H2(L, i, a, b) * a1[a][b];
+                    for (int a = 0; a < D; ++a)
+                        for (int b = 0; b < D; ++b) {
+                            if (a == b) continue;
+                            const double H3 = (double)(L->xi[i][a] * L->xi[i][a] * L->xi[i][b]) - c2 * L->xi[i][b];
+                            const double a13 = 2.0 * uq[a] * a1[a][b] + uq[b] * a1[a][a];
+                            t3 += H3 * a13;
+                        }
+                    const double f1 = L->w[i] * (t2 / (2.0 * c2 * c2) + t3 / (2.0 * c2 * c2 * c2));
+                    v->f[q * Q + i] = f0[i] + (1.0 - 1.0 / tau) * f1 + 0.5 * psi[i];
+                }
+            }
+    free(rho);
+    free(u);
+}
+
 /* BGK collision of every active node of level l; co-located nodes use X. */
 static void collide_level(orc_sim* s, int l)
 {
+    if (s->collision == 1) {
+        collide_level_hrr(s, l);
+        return;
+    }
     const lattice_t* L = &s->L;
     level_t* v = &s->lv[l];
     double omega = 1.0 / v->tau;

@@ -26,6 +26,7 @@ int orc_level_tau(const orc_sim* s, int l, double* tau);
 int orc_classes(const orc_sim* s, int l, unsigned char* out);
 void orc_set_newton(orc_sim* s, double tol, int maxit);
 void orc_plant_R(orc_sim* s, double R);
+int orc_set_collision(orc_sim* s, int kind, double sigma, int psi_on);
 /* rho: [n], u: [D][n], dense over the level's nodes */
 int orc_init(orc_sim* s, int l, const double* rho, const double* u);
 int orc_run(orc_sim* s, long long n_coarse_steps);

@@ -65,6 +65,7 @@ def load_library(path: str = None):
             lib.orc_classes.argtypes = [P, C.c_int, C.POINTER(C.c_ubyte)]
             lib.orc_set_newton.argtypes = [P, C.c_double, C.c_int]
             lib.orc_plant_R.argtypes = [P, C.c_double]
+            lib.orc_set_collision.argtypes = [P, C.c_int, C.c_double, C.c_int]
             lib.orc_init.argtypes = [P, C.c_int, dp, dp]
             lib.orc_run.argtypes = [P, C.c_longlong]
             for name in ("orc_get_f", "orc_get_pre", "orc_get_x", "orc_set_f"):
@@ -227,6 +228,11 @@ class Oracle:
 
     def plant_R(self, R):
         self.lib.orc_plant_R(self.h, R)
+
+    def set_collision(self, kind: str = "bgk", sigma: float = 0.98, psi: bool = True):
+        """'bgk' or 'hrr' (Sec. 2; one periodic level only)."""
+        if self.lib.orc_set_collision(self.h, {"bgk": 0, "hrr": 1}[kind], float(sigma), int(bool(psi))) != 0:
+            raise ValueError("oracle: invalid collision setting (H-RR needs a single level, 0 <= sigma <= 1)")
 
     def init(self, l, rho, u):
         rho = np.ascontiguousarray(rho, np.float64).reshape(-1)
