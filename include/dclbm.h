@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define DCLBM_ABI_VERSION 2
+#define DCLBM_ABI_VERSION 3
 #define DCLBM_MAX_LEVELS 4
 
 typedef enum {
@@ -61,6 +61,18 @@ typedef enum { DCLBM_FP64 = 0, DCLBM_FP32 = 1, DCLBM_FP32_FP16 = 2 } dclbm_preci
  * "choice_Gamma_fine": DC1 takes P from the fine grid, DC2 from the coarse. */
 typedef enum { DCLBM_DC1 = 1, DCLBM_DC2 = 2 } dclbm_coupling;
 
+/* Collision model.
+ *  BGK:  f* = f0 + (1 - 1/tau)(f - f0) (Eq.(LBMscheme_reg) with f1 = f - f0,
+ *        psi = 0); every mesh.
+ *  HRR:  the hybrid recursive regularised collision of Sec. 2: a_1^(2) of
+ *        Eq.(a12_HRR) mixing the projection of Eq.(a1Proj) (weight sigma)
+ *        and the centred finite differences of Eq.(a1FD_scheme), a_1^(3) of
+ *        Eq.(a13RR), the cubic Mach correction psi_i of App. A (optional).
+ *        Built for a single periodic level (n_levels = 1); its interface
+ *        gradients of Sec. 3.3 are not built, so refined meshes are
+ *        rejected (DCLBM_ERR_INVALID). */
+typedef enum { DCLBM_BGK = 0, DCLBM_HRR = 1 } dclbm_collision;
+
 typedef struct {
     int32_t abi_version;      /* DCLBM_ABI_VERSION */
     int32_t lattice;          /* dclbm_lattice: D2Q9 (Fig. 1 numbering) or D3Q19 (Eq.(xi_i)) */
@@ -82,6 +94,9 @@ typedef struct {
     double newton_tol;        /* 0 -> 1e-12 (FP64) or 2e-6 (FP32 forms); Sec. 3.2 stop rule |dX| < tol */
     double u_ref[3];          /* reference velocity of the reduced-precision storage (ignored by FP64);
                                * |u_ref| below the sound speed; zero: deviations from w_i */
+    int32_t collision;        /* dclbm_collision */
+    double hrr_sigma;         /* HRR: weight of the projected part, 0..1 (0.98 in the paper's runs) */
+    int32_t hrr_psi;          /* HRR: cubic Mach correction of App. A on (1) or off (0) */
 } dclbm_config;
 
 typedef struct dclbm_sim dclbm_sim;

@@ -14,10 +14,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdclbm.so")
 
 MAX_LEVELS = 4
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 LATTICE = {"D2Q9": 0, "D3Q19": 1}
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2}
+COLLISION = {"bgk": 0, "hrr": 1}
 
 STATUS = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "NEWTON", -5: "UNSTABLE", -6: "BUSY"}
 
@@ -46,6 +47,9 @@ class Config(C.Structure):
         ("newton_max_iter", C.c_int32),
         ("newton_tol", C.c_double),
         ("u_ref", C.c_double * 3),
+        ("collision", C.c_int32),
+        ("hrr_sigma", C.c_double),
+        ("hrr_psi", C.c_int32),
     ]
 
 

@@ -345,6 +345,14 @@ dclbm_status build_geometry(Sim& s)
     if (c.n_probes < 0 || c.n_probes > 32) return fail(DCLBM_ERR_INVALID, "n_probes must be in [0, 32]");
     if (c.n_probes > 0 && (!c.h_probe_xyz || c.probe_capacity < 1))
         return fail(DCLBM_ERR_INVALID, "probes need coordinates and a capacity");
+    if (c.collision != DCLBM_BGK && c.collision != DCLBM_HRR) return fail(DCLBM_ERR_INVALID, "unknown collision model %d", c.collision);
+    if (c.collision == DCLBM_HRR) {
+        if (c.n_levels != 1)
+            return fail(DCLBM_ERR_INVALID, "H-RR collision is built for a single periodic level (its interface "
+                                           "gradients are not built)");
+        if (!(c.hrr_sigma >= 0.0 && c.hrr_sigma <= 1.0)) return fail(DCLBM_ERR_INVALID, "hrr_sigma must be in [0, 1]");
+    }
+    s.hrr = c.collision == DCLBM_HRR ? 1 : 0;
     s.D = c.lattice == DCLBM_D2Q9 ? 2 : 3;
     s.Q = s.D == 2 ? 9 : 19;
     s.P = c.precision;
@@ -363,14 +371,20 @@ dclbm_status build_geometry(Sim& s)
     s.lv.assign(c.n_levels, HostLevel());
     for (auto& L : s.lv) {
         for (int a = 0; a < 3; ++a) L.ur[a] = (s.P == 0 || a >= D) ? 0.0 : c.u_ref[a];
-        // w_i (1 + B_i(ur)) and 3 + 9 xi_i.ur of the second-order equilibrium
+        // w_i (1 + B_i(ur)) (with the H3 terms when eq_order = 3) and
+        // 3 + 9 xi_i.ur of the equilibrium in the carried variable
         const double uu = L.ur[0] * L.ur[0] + L.ur[1] * L.ur[1] + L.ur[2] * L.ur[2];
         for (int i = 0; i < Q; ++i) {
             int xi[3];
             dirs(D, i, xi);
             const double cr = xi[0] * L.ur[0] + xi[1] * L.ur[1] + xi[2] * L.ur[2];
             const double w = D == 2 ? Lat<2>::w[i] : Lat<3>::w[i];
-            L.k1[i] = (float)(w * (1.0 + 3.0 * cr + 4.5 * cr * cr - 1.5 * uu));
+            double b3 = 0.0;
+            if (c.eq_order == 3)
+                for (int a = 0; a < D; ++a)
+                    for (int g = 0; g < D; ++g)
+                        if (a != g) b3 += (xi[a] * xi[a] * xi[g] - xi[g] / 3.0) * L.ur[a] * L.ur[a] * L.ur[g];
+            L.k1[i] = (float)(w * (1.0 + 3.0 * cr + 4.5 * cr * cr - 1.5 * uu + 13.5 * b3));
             L.k2[i] = (float)(3.0 + 9.0 * cr);
         }
     }
@@ -575,6 +589,7 @@ dclbm_status build_geometry(Sim& s)
     s.off_flags = take(8);
     s.off_partial = take((int64_t)DCLBM_MAX_LEVELS * s.partial_blocks * 5 * 8);
     s.off_bal = take(DCLBM_MAX_LEVELS * 5 * 8);
+    if (s.hrr) s.off_M = take(4 * s.lv[0].n_dense() * (int64_t)s.rsize);
     s.need_bytes = (size_t)off;
     return DCLBM_OK;
 }
@@ -629,6 +644,7 @@ dclbm_status sim_attach(Sim& s, void* d_workspace, size_t bytes, hipStream_t str
         HIPCHECK(upload(s, s.d_probe_args, s.h_probe_args));
     }
     s.d_flags = s.at<int>(s.off_flags);
+    s.d_M = s.hrr ? (void*)(s.ws + s.off_M) : nullptr;
     s.d_partial = s.at<double>(s.off_partial);
     s.d_bal = s.at<double>(s.off_bal);
     s.eng.reset(make_engine(s.D, s.EQ, s.P));
@@ -805,6 +821,11 @@ static uint64_t config_fingerprint(const Sim& s)
     f.add(s.newton_maxit);
     f.add(s.newton_tol);
     for (int a = 0; a < s.D; ++a) f.add(c.u_ref[a]);
+    f.add(c.collision);
+    if (c.collision == DCLBM_HRR) {
+        f.add(c.hrr_sigma);
+        f.add(c.hrr_psi);
+    }
     f.add((uint64_t)s.need_bytes);
     f.add((uint64_t)s.probe_xyz.size());
     for (int32_t v : s.probe_xyz) f.add(v);
@@ -910,6 +931,8 @@ dclbm_status dclbm_create(const dclbm_config* cfg, void* d_workspace, size_t byt
         s.off_flags = tmp.off_flags;
         s.off_partial = tmp.off_partial;
         s.off_bal = tmp.off_bal;
+        s.hrr = tmp.hrr;
+        s.off_M = tmp.off_M;
     }
     dclbm_status st = sim_attach(s, d_workspace, bytes, (hipStream_t)stream);
     if (st != DCLBM_OK) return st;

@@ -94,6 +94,7 @@ struct HostLevel {
         m.ty = ((boundary ? ny - 2 : ny - 1) >> 2) + 1;
         m.nrows = m.ty * nz;
         m.per = m.tx * ((m.nrows + 7) / 8);
+        m.blk = 1;
         return m;
     }
     int64_t elem0(int Q, int x, int y, int z) const
@@ -148,6 +149,9 @@ struct Sim {
     double* d_partial = nullptr;
     double* d_bal = nullptr;
     int partial_blocks = 1024;
+    int hrr = 0;                      // H-RR collision (single periodic level)
+    int64_t off_M = 0;
+    void* d_M = nullptr;              // [4][n] macroscopic state of level 0 between the two H-RR launches
     int device = -1;                  // device current at creation
     double* d_scratch = nullptr;      // that device's static scratch array (dclbm_balance_static)
     std::unique_ptr<Engine> eng;

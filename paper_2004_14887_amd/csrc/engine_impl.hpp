@@ -29,6 +29,35 @@ struct EngineImpl final : Engine {
     {
         unsigned grid = 0;
         const LevelArgs a = level_args(s, l, substep, first, &grid);
+        if (s.hrr) {
+            // H-RR on one periodic level: macroscopic fields (with the probe
+            // workgroup in front), then the collision
+            HrrArgs h;
+            h.a = a;
+            // each node's macroscopic state is read again by its 2 D axis
+            // neighbours: rows go to the XCDs in slabs of 8 consecutive tile
+            // rows, so the neighbour rows of a tile are read by the same L2
+            h.a.tm.blk = 8;
+            h.a.tm.per = h.a.tm.tx * (((h.a.tm.nrows + 63) / 64) * 8);
+            h.M = s.d_M;
+            h.tau = s.lv[0].tau;
+            h.sigma = s.cfg.hrr_sigma;
+            h.psi = s.cfg.hrr_psi ? 1 : 0;
+            const unsigned g_bulk = (unsigned)bulk_groups(h.a.tm.per);
+            if (s.timing) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                s.note(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+                s.note(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+                hipExtLaunchKernelGGL((k_hrr_macros<DIM, EQ, P>), dim3(a.nb_probe + g_bulk), dim3(kBlock), 0, s.stream, e0,
+                                      nullptr, 0, h);
+                hipExtLaunchKernelGGL((k_hrr_collide<DIM, EQ, P>), dim3(g_bulk), dim3(kBlock), 0, s.stream, nullptr, e1, 0, h);
+                s.tev[l].push_back({e0, e1});
+            } else {
+                hipLaunchKernelGGL((k_hrr_macros<DIM, EQ, P>), dim3(a.nb_probe + g_bulk), dim3(kBlock), 0, s.stream, h);
+                hipLaunchKernelGGL((k_hrr_collide<DIM, EQ, P>), dim3(g_bulk), dim3(kBlock), 0, s.stream, h);
+            }
+            return;
+        }
         if constexpr (DIM == 3 && P == 2) {
             if (s.side) {
                 // 3-D FP16 storage: the bulk on the simulation's stream, the

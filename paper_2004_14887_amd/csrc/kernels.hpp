@@ -105,8 +105,9 @@ struct LevelDev {
     int has_child;
     int clo[3], chi[3];// child box, closed, in this level's node coordinates
     double ur[3];      // reference velocity of the carried variable (shifted forms; 0 for FP64)
-    // per direction, for the second-order shifted equilibrium (host-computed
-    // from ur, the same for every node): w_i (1 + B_i(ur)) and 3 + 9 xi_i.ur
+    // per direction, for the shifted equilibrium (host-computed from ur, the
+    // same for every node): w_i (1 + B_i(ur)) (H3 terms included when the
+    // equilibrium has them) and 3 + 9 xi_i.ur
     float k1[19], k2[19];
     // 3-D refined levels: the x-face nodes (x = 0 and nx - 1) live in their
     // own y-fastest buffers xf[parity], [2][Q][nz][ny] (face x = 0 first), so
@@ -182,6 +183,53 @@ struct EqGradShift2 {
         if (DIM == 2) gr[3] = R(0);
     }
 };
+
+// All Q equilibria of a node in the carried variable, with the node-level
+// products formed once:
+//   shifted: s0_i = drho k1_i + w_i rho (dc (k2_i + 4.5 dc) - 1.5 q
+//                   [+ 13.5 sum_{a!=g} h_{i,ag} (du_a (2 ur_a + du_a) u_g + ur_a^2 du_g)])
+//   FP64:    f0_i = w_i rho (1 + cu (3 + 4.5 cu) - 1.5 u.u [+ 13.5 sum_{a!=g} h_{i,ag} u_a^2 u_g])
+// with dc = xi_i.du, cu = xi_i.u, h_{i,ag} = xi_a^2 xi_g - xi_g/3 (the H3
+// terms of Eq.(fEq_herm) when EQ = 3); the same values as eq_s.
+template <int DIM, int EQ, bool SH, typename R>
+__device__ __forceinline__ void eq_all(const LevelDev& g, const Ref<R>& rf, const Mac<R>& m, R out[])
+{
+    constexpr int Q = Lat<DIM>::Q;
+    const R rho = (SH ? R(1) : R(0)) + m.drho;
+    R T[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            T[a][c] = (EQ == 3 && a != c && a < DIM && c < DIM)
+                          ? (SH ? m.du[a] * (R(2) * rf.ur[a] + m.du[a]) * m.u[c] + rf.ur[a] * rf.ur[a] * m.du[c]
+                                : m.u[a] * m.u[a] * m.u[c])
+                          : R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        R dc = R(0);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            if (cdir<DIM>(i, a) > 0) dc += m.du[a];
+            if (cdir<DIM>(i, a) < 0) dc -= m.du[a];
+        }
+        R b = SH ? dc * (R(g.k2[i]) + R(4.5) * dc) - R(1.5) * m.q : dc * (R(3) + R(4.5) * dc) - R(1.5) * m.uu;
+        if constexpr (EQ == 3) {
+            R t = R(0);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    if (a == c || cdir<DIM>(i, c) == 0) continue;
+                    const R h = (cdir<DIM>(i, a) != 0 ? R(1) : R(0)) - R(1) / R(3);
+                    if (cdir<DIM>(i, c) > 0) t += h * T[a][c];
+                    else t -= h * T[a][c];
+                }
+            b += R(13.5) * t;
+        }
+        out[i] = SH ? m.drho * R(g.k1[i]) + R(Lat<DIM>::w[i]) * rho * b : R(Lat<DIM>::w[i]) * rho * (R(1) + b);
+    }
+}
 
 // Reciprocal: in FP32 the hardware estimate refined by one Newton step
 // (r + r (1 - x r), two FMAs; the bare 1-ulp estimate biases u step after
@@ -304,7 +352,15 @@ struct TileMap {
     int tx, ty;      // tiles per tile row, 4-row groups per plane
     int nrows;       // tile rows: ty * nz
     int per;         // tiles per XCD: tx * ceil(nrows / 8)
+    int blk;         // tile rows dealt to an XCD at a time (1: row by row)
 };
+
+// Tile row of XCD c's rr-th row: rows are dealt to the 8 XCDs in turns of
+// tm.blk consecutive rows (blk = 1 interleaves single rows over the XCDs).
+__device__ __forceinline__ int tile_row(const TileMap& tm, int c, int rr)
+{
+    return tm.blk == 1 ? c + 8 * rr : c * tm.blk + rr % tm.blk + 8 * tm.blk * (rr / tm.blk);
+}
 
 // Bulk workgroups of a level: one per tile.
 __host__ __device__ constexpr int bulk_groups(int per) { return 8 * per; }
@@ -588,7 +644,8 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
 // Returns false for lanes without a bulk node (beyond the level, interface
 // nodes, holes), which load nothing.
 template <int DIM, int P>
-__device__ __forceinline__ bool bulk_load(const LevelArgs& a, int bb, typename Form<P>::R s[], int64_t& e0)
+__device__ __forceinline__ bool bulk_load(const LevelArgs& a, int bb, typename Form<P>::R s[], int64_t& e0,
+                                          int* xyz = nullptr)
 {
     using F = Form<P>;
     using T = typename F::T;
@@ -596,12 +653,17 @@ __device__ __forceinline__ bool bulk_load(const LevelArgs& a, int bb, typename F
     const TileMap& tm = a.tm;
     const int m = bb >> 3;
     const int rr = m / tm.tx;
-    const int row = (bb & 7) + 8 * rr;
+    const int row = tile_row(tm, bb & 7, rr);
     if (row >= tm.nrows) return false;
     const int z = row / tm.ty;
     const int ty = row - z * tm.ty;
     const int x = (m - rr * tm.tx) * 64 + (threadIdx.x & 63);
     const int y = ty * 4 + (threadIdx.x >> 6);
+    if (xyz) {
+        xyz[0] = x;
+        xyz[1] = y;
+        xyz[2] = z;
+    }
     const LevelDev& g = a.g;
     if (x >= g.nx || y >= g.ny) return false;
     if (is_interface_or_hole<DIM>(g, x, y, z)) return false;
@@ -793,6 +855,231 @@ template <int DIM, int EQ, int P>
 __global__ __launch_bounds__(kBlock) void k_level_top(LevelArgs a)
 {
     level_block<DIM, EQ, P, true, false>(a, blockIdx.x, nullptr);
+}
+
+// ---------------------------------------------------------------- H-RR collision (one periodic level)
+// The hybrid recursive regularised collision of Sec. 2 needs the velocity
+// and third-order moment gradients of the post-streaming state, so a step is
+// two launches over the bulk tiles: k_hrr_macros pulls and writes each
+// node's (drho, du) into M; k_hrr_collide pulls again, reads M at the node
+// and its 2 D axis neighbours (centred differences, Eq.(a1FD_scheme),
+// Eq.(PSI_FD)) and collides:
+//   psi_i   = -w_i/(2c^4) H2_i:(div Psi)          (App. A; the sign that
+//             cancels the lattice's missing third-order moments Psi)
+//   a1      = sigma sum_i H2_i (f_i - f0_i + psi_i/2) + (1 - sigma) a1FD
+//   a1FD_ab = -tau rho c^2 (d_b u_a + d_a u_b)
+//   f*_i    = f0_i + (1 - 1/tau) w_i [H2_i:a1/(2c^4)
+//             + sum_{a!=b} H3_{i,aab} (2 u_a a1_ab + u_b a1_aa)/(2c^6)] + psi_i/2
+// with Psi = rho u_a^3 on aaa and, in D3Q19, rho u_b u_g^2/2 on aab (g the
+// remaining axis) and rho u_x u_y u_z on xyz.
+struct HrrArgs {
+    LevelArgs a;          // level 0 of a single simulation: source, destination, tiles, probes, flags
+    void* M;              // [4][n] (drho, du) of every node, arithmetic type, x fastest
+    double tau, sigma;
+    int psi;              // cubic Mach correction on
+};
+
+template <int DIM>
+__device__ __forceinline__ int64_t dense_index(const LevelDev& g, int x, int y, int z)
+{
+    return ((int64_t)z * g.ny + y) * g.nx + x;
+}
+
+// Psi_abg of Eq.(Psi) at one node, for the index pattern (a, b, g).
+template <int DIM, typename R>
+__device__ __forceinline__ R hrr_Psi(int a, int b, int g, R rho, const R u[3])
+{
+    if (a == b && b == g) return rho * u[a] * u[a] * u[a];
+    if (DIM == 2) return R(0);
+    if (a != b && b != g && a != g) return rho * u[0] * u[1] * u[2];
+    const int dbl = a == b ? a : (a == g ? a : b);
+    const int sgl = a == b ? g : (a == g ? b : a);
+    const int third = 3 - dbl - sgl;
+    return R(0.5) * rho * u[sgl] * u[third] * u[third];
+}
+
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(kBlock) void k_hrr_macros(HrrArgs h)
+{
+    using F = Form<P>;
+    using R = typename F::R;
+    constexpr int Q = Lat<DIM>::Q;
+    const LevelArgs& a = h.a;
+    int b = blockIdx.x;
+    if (b < a.nb_probe) {
+        // the previous coarse step's probes, from the state this step reads
+        const int64_t started = a.counter[1];
+        probe_pending<DIM, P>(*a.probe, a.series, a.counter);
+        __syncthreads();
+        if (threadIdx.x == 0) a.counter[1] = started + 1;
+        return;
+    }
+    b -= a.nb_probe;
+    R s[Q];
+    int64_t e0 = 0;
+    int xyz[3];
+    if (!bulk_load<DIM, P>(a, b, s, e0, xyz)) return;
+    const LevelDev& g = a.g;
+    const int x = xyz[0], y = xyz[1], z = xyz[2];
+    constexpr bool SH = F::shifted;
+    const Ref<R> rf = ref_of<R>(g);
+    R drho, j[3], du[3];
+    moments<DIM, R>(s, drho, j);
+    flag_unstable((SH ? R(1) : R(0)) + drho, a.flags);
+    velocity<DIM, SH, R>(rf, drho, j, du);
+    R* M = (R*)h.M;
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz, d = dense_index<DIM>(g, x, y, z);
+    M[d] = drho;
+    M[n + d] = du[0];
+    M[2 * n + d] = du[1];
+    M[3 * n + d] = du[2];
+}
+
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(kBlock) void k_hrr_collide(HrrArgs h)
+{
+    using F = Form<P>;
+    using T = typename F::T;
+    using R = typename F::R;
+    constexpr int Q = Lat<DIM>::Q;
+    constexpr bool SH = F::shifted;
+    const LevelArgs& a = h.a;
+    const int b = blockIdx.x;
+    R s[Q];
+    int64_t e0 = 0;
+    int xyz[3];
+    if (!bulk_load<DIM, P>(a, b, s, e0, xyz)) return;
+    const LevelDev& g = a.g;
+    const int x = xyz[0], y = xyz[1], z = xyz[2];
+    const Ref<R> rf = ref_of<R>(g);
+    const R* M = (const R*)h.M;
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    // this node's macroscopic state (as written by k_hrr_macros from the same pulls)
+    const int64_t d0 = dense_index<DIM>(g, x, y, z);
+    R du0[3] = {M[n + d0], M[2 * n + d0], M[3 * n + d0]};
+    const Mac<R> mc = make_mac<DIM, SH, R>(rf, M[d0], du0);
+    const R rho = (SH ? R(1) : R(0)) + mc.drho;
+    // neighbours -e_c (0) and +e_c (1) along each axis, periodic
+    const int p3[3] = {x, y, z}, n3[3] = {g.nx, g.ny, g.nz};
+    R gradu[3][3], dPsi[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gradu[r][c] = dPsi[r][c] = R(0);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        R un[2][3], rn[2];
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+            int q3[3] = {p3[0], p3[1], p3[2]};
+            q3[c] += sg ? 1 : -1;
+            q3[c] = q3[c] < 0 ? q3[c] + n3[c] : (q3[c] >= n3[c] ? q3[c] - n3[c] : q3[c]);
+            const int64_t dn = dense_index<DIM>(g, q3[0], q3[1], q3[2]);
+            rn[sg] = (SH ? R(1) : R(0)) + M[dn];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) un[sg][k] = (k < DIM ? M[(1 + k) * n + dn] : R(0)) + (SH ? rf.ur[k] : R(0));
+        }
+        // d_c u_a (du differences equal u differences)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) gradu[k][c] = R(0.5) * (un[1][k] - un[0][k]);
+        if (h.psi) {
+#pragma unroll
+            for (int p = 0; p < DIM; ++p)
+#pragma unroll
+                for (int q = p; q < DIM; ++q)
+                    dPsi[p][q] += R(0.5) * (hrr_Psi<DIM, R>(p, q, c, rn[1], un[1]) - hrr_Psi<DIM, R>(p, q, c, rn[0], un[0]));
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < DIM; ++p)
+#pragma unroll
+        for (int q = 0; q < p; ++q) dPsi[p][q] = dPsi[q][p];
+    // The Hermite contractions use only the non-zero lattice components
+    // (compile-time), H2_{i,pq} = xi_p xi_q - c^2 delta_pq:
+    //   sum_i H2_{i,pq} x_i = sum_{xi_p xi_q != 0} xi_p xi_q x_i - c^2 delta_pq sum_i x_i
+    //   H2_i : A            = sum_{xi_p, xi_q != 0} xi_p xi_q A_pq - c^2 tr A
+    constexpr R c2 = R(1) / R(3);
+    const R keep = R(a.keep), tau = R(h.tau), sig = R(h.sigma);
+    R trP = R(0);
+#pragma unroll
+    for (int p = 0; p < DIM; ++p) trP += dPsi[p][p];
+    R f0[Q], psi[Q];
+    eq_all<DIM, EQ, SH, R>(g, rf, mc, f0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        R t = -c2 * trP;
+#pragma unroll
+        for (int p = 0; p < DIM; ++p)
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) {
+                const int cc = cdir<DIM>(i, p) * cdir<DIM>(i, q);
+                if (cc == 1) t += dPsi[p][q];
+                if (cc == -1) t -= dPsi[p][q];
+            }
+        psi[i] = h.psi ? -R(Lat<DIM>::w[i]) * R(4.5) * t : R(0);   // w_i / (2 c^4) = 4.5 w_i
+    }
+    // second moments of x_i = s_i - f0_i + psi_i / 2
+    R m0 = R(0), m2[3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) m2[p][q] = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const R xv = s[i] - f0[i] + R(0.5) * psi[i];
+        m0 += xv;
+#pragma unroll
+        for (int p = 0; p < DIM; ++p)
+#pragma unroll
+            for (int q = p; q < DIM; ++q) {
+                const int cc = cdir<DIM>(i, p) * cdir<DIM>(i, q);
+                if (cc == 1) m2[p][q] += xv;
+                if (cc == -1) m2[p][q] -= xv;
+            }
+    }
+    R a1[3][3];
+#pragma unroll
+    for (int p = 0; p < DIM; ++p)
+#pragma unroll
+        for (int q = p; q < DIM; ++q) {
+            const R pr = m2[p][q] - (p == q ? c2 * m0 : R(0));
+            const R fd = -tau * rho * c2 * (gradu[p][q] + gradu[q][p]);
+            a1[p][q] = sig * pr + (R(1) - sig) * fd;
+            a1[q][p] = a1[p][q];
+        }
+    R tr1 = R(0);
+#pragma unroll
+    for (int p = 0; p < DIM; ++p) tr1 += a1[p][p];
+    // a_1^(3)_ppq = 2 u_p a1_pq + u_q a1_pp (Eq.(a13RR)), p != q
+    R A3[3][3];
+#pragma unroll
+    for (int p = 0; p < DIM; ++p)
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) A3[p][q] = p == q ? R(0) : R(2) * mc.u[p] * a1[p][q] + mc.u[q] * a1[p][p];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        R t2 = -c2 * tr1, t3 = R(0);
+#pragma unroll
+        for (int p = 0; p < DIM; ++p)
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) {
+                const int cc = cdir<DIM>(i, p) * cdir<DIM>(i, q);
+                if (cc == 1) t2 += a1[p][q];
+                if (cc == -1) t2 -= a1[p][q];
+                // H3_{i,ppq} = (xi_p^2 - c^2) xi_q, p != q
+                if (p != q && cdir<DIM>(i, q) != 0) {
+                    const R h3 = (cdir<DIM>(i, p) != 0 ? R(1) - c2 : -c2);
+                    if (cdir<DIM>(i, q) > 0) t3 += h3 * A3[p][q];
+                    else t3 -= h3 * A3[p][q];
+                }
+            }
+        const R f1 = R(Lat<DIM>::w[i]) * (R(4.5) * t2 + R(13.5) * t3);   // 1/(2c^4), 1/(2c^6)
+        s[i] = f0[i] + keep * f1 + R(0.5) * psi[i];
+    }
+    T* dst = (T*)a.dst + e0;
+    const int64_t BX = (int64_t)1 << g.xsh;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) F::store(dst + i * BX, s[i]);
 }
 
 // ---------------------------------------------------------------- history ring init

@@ -49,6 +49,9 @@ def make_config(wl: Workload, precision: str = "fp64", probe_capacity: Optional[
     ur = wl.background if u_ref is None else u_ref
     for a in range(3):
         cfg.u_ref[a] = float(ur[a]) if a < len(ur) and a < wl.D else 0.0
+    cfg.collision = _lib.COLLISION[wl.collision]
+    cfg.hrr_sigma = float(wl.hrr_sigma)
+    cfg.hrr_psi = 1 if wl.hrr_psi else 0
     return cfg, probes
 
 

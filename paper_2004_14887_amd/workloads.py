@@ -44,6 +44,9 @@ class Workload:
     pulses: List[dict] = dataclasses.field(default_factory=list)
     rings: List[dict] = dataclasses.field(default_factory=list)      # 3-D vortex rings
     seed: int = 0
+    collision: str = "bgk"            # "bgk" | "hrr" (Sec. 2; single periodic level)
+    hrr_sigma: float = 0.98
+    hrr_psi: bool = True
 
     @property
     def D(self) -> int:

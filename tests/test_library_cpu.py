@@ -121,3 +121,20 @@ def test_checkpoint_entry_points_reject_null_arguments():
     assert lib.dclbm_save(None, None, 0) == -1
     assert lib.dclbm_load(None, None, 0) == -1
     assert "null" in lib.dclbm_last_error().decode()
+
+
+def test_hrr_configuration_validation():
+    _lib()
+    from paper_2004_14887_amd._lib import DclbmError
+    from paper_2004_14887_amd.sim import workspace_bytes
+
+    wl = W.Workload("h", "D3Q19", (16, 16, 16), [], 0.55, 1, collision="hrr")
+    assert workspace_bytes(wl, "fp32") > workspace_bytes(W.Workload("b", "D3Q19", (16, 16, 16), [], 0.55, 1), "fp32")
+    refined = W.vortex_2level(n0=64)
+    refined.collision = "hrr"
+    with pytest.raises(DclbmError) as ei:
+        workspace_bytes(refined)
+    assert "single periodic level" in str(ei.value)
+    wl.hrr_sigma = 1.5
+    with pytest.raises(DclbmError):
+        workspace_bytes(wl)
