@@ -736,19 +736,24 @@ static dclbm_status coarse_step(Sim& s)
     if (s.timing || s.stream == nullptr || !all_first_steps_done(s)) return coarse_step_eager(s);
     const int par = s.lv[0].parity;
     if (!s.gexec[par]) {
-        HIPCHECK(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal));
-        one_coarse_step(s);
+        // the coarse step's launches, recorded from the host state (which
+        // this advances like a launched step), as an explicit graph
+        std::vector<StepRecord> recs;
+        ProbeArgs pa;
+        record_coarse_step(s, recs, pa);
         hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(s.stream, &g);
-        if (e != hipSuccess) return fail(DCLBM_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
-        const dclbm_status ls = launch_status(s, "level substep capture");
-        if (ls != DCLBM_OK) {
-            (void)hipGraphDestroy(g);
-            return ls;
+        HIPCHECK(hipGraphCreate(&g, 0));
+        std::vector<hipGraphNode_t> deps;
+        for (const StepRecord& r : recs) {
+            const hipError_t e = s.eng->add_nodes(s, g, r, deps);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return fail(DCLBM_ERR_HIP, "graph node of level %d: %s", r.level, hipGetErrorString(e));
+            }
         }
         s.graph[par] = g;
         HIPCHECK(hipGraphInstantiate(&s.gexec[par], g, nullptr, nullptr, 0));
-        HIPCHECK(hipGraphLaunch(s.gexec[par], s.stream));   // capture advanced the host state already
+        HIPCHECK(hipGraphLaunch(s.gexec[par], s.stream));   // recording advanced the host state already
         return DCLBM_OK;
     }
     HIPCHECK(hipGraphLaunch(s.gexec[par], s.stream));

@@ -119,6 +119,9 @@ struct Engine {
     // serving: one phase of the resident simulations, and the step tail
     virtual void launch_multi(hipStream_t st, const MultiArgs& m, unsigned grid) = 0;
     virtual void launch_tail(hipStream_t st, const MultiArgs& m, unsigned grid) = 0;
+    // graph construction: the kernel node(s) of one recorded level substep,
+    // each depending on `deps`; on return `deps` holds the new node(s)
+    virtual hipError_t add_nodes(Sim& s, hipGraph_t g, const struct StepRecord& r, std::vector<hipGraphNode_t>& deps) = 0;
 };
 
 struct ProbeLoc {

@@ -32,17 +32,7 @@ struct EngineImpl final : Engine {
         if (s.hrr) {
             // H-RR on one periodic level: macroscopic fields (with the probe
             // workgroup in front), then the collision
-            HrrArgs h;
-            h.a = a;
-            // each node's macroscopic state is read again by its 2 D axis
-            // neighbours: rows go to the XCDs in slabs of 8 consecutive tile
-            // rows, so the neighbour rows of a tile are read by the same L2
-            h.a.tm.blk = 8;
-            h.a.tm.per = h.a.tm.tx * (((h.a.tm.nrows + 63) / 64) * 8);
-            h.M = s.d_M;
-            h.tau = s.lv[0].tau;
-            h.sigma = s.cfg.hrr_sigma;
-            h.psi = s.cfg.hrr_psi ? 1 : 0;
+            const HrrArgs h = hrr_args(s, a);
             const unsigned g_bulk = (unsigned)bulk_groups(h.a.tm.per);
             if (s.timing) {
                 hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -60,9 +50,10 @@ struct EngineImpl final : Engine {
         }
         if constexpr (DIM == 3 && P == 2) {
             if (s.side) {
-                // 3-D FP16 storage: the bulk on the simulation's stream, the
-                // interface workgroups beside it on the side stream (fork,
-                // launch both, join).  Alone, the bulk kernel needs 46 VGPRs
+                // 3-D FP16 storage, eager launches (graphs get the same two
+                // kernels as independent nodes, see add_nodes): the bulk on
+                // the simulation's stream, the interface workgroups beside it
+                // on the side stream (fork, launch both, join).  Alone, the bulk kernel needs 46 VGPRs
                 // instead of 110 and runs at 8 waves per SIMD instead of 4,
                 // which the 2-byte loads need to keep enough bytes in flight
                 // (measured 4% faster).  The FP32/FP64 bulk and every 2-D
@@ -112,6 +103,79 @@ struct EngineImpl final : Engine {
         } else {
             hipLaunchKernelGGL((k_level<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, a);
         }
+    }
+    // The same launches as level_step, as graph nodes with explicit
+    // dependencies (no stream capture, so no events or side stream take part
+    // in building a graph): one node per launch in a chain, except the two
+    // kernels of a split 3-D FP16 substep, which both depend on the previous
+    // node(s) and not on each other.
+    static hipError_t kernel_node(hipGraph_t g, const void* func, unsigned grid, void* args,
+                                  const std::vector<hipGraphNode_t>& deps, hipGraphNode_t* out)
+    {
+        hipKernelNodeParams p;
+        memset(&p, 0, sizeof(p));
+        void* params[1] = {args};
+        p.func = const_cast<void*>(func);
+        p.gridDim = dim3(grid);
+        p.blockDim = dim3(kBlock);
+        p.sharedMemBytes = 0;
+        p.kernelParams = params;
+        p.extra = nullptr;
+        return hipGraphAddKernelNode(out, g, deps.empty() ? nullptr : deps.data(), deps.size(), &p);
+    }
+    hipError_t add_nodes(Sim& s, hipGraph_t g, const StepRecord& r, std::vector<hipGraphNode_t>& deps) override
+    {
+        LevelArgs a = r.args;
+        hipGraphNode_t n0 = nullptr, n1 = nullptr;
+        hipError_t e = hipSuccess;
+        if (s.hrr) {
+            HrrArgs h = hrr_args(s, a);
+            const unsigned g_bulk = (unsigned)bulk_groups(h.a.tm.per);
+            e = kernel_node(g, reinterpret_cast<const void*>(&k_hrr_macros<DIM, EQ, P>), a.nb_probe + g_bulk, &h, deps, &n0);
+            if (e != hipSuccess) return e;
+            e = kernel_node(g, reinterpret_cast<const void*>(&k_hrr_collide<DIM, EQ, P>), g_bulk, &h, {n0}, &n1);
+            deps.assign(1, n1);
+            return e;
+        }
+        if constexpr (DIM == 3 && P == 2) {
+            if (s.side) {
+                const unsigned g_bulk = (unsigned)bulk_groups(a.tm.per), g_if = r.grid - g_bulk;
+                std::vector<hipGraphNode_t> out;
+                if (g_if > 0) {
+                    e = kernel_node(g, reinterpret_cast<const void*>(&k_iface<DIM, EQ, P>), g_if, &a, deps, &n0);
+                    if (e != hipSuccess) return e;
+                    out.push_back(n0);
+                }
+                if (g_bulk > 0) {
+                    e = kernel_node(g, reinterpret_cast<const void*>(&k_bulk<DIM, EQ, P>), g_bulk, &a, deps, &n1);
+                    if (e != hipSuccess) return e;
+                    out.push_back(n1);
+                }
+                deps = out;
+                return hipSuccess;
+            }
+        }
+        const bool top = DIM == 2 && P == 2 && a.nb_seg == 0;
+        const void* f = top ? reinterpret_cast<const void*>(&k_level_top<DIM, EQ, P>)
+                            : reinterpret_cast<const void*>(&k_level<DIM, EQ, P>);
+        e = kernel_node(g, f, r.grid, &a, deps, &n0);
+        deps.assign(1, n0);
+        return e;
+    }
+    static HrrArgs hrr_args(const Sim& s, const LevelArgs& a)
+    {
+        HrrArgs h;
+        h.a = a;
+        // each node's macroscopic state is read again by its 2 D axis
+        // neighbours: rows go to the XCDs in slabs of 8 consecutive tile
+        // rows, so the neighbour rows of a tile are read by the same L2
+        h.a.tm.blk = 8;
+        h.a.tm.per = h.a.tm.tx * (((h.a.tm.nrows + 63) / 64) * 8);
+        h.M = s.d_M;
+        h.tau = s.lv[0].tau;
+        h.sigma = s.cfg.hrr_sigma;
+        h.psi = s.cfg.hrr_psi ? 1 : 0;
+        return h;
     }
     void probe(Sim& s) override
     {
