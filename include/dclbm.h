@@ -143,14 +143,25 @@ dclbm_status dclbm_read_macros(const dclbm_sim* sim, int32_t level, double* d_rh
  * nodes of a refined level (Sec. 3.2), [4][n] dense, NaN elsewhere. */
 dclbm_status dclbm_read_shared(const dclbm_sim* sim, int32_t level, double* d_out);
 
-/* Probe series p' = (rho - 1)/3, [steps][n_probes] FP64 into d_out (may be
- * NULL to query); *n_steps receives the number of coarse steps recorded
- * (at most probe_capacity).  Synchronises. */
+/* Pressure probes, the "microphones" of Sec. 4.2 (36 pressure probes on a
+ * circle around the source, whose series give the OASPL of the spurious
+ * acoustics).  Reading of the paper: the probe records p' = c_s^2 (rho - 1)
+ * = (rho - 1)/3 from the post-collision populations after each coarse step,
+ * at a level-0 node coordinate, on the finest level whose closed box holds
+ * the point.  Series [steps][n_probes] FP64 into d_out (may be NULL to
+ * query); *n_steps receives the number of coarse steps recorded (at most
+ * probe_capacity).  Synchronises. */
 dclbm_status dclbm_read_probes(const dclbm_sim* sim, double* d_out, int64_t* n_steps);
 
-/* FP64 balances over the nodes each level owns (the finest level containing
- * a point owns it), cell-volume weighted: mass, momentum[3], kinetic energy.
- * Synchronises; also latches DCLBM_ERR_UNSTABLE on a non-finite density. */
+/* FP64 balances of the moments of Eq.(moment_rho) and Eq.(moment_rhoU):
+ * mass sum rho, momentum sum rho u and kinetic energy sum rho |u|^2 / 2
+ * over the nodes each level owns (the finest level containing a point owns
+ * it; the coarse co-located nodes of Sec. 3.2 belong to the finer level),
+ * each node weighted by its cell volume 2^(-D l) (Sec. 3.1: level l has
+ * spacing 2^-l).  The paper reports no balances; they are the conservation
+ * diagnostics of the method (mass is exact on one level and drifts at the
+ * interfaces, whose interpolations do not conserve it).  Synchronises; also
+ * latches DCLBM_ERR_UNSTABLE on a non-finite density. */
 dclbm_status dclbm_balance(dclbm_sim* sim, double h_out[5]);
 
 /* For callers that cannot allocate or synchronise, such as code under HIP
