@@ -322,14 +322,15 @@ static dclbm_status build_segments(Sim& s, int l)
     return DCLBM_OK;
 }
 
-// Width of a level's row blocks (log2): 64 nodes, one wavefront.  Blocks of
-// 128 and 256 nodes (longer contiguous runs per direction) measured no
-// faster on the 256^3 D3Q19 levels, and waste memory on odd extents.
+// Width of a level's row blocks (log2): 64 nodes, one wavefront, the width
+// the bulk role takes as a compile-time constant.  Blocks of 128 and 256
+// nodes (longer contiguous runs per direction) measured no faster on the
+// 256^3 D3Q19 levels, and waste memory on odd extents.
 static int row_block_shift(int D, const HostLevel& L)
 {
     (void)D;
     (void)L;
-    return 6;
+    return kRowShift;
 }
 
 dclbm_status build_geometry(Sim& s)
@@ -425,7 +426,13 @@ dclbm_status build_geometry(Sim& s)
     for (int l = 0; l < c.n_levels; ++l) {
         HostLevel& L = s.lv[l];
         L.xsh = row_block_shift(D, L);
-        L.nxb = (L.nx + (1 << L.xsh) - 1) >> L.xsh;
+        // a 3-D refined level keeps its x = nx - 1 face in the face buffer
+        // (x = 0 keeps an unused slot in block 0), so its rows need only
+        // the blocks of x < nx - 1: a 257-node row takes 4 blocks, the
+        // pitch of a 256-node row (with a fifth block the launches fetched
+        // 12-22% more than the algorithmic bytes and ran 4-5% slower)
+        const int stored = D == 3 && L.boundary ? L.nx - 1 : L.nx;
+        L.nxb = (stored + (1 << L.xsh) - 1) >> L.xsh;
         L.elems = ((int64_t)L.nz * L.ny * L.nxb * Q) << L.xsh;
         int64_t hole = 0;
         if (L.has_child) {
@@ -779,7 +786,8 @@ static dclbm_status check_level_impl(const dclbm_sim* sim, int32_t level)
 // ------------------------------------------------------------------ checkpoints
 // A checkpoint is a 256-byte header followed by the state regions, each at a
 // 256-byte aligned offset, in the order state_regions lists them.
-static constexpr uint64_t kCkptMagic = 0x3130544b504c4344ull;   // "DCLPKT01"
+// "DCLPKT02": the row pitch of 3-D refined levels changed from "01"
+static constexpr uint64_t kCkptMagic = 0x3230544b504c4344ull;   // "DCLPKT02"
 static constexpr int64_t kCkptHeader = 256;
 
 struct CkptHeader {

@@ -96,6 +96,9 @@ struct Form<2> {
 };
 
 // ---------------------------------------------------------------- level geometry
+// Row blocks hold 2^kRowShift nodes (one wavefront of 64) on every level.
+constexpr int kRowShift = 6;
+
 struct LevelDev {
     int nx, ny, nz;
     int nxb;           // row blocks per row
@@ -422,13 +425,18 @@ struct LevelArgs {
 // checks every node; a wave holding such a node sets the flag from one lane,
 // and only if it is not set yet (a diverged state is NaN everywhere: one
 // atomic per lane would serialise the whole launch on one address).
-template <typename R>
-__device__ __forceinline__ void flag_unstable(R rho, int* flags)
+__device__ __forceinline__ void flag_unstable_if(bool bad_lane, int* flags)
 {
-    const unsigned long long bad = __ballot(!(rho > R(0) && rho < R(1e30)));
+    const unsigned long long bad = __ballot(bad_lane);
     if (bad != 0ull && __lane_id() == (unsigned)(__ffsll((unsigned long long)bad) - 1)) {
         if (!(__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2)) atomicOr(flags, 2);
     }
+}
+
+template <typename R>
+__device__ __forceinline__ void flag_unstable(R rho, int* flags)
+{
+    flag_unstable_if(!(rho > R(0) && rho < R(1e30)), flags);
 }
 
 template <int DIM, int P>
@@ -712,22 +720,19 @@ __device__ __forceinline__ bool bulk_load(const LevelArgs& a, int bb, typename F
     return true;
 }
 
-// Second half: moments, BGK collision and the store of the node's element e0.
+// BGK collision of one bulk node in place (moments, reference velocity
+// split, equilibrium); returns its density.
 template <int DIM, int EQ, int P>
-__device__ __forceinline__ void bulk_update(const LevelArgs& a, int64_t e0, typename Form<P>::R s[])
+__device__ __forceinline__ typename Form<P>::R bulk_collide(const LevelArgs& a, typename Form<P>::R s[])
 {
     using F = Form<P>;
-    using T = typename F::T;
     using R = typename F::R;
-    constexpr int Q = Lat<DIM>::Q;
     const LevelDev& g = a.g;
-    const int64_t BX = (int64_t)1 << g.xsh;
     constexpr bool SH = F::shifted;
     const Ref<R> rf = ref_of<R>(g);
     R drho, j[3], du[3];
     moments<DIM, R>(s, drho, j);
     const R rho = (SH ? R(1) : R(0)) + drho;
-    flag_unstable(rho, a.flags);
     const R inv = recip<R>(rho);
 #pragma unroll
     for (int c = 0; c < 3; ++c) du[c] = c < DIM ? (SH ? j[c] - drho * rf.ur[c] : j[c]) * inv : R(0);
@@ -735,18 +740,172 @@ __device__ __forceinline__ void bulk_update(const LevelArgs& a, int64_t e0, type
         bgk_shift2<DIM, R>(s, g, drho, du, R(a.keep));
     else
         bgk<DIM, EQ, SH, R>(s, rf, make_mac<DIM, SH, R>(rf, drho, du), R(a.keep));
+    return rho;
+}
+
+// Second half: moments, BGK collision and the store of the node's element e0.
+template <int DIM, int EQ, int P>
+__device__ __forceinline__ void bulk_update(const LevelArgs& a, int64_t e0, typename Form<P>::R s[])
+{
+    using F = Form<P>;
+    using T = typename F::T;
+    constexpr int Q = Lat<DIM>::Q;
+    const int64_t BX = (int64_t)1 << a.g.xsh;
+    flag_unstable(bulk_collide<DIM, EQ, P>(a, s), a.flags);
     T* d = (T*)a.dst + e0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) F::store(d + i * BX, s[i]);
 }
 
-// Fused pull-stream + BGK of bulk tile bb.
+// Raw buffer access through a descriptor (base, size in bytes).  An offset
+// at or past the size loads 0 and stores nothing, without a memory access:
+// lanes without a node pass such an offset instead of branching around the
+// access.
+template <int BYTES>
+struct Buf;
+template <>
+struct Buf<2> {
+    __device__ static __forceinline__ unsigned short ld(__amdgpu_buffer_rsrc_t r, uint32_t o)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, o, 0, 0);
+    }
+    __device__ static __forceinline__ void st_nt(__amdgpu_buffer_rsrc_t r, uint32_t o, unsigned short v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(v, r, o, 0, 2);
+    }
+};
+template <>
+struct Buf<4> {
+    __device__ static __forceinline__ uint32_t ld(__amdgpu_buffer_rsrc_t r, uint32_t o)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0);
+    }
+    __device__ static __forceinline__ void st_nt(__amdgpu_buffer_rsrc_t r, uint32_t o, uint32_t v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, o, 0, 2);
+    }
+};
+template <>
+struct Buf<8> {
+    using V2 = uint32_t __attribute__((ext_vector_type(2)));
+    __device__ static __forceinline__ V2 ld(__amdgpu_buffer_rsrc_t r, uint32_t o)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0);
+    }
+    __device__ static __forceinline__ void st_nt(__amdgpu_buffer_rsrc_t r, uint32_t o, V2 v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, o, 0, 2);
+    }
+};
+
+// Carried value <-> raw storage bits of each form.
+template <int P>
+using RawOf = std::conditional_t<P == 0, Buf<8>::V2, std::conditional_t<P == 1, uint32_t, unsigned short>>;
+template <int P>
+__device__ __forceinline__ typename Form<P>::R from_bits(RawOf<P> b)
+{
+    if constexpr (P == 0) return __builtin_bit_cast(double, b);
+    else if constexpr (P == 1) return __builtin_bit_cast(float, b);
+    else return __half2float(__ushort_as_half(b)) * (1.0f / Form<2>::scale);
+}
+template <int P>
+__device__ __forceinline__ RawOf<P> to_bits(typename Form<P>::R v)
+{
+    if constexpr (P == 0) return __builtin_bit_cast(Buf<8>::V2, v);
+    else if constexpr (P == 1) return __builtin_bit_cast(uint32_t, v);
+    else return __half_as_ushort(__float2half_rn(v * Form<2>::scale));
+}
+
+// Fused pull-stream + BGK of bulk tile bb (64 x 4 nodes, one row of 64
+// nodes per wave).  The row of a wave is the same for all its lanes, so the
+// 3^(D-1) source rows are buffer descriptors in scalar registers; a lane
+// forms the byte offsets of its three x sources (x - 1, x, x + 1, wrapped
+// on level 0) and each direction adds a constant that the load takes as its
+// immediate offset.  No 64-bit address arithmetic per direction, and no
+// branch around a load or store.  The values are those of bulk_load /
+// bulk_update.
 template <int DIM, int EQ, int P>
 __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
 {
-    typename Form<P>::R s[Lat<DIM>::Q];
-    int64_t e0 = 0;
-    if (bulk_load<DIM, P>(a, bb, s, e0)) bulk_update<DIM, EQ, P>(a, e0, s);
+    using F = Form<P>;
+    using T = typename F::T;
+    using R = typename F::R;
+    using B = Buf<sizeof(T)>;
+    constexpr int Q = Lat<DIM>::Q;
+    const TileMap& tm = a.tm;
+    const LevelDev& g = a.g;
+    const int m = bb >> 3;
+    const int rr = m / tm.tx;
+    const int row = tile_row(tm, bb & 7, rr);
+    if (row >= tm.nrows) return;                              // whole workgroup
+    const int z = row / tm.ty;
+    const int y = __builtin_amdgcn_readfirstlane((row - z * tm.ty) * 4 + (int)(threadIdx.x >> 6));
+    if (y >= g.ny) return;                                    // whole wave
+    const int x = (m - rr * tm.tx) * 64 + (int)(threadIdx.x & 63);
+    const bool v = x < g.nx && !is_interface_or_hole<DIM>(g, x, y, z);
+    if (__ballot(v) == 0ull) return;                          // whole wave
+    // 64-node row blocks (the level's xsh): a compile-time width, so that
+    // each direction's offset is an immediate of the access
+    constexpr int xsh = kRowShift, xm1 = (1 << xsh) - 1;
+    const int64_t XQ = (int64_t)Q << xsh;
+    const int64_t rowe = (int64_t)g.nxb * XQ;                 // elements per row
+    const int rbytes = (int)(rowe * (int64_t)sizeof(T));
+    const int none = rbytes;                                  // past the row
+    // a wave with a bulk node lies inside a refined level; level 0 wraps
+    int ys[3] = {y + 1, y, y - 1}, zs[3] = {z + 1, z, z - 1}; // source of xi = c at index c + 1
+    int xs[3] = {x + 1, x, x - 1};
+    if (g.periodic) {
+#pragma unroll
+        for (int k = 0; k < 3; k += 2) {
+            ys[k] = ys[k] < 0 ? ys[k] + g.ny : (ys[k] >= g.ny ? ys[k] - g.ny : ys[k]);
+            zs[k] = zs[k] < 0 ? zs[k] + g.nz : (zs[k] >= g.nz ? zs[k] - g.nz : zs[k]);
+            xs[k] = xs[k] < 0 ? xs[k] + g.nx : (xs[k] >= g.nx ? xs[k] - g.nx : xs[k]);
+        }
+    }
+    int ox[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ox[k] = v ? ((xs[k] >> xsh) * (int)XQ + (xs[k] & xm1)) * (int)sizeof(T) : none;
+    const T* src = (const T*)a.src;
+    auto rsrc = [&](const T* base, int yy, int zz) {
+        return __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(base + ((int64_t)(DIM == 3 ? zz : 0) * g.ny + yy) * rowe), (short)0, rbytes, 0x00020000);
+    };
+    R s[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int cx = cdir<DIM>(i, 0), cy = cdir<DIM>(i, 1), cz = DIM == 3 ? cdir<DIM>(i, 2) : 0;
+        const int o = ox[cx + 1];
+        // none + the direction's constant stays past the row (a row is far
+        // below 2^31 bytes), so it needs no select
+        // (signed: the add cannot wrap, so it folds into the immediate offset)
+        s[i] = from_bits<P>(B::ld(rsrc(src, ys[cy + 1], zs[cz + 1]), (uint32_t)(o + i * ((int)sizeof(T) << xsh))));
+    }
+    if constexpr (DIM == 3) {
+        // next to an x face the +x (x = 1) or -x (x = nx - 2) directions
+        // come from the face buffer; one arm per face, so that each arm's
+        // direction set is fixed and its loads issue as one batch
+        if (g.xface) {
+            const T* xfb = reinterpret_cast<const T*>(g.xf[a.par]);
+            if (v && x == 1) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    if (cdir<DIM>(i, 0) == 1)
+                        s[i] = F::load(xfb + xfoff<DIM>(g, 0, i, y - cdir<DIM>(i, 1), z - cdir<DIM>(i, 2)));
+            } else if (v && x == g.nx - 2) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    if (cdir<DIM>(i, 0) == -1)
+                        s[i] = F::load(xfb + xfoff<DIM>(g, g.nx - 1, i, y - cdir<DIM>(i, 1), z - cdir<DIM>(i, 2)));
+            }
+        }
+    }
+    const R rho = bulk_collide<DIM, EQ, P>(a, s);
+    flag_unstable_if(v && !(rho > R(0) && rho < R(1e30)), a.flags);
+    const __amdgpu_buffer_rsrc_t rd = rsrc((const T*)a.dst, y, z);
+    const int od = ox[1];
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        B::st_nt(rd, (uint32_t)(od + i * ((int)sizeof(T) << xsh)), to_bits<P>(s[i]));
 }
 
 // p' = (rho - 1)/3 in FP64 of every probe (thread p), appended to the series
