@@ -806,7 +806,8 @@ static void restrict_tfc(orc_sim* s, int l)
 /* ------------------------------------------------------------------------- */
 /* H-RR collision, Sec. 2 (one periodic level).  For every node, from the     */
 /* post-streaming populations of the level and its macroscopic fields:       */
-/*   psi_i = w_i/(2c^4) H2_i:(div Psi)            (App. A, Eq.(psi))          */
+/*   psi_i = -w_i/(2c^4) H2_i:(div Psi)           (App. A, Eq.(psi); the     */
+/*           sign that cancels the lattice's missing third-order moments)    */
 /*   a1PR  = sum_i H2_i (f_i - f0_i + psi_i/2)    (Eq.(a1Proj))               */
 /*   a1FD  = -tau rho c^2 (d_b u_a + d_a u_b)     (Eq.(a1FD_scheme))          */
 /*   a1    = sigma a1PR + (1 - sigma) a1FD        (Eq.(a12_HRR))              */

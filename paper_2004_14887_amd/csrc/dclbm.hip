@@ -140,7 +140,7 @@ LevelArgs level_args(const Sim& s, int l, int substep, int first, unsigned* grid
         a.series = s.d_series;
         a.counter = s.d_counter;
     }
-    *grid = (unsigned)(a.nb_probe + a.nb_cap + 8 * a.seg_groups + bulk_groups(a.tm.per));
+    *grid = (unsigned)(a.nb_probe + a.nb_cap + 8 * a.seg_groups + bulk_groups(a.tm.per, bulk_k(s.D, s.P)));
     return a;
 }
 

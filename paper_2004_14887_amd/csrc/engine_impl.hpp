@@ -33,7 +33,7 @@ struct EngineImpl final : Engine {
             // H-RR on one periodic level: macroscopic fields (with the probe
             // workgroup in front), then the collision
             const HrrArgs h = hrr_args(s, a);
-            const unsigned g_bulk = (unsigned)bulk_groups(h.a.tm.per);
+            const unsigned g_bulk = (unsigned)bulk_groups(h.a.tm.per, 1);
             if (s.timing) {
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 s.note(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
@@ -58,7 +58,7 @@ struct EngineImpl final : Engine {
                 // which the 2-byte loads need to keep enough bytes in flight
                 // (measured 4% faster).  The FP32/FP64 bulk and every 2-D
                 // form measured slower split, so they stay one launch.
-                const unsigned g_bulk = (unsigned)bulk_groups(a.tm.per), g_if = grid - g_bulk;
+                const unsigned g_bulk = (unsigned)bulk_groups(a.tm.per, bulk_k(DIM, P)), g_if = grid - g_bulk;
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (s.timing) {
                     s.note(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
@@ -130,7 +130,7 @@ struct EngineImpl final : Engine {
         hipError_t e = hipSuccess;
         if (s.hrr) {
             HrrArgs h = hrr_args(s, a);
-            const unsigned g_bulk = (unsigned)bulk_groups(h.a.tm.per);
+            const unsigned g_bulk = (unsigned)bulk_groups(h.a.tm.per, 1);
             e = kernel_node(g, reinterpret_cast<const void*>(&k_hrr_macros<DIM, EQ, P>), a.nb_probe + g_bulk, &h, deps, &n0);
             if (e != hipSuccess) return e;
             e = kernel_node(g, reinterpret_cast<const void*>(&k_hrr_collide<DIM, EQ, P>), g_bulk, &h, {n0}, &n1);
@@ -139,7 +139,7 @@ struct EngineImpl final : Engine {
         }
         if constexpr (DIM == 3 && P == 2) {
             if (s.side) {
-                const unsigned g_bulk = (unsigned)bulk_groups(a.tm.per), g_if = r.grid - g_bulk;
+                const unsigned g_bulk = (unsigned)bulk_groups(a.tm.per, bulk_k(DIM, P)), g_if = r.grid - g_bulk;
                 std::vector<hipGraphNode_t> out;
                 if (g_if > 0) {
                     e = kernel_node(g, reinterpret_cast<const void*>(&k_iface<DIM, EQ, P>), g_if, &a, deps, &n0);

@@ -365,8 +365,8 @@ __device__ __forceinline__ int tile_row(const TileMap& tm, int c, int rr)
     return tm.blk == 1 ? c + 8 * rr : c * tm.blk + rr % tm.blk + 8 * tm.blk * (rr / tm.blk);
 }
 
-// Bulk workgroups of a level: one per tile.
-__host__ __device__ constexpr int bulk_groups(int per) { return 8 * per; }
+// Bulk workgroups of a level with k tiles per workgroup (bulk_k).
+__host__ __device__ constexpr int bulk_groups(int per, int k) { return 8 * ((per + k - 1) / k); }
 
 struct ProbeArgs {
     int n;
@@ -817,33 +817,47 @@ __device__ __forceinline__ RawOf<P> to_bits(typename Form<P>::R v)
 }
 
 // Fused pull-stream + BGK of bulk tile bb (64 x 4 nodes, one row of 64
-// nodes per wave).  The row of a wave is the same for all its lanes, so the
-// 3^(D-1) source rows are buffer descriptors in scalar registers; a lane
-// forms the byte offsets of its three x sources (x - 1, x, x + 1, wrapped
-// on level 0) and each direction adds a constant that the load takes as its
-// immediate offset.  No 64-bit address arithmetic per direction, and no
-// branch around a load or store.  The values are those of bulk_load /
-// bulk_update.
-template <int DIM, int EQ, int P>
-__device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
+// nodes per wave), in parts so that a workgroup can fetch several tiles
+// before it collides the first.  The row of a wave is the same for all its
+// lanes, so the 3^(D-1) source rows are buffer descriptors in scalar
+// registers; a lane forms the byte offsets of its three x sources (x - 1,
+// x, x + 1, wrapped on level 0) and each direction adds a constant that the
+// load takes as its immediate offset.  No 64-bit address arithmetic per
+// direction, and no branch around a load or store: a lane without a bulk
+// node passes offsets past the row, for which the hardware loads 0 and
+// stores nothing.  The values are those of bulk_load / bulk_update.
+template <int DIM, int P>
+struct BulkTile {
+    typename Form<P>::R s[Lat<DIM>::Q];
+    __amdgpu_buffer_rsrc_t rs[DIM == 3 ? 9 : 3];   // source rows (y - cy, z - cz) at (cy + 1) + 3 (cz + 1)
+    __amdgpu_buffer_rsrc_t rd;                       // destination row
+    int ox[3];                                       // byte offsets of x + 1, x, x - 1 (past the row: none)
+    int x, y, z;
+    bool v;                                          // the lane holds a bulk node
+    bool any;                                        // the wave holds one
+};
+
+// Where tile bb's wave reads and writes; tile_ok false makes it a tile
+// without nodes.
+template <int DIM, int P>
+__device__ __forceinline__ void bulk_locate(const LevelArgs& a, int bb, BulkTile<DIM, P>& t, bool tile_ok = true)
 {
-    using F = Form<P>;
-    using T = typename F::T;
-    using R = typename F::R;
-    using B = Buf<sizeof(T)>;
+    using T = typename Form<P>::T;
     constexpr int Q = Lat<DIM>::Q;
     const TileMap& tm = a.tm;
     const LevelDev& g = a.g;
     const int m = bb >> 3;
     const int rr = m / tm.tx;
     const int row = tile_row(tm, bb & 7, rr);
-    if (row >= tm.nrows) return;                              // whole workgroup
-    const int z = row / tm.ty;
-    const int y = __builtin_amdgcn_readfirstlane((row - z * tm.ty) * 4 + (int)(threadIdx.x >> 6));
-    if (y >= g.ny) return;                                    // whole wave
+    const bool in = tile_ok && row < tm.nrows;
+    const int z = in ? row / tm.ty : 0;
+    const int y = __builtin_amdgcn_readfirstlane(in ? (row - z * tm.ty) * 4 + (int)(threadIdx.x >> 6) : 0);
     const int x = (m - rr * tm.tx) * 64 + (int)(threadIdx.x & 63);
-    const bool v = x < g.nx && !is_interface_or_hole<DIM>(g, x, y, z);
-    if (__ballot(v) == 0ull) return;                          // whole wave
+    t.x = x;
+    t.y = y;
+    t.z = z;
+    t.v = in && y < g.ny && x < g.nx && !is_interface_or_hole<DIM>(g, x, y, z);
+    t.any = __ballot(t.v) != 0ull;
     // 64-node row blocks (the level's xsh): a compile-time width, so that
     // each direction's offset is an immediate of the access
     constexpr int xsh = kRowShift, xm1 = (1 << xsh) - 1;
@@ -852,6 +866,7 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
     const int rbytes = (int)(rowe * (int64_t)sizeof(T));
     const int none = rbytes;                                  // past the row
     // a wave with a bulk node lies inside a refined level; level 0 wraps
+    // (the rows of a wave without one are never accessed)
     int ys[3] = {y + 1, y, y - 1}, zs[3] = {z + 1, z, z - 1}; // source of xi = c at index c + 1
     int xs[3] = {x + 1, x, x - 1};
     if (g.periodic) {
@@ -862,23 +877,36 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
             xs[k] = xs[k] < 0 ? xs[k] + g.nx : (xs[k] >= g.nx ? xs[k] - g.nx : xs[k]);
         }
     }
-    int ox[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) ox[k] = v ? ((xs[k] >> xsh) * (int)XQ + (xs[k] & xm1)) * (int)sizeof(T) : none;
-    const T* src = (const T*)a.src;
-    auto rsrc = [&](const T* base, int yy, int zz) {
+    for (int k = 0; k < 3; ++k) t.ox[k] = t.v ? ((xs[k] >> xsh) * (int)XQ + (xs[k] & xm1)) * (int)sizeof(T) : none;
+    auto rsrc = [&](const void* base, int yy, int zz) {
         return __builtin_amdgcn_make_buffer_rsrc(
-            (void*)(base + ((int64_t)(DIM == 3 ? zz : 0) * g.ny + yy) * rowe), (short)0, rbytes, 0x00020000);
+            (void*)((const T*)base + ((int64_t)(DIM == 3 ? zz : 0) * g.ny + yy) * rowe), (short)0, rbytes, 0x00020000);
     };
-    R s[Q];
+#pragma unroll
+    for (int cz = 0; cz < (DIM == 3 ? 3 : 1); ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy) t.rs[cy + 3 * cz] = rsrc(a.src, ys[cy], zs[DIM == 3 ? cz : 1]);
+    t.rd = rsrc(a.dst, ys[1], zs[1]);
+}
+
+// The tile's pull-stream loads.
+template <int DIM, int P>
+__device__ __forceinline__ void bulk_pull(const LevelArgs& a, BulkTile<DIM, P>& t)
+{
+    using F = Form<P>;
+    using T = typename F::T;
+    using B = Buf<sizeof(T)>;
+    constexpr int Q = Lat<DIM>::Q;
+    const LevelDev& g = a.g;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int cx = cdir<DIM>(i, 0), cy = cdir<DIM>(i, 1), cz = DIM == 3 ? cdir<DIM>(i, 2) : 0;
-        const int o = ox[cx + 1];
         // none + the direction's constant stays past the row (a row is far
-        // below 2^31 bytes), so it needs no select
-        // (signed: the add cannot wrap, so it folds into the immediate offset)
-        s[i] = from_bits<P>(B::ld(rsrc(src, ys[cy + 1], zs[cz + 1]), (uint32_t)(o + i * ((int)sizeof(T) << xsh))));
+        // below 2^31 bytes), so it needs no select; signed, the add cannot
+        // wrap and folds into the immediate offset
+        t.s[i] = from_bits<P>(B::ld(t.rs[(cy + 1) + 3 * (cz + 1) * (DIM == 3)],
+                                    (uint32_t)(t.ox[cx + 1] + i * ((int)sizeof(T) << kRowShift))));
     }
     if constexpr (DIM == 3) {
         // next to an x face the +x (x = 1) or -x (x = nx - 2) directions
@@ -886,26 +914,83 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
         // direction set is fixed and its loads issue as one batch
         if (g.xface) {
             const T* xfb = reinterpret_cast<const T*>(g.xf[a.par]);
-            if (v && x == 1) {
+            if (t.v && t.x == 1) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
                     if (cdir<DIM>(i, 0) == 1)
-                        s[i] = F::load(xfb + xfoff<DIM>(g, 0, i, y - cdir<DIM>(i, 1), z - cdir<DIM>(i, 2)));
-            } else if (v && x == g.nx - 2) {
+                        t.s[i] = F::load(xfb + xfoff<DIM>(g, 0, i, t.y - cdir<DIM>(i, 1), t.z - cdir<DIM>(i, 2)));
+            } else if (t.v && t.x == g.nx - 2) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
                     if (cdir<DIM>(i, 0) == -1)
-                        s[i] = F::load(xfb + xfoff<DIM>(g, g.nx - 1, i, y - cdir<DIM>(i, 1), z - cdir<DIM>(i, 2)));
+                        t.s[i] =
+                            F::load(xfb + xfoff<DIM>(g, g.nx - 1, i, t.y - cdir<DIM>(i, 1), t.z - cdir<DIM>(i, 2)));
             }
         }
     }
-    const R rho = bulk_collide<DIM, EQ, P>(a, s);
-    flag_unstable_if(v && !(rho > R(0) && rho < R(1e30)), a.flags);
-    const __amdgpu_buffer_rsrc_t rd = rsrc((const T*)a.dst, y, z);
-    const int od = ox[1];
+}
+
+// Collision and stores of the tile.  The stores are issued by every wave
+// (a wave without a bulk node stores nothing: offsets past the row), so
+// that the memory counter is the same on both paths and a following tile's
+// loads are waited for alone.
+template <int DIM, int EQ, int P>
+__device__ __forceinline__ void bulk_finish(const LevelArgs& a, BulkTile<DIM, P>& t)
+{
+    using F = Form<P>;
+    using T = typename F::T;
+    using R = typename F::R;
+    using B = Buf<sizeof(T)>;
+    constexpr int Q = Lat<DIM>::Q;
+    if (t.any) {                                              // whole wave
+        const R rho = bulk_collide<DIM, EQ, P>(a, t.s);
+        flag_unstable_if(t.v && !(rho > R(0) && rho < R(1e30)), a.flags);
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        B::st_nt(rd, (uint32_t)(od + i * ((int)sizeof(T) << xsh)), to_bits<P>(s[i]));
+        B::st_nt(t.rd, (uint32_t)(t.ox[1] + i * ((int)sizeof(T) << kRowShift)), to_bits<P>(t.s[i]));
+}
+
+template <int DIM, int EQ, int P>
+__device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
+{
+    BulkTile<DIM, P> t;
+    bulk_locate<DIM, P>(a, bb, t);
+    if (!t.any) return;                                       // whole wave
+    bulk_pull<DIM, P>(a, t);
+    bulk_finish<DIM, EQ, P>(a, t);
+}
+
+// Bulk workgroup b of a launch: bulk_k tiles, fetched together, then
+// collided and stored in turn (twice the bytes in flight per wave for the
+// same per-node work; measured faster only for 2-D FP16 storage, whose
+// 2-byte loads keep the fewest bytes in flight).  Workgroup b = 8 q + c
+// (on XCD c) takes the tiles 8 (q k + j) + c, j < k, so each XCD still
+// walks whole tile rows.
+__host__ __device__ constexpr int bulk_k(int dim, int p) { return dim == 2 && p == 2 ? 2 : 1; }
+
+template <int DIM, int EQ, int P>
+__device__ __forceinline__ void role_bulk_group(const LevelArgs& a, int b)
+{
+    constexpr int K = bulk_k(DIM, P);
+    if constexpr (K == 1) {
+        role_bulk<DIM, EQ, P>(a, b);
+    } else {
+        const int c = b & 7, q = b >> 3;
+        BulkTile<DIM, P> t[K];
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int m = q * K + j;   // past the level's tiles: a tile without nodes
+            bulk_locate<DIM, P>(a, 8 * m + c, t[j], m < a.tm.per);
+            any = any || t[j].any;
+        }
+        if (!any) return;                                     // whole wave
+#pragma unroll
+        for (int j = 0; j < K; ++j) bulk_pull<DIM, P>(a, t[j]);
+#pragma unroll
+        for (int j = 0; j < K; ++j) bulk_finish<DIM, EQ, P>(a, t[j]);
+    }
 }
 
 // p' = (rho - 1)/3 in FP64 of every probe (thread p), appended to the series
@@ -976,7 +1061,7 @@ __device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename 
         }
         return false;
     }
-    role_bulk<DIM, EQ, P>(a, b2 - nseg);
+    role_bulk_group<DIM, EQ, P>(a, b2 - nseg);
     return false;
 }
 
@@ -996,7 +1081,7 @@ __global__ __launch_bounds__(kBlock) void k_level(LevelArgs a)
 template <int DIM, int EQ, int P>
 __global__ __launch_bounds__(kBlock) void k_bulk(LevelArgs a)
 {
-    role_bulk<DIM, EQ, P>(a, blockIdx.x);
+    role_bulk_group<DIM, EQ, P>(a, blockIdx.x);
 }
 
 template <int DIM, int EQ, int P>
