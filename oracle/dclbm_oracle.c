@@ -311,6 +311,10 @@ typedef struct {
     long long n_tfc;
     double* H;         /* history ring [n_tfc][3][Q]: slot 0 = t-dt, 1 = t, 2 = t+dt */
     long long captures;/* number of history captures made on this level */
+    /* H-RR only */
+    double* M;         /* (rho, u) of every active node at the level's current time [N][4] */
+    double* Mring;     /* post-streaming (rho, u) at the coarse times t-dt, t, t+dt [3][N][4] (levels with a child) */
+    double* G;         /* gradients: d_b u_a, then sum_g d_g Psi_abg [N][2][3][3] */
 } level_t;
 
 struct orc_sim {
@@ -320,7 +324,7 @@ struct orc_sim {
     double newton_tol;
     int newton_maxit;
     double R_override; /* planted-mistake hook for tests; 0 = off */
-    int collision;     /* 0: BGK; 1: H-RR (single periodic level) */
+    int collision;     /* 0: BGK; 1: H-RR */
     double hrr_sigma;  /* weight of the projected part of a_1^(2), Eq.(a12_HRR) */
     int hrr_psi;       /* cubic Mach correction psi_i of App. A on (1) or off (0) */
     long long newton_calls;
@@ -419,6 +423,9 @@ static void free_sim(orc_sim* s)
         free(v->X);
         free(v->tfc_id);
         free(v->H);
+        free(v->M);
+        free(v->Mring);
+        free(v->G);
     }
     free(s->probes);
     free(s->probe_series);
@@ -567,17 +574,27 @@ void orc_set_newton(orc_sim* s, double tol, int maxit)
 void orc_plant_R(orc_sim* s, double R) { s->R_override = R; }
 
 /* Collision model: 0 BGK, 1 H-RR with weight sigma of the projected part and
- * the cubic Mach correction on or off.  H-RR is defined here for a single
- * periodic level (its interface gradients of Sec. 3.3 are not part of the
- * oracle): returns -1 on a refined mesh. */
+ * the cubic Mach correction on or off (Sec. 2; on refined meshes with the
+ * interface gradients of Sec. 3.3).  Call before orc_init. */
 int orc_set_collision(orc_sim* s, int kind, double sigma, int psi_on)
 {
     if (kind != 0 && kind != 1) return -1;
-    if (kind == 1 && s->nlev != 1) return -1;
     if (!(sigma >= 0.0 && sigma <= 1.0)) return -1;
     s->collision = kind;
     s->hrr_sigma = sigma;
     s->hrr_psi = psi_on ? 1 : 0;
+    if (kind == 1)
+        for (int l = 0; l < s->nlev; ++l) {
+            level_t* v = &s->lv[l];
+            if (!v->M) v->M = (double*)malloc(sizeof(double) * v->N * 4);
+            if (!v->G) v->G = (double*)malloc(sizeof(double) * v->N * 18);
+            if (v->has_child && !v->Mring) v->Mring = (double*)malloc(sizeof(double) * 3 * v->N * 4);
+            if (!v->M || !v->G || (v->has_child && !v->Mring)) return -1;
+            for (long long q = 0; q < v->N * 4; ++q) v->M[q] = NAN;
+            for (long long q = 0; q < v->N * 18; ++q) v->G[q] = NAN;
+            if (v->Mring)
+                for (long long q = 0; q < 3 * v->N * 4; ++q) v->Mring[q] = NAN;
+        }
     return 0;
 }
 
@@ -605,6 +622,11 @@ int orc_init(orc_sim* s, int l, const double* rho, const double* u)
         }
         v->X[q * 4 + 0] = rho[q];
         for (int a = 0; a < 3; ++a) v->X[q * 4 + 1 + a] = uu[a];
+        if (v->M)
+            for (int a = 0; a < 4; ++a) v->M[q * 4 + a] = v->X[q * 4 + a];
+        if (v->Mring)
+            for (int r = 0; r < 3; ++r)
+                for (int a = 0; a < 4; ++a) v->Mring[(r * v->N + q) * 4 + a] = v->X[q * 4 + a];
         if (v->has_child && v->tfc_id[q] >= 0)
             for (int r = 0; r < 3; ++r)
                 for (int i = 0; i < L->Q; ++i)
@@ -649,6 +671,30 @@ static void capture_history(orc_sim* s, int l)
             H[0 * L->Q + i] = H[1 * L->Q + i];
             H[1 * L->Q + i] = H[2 * L->Q + i];
             H[2 * L->Q + i] = v->pre[q * L->Q + i];
+        }
+    }
+    if (v->Mring) {
+        /* H-RR: the post-streaming macroscopic fields of the whole level at
+         * the same coarse times, for the coarse-stencil gradients of the
+         * child's co-located nodes (Sec. 3.3); only nodes outside the child
+         * box are read, and their populations are complete */
+#pragma omp parallel for schedule(static)
+        for (long long q = 0; q < v->N; ++q) {
+            double* R0 = v->Mring + q * 4;
+            double* R1 = v->Mring + (v->N + q) * 4;
+            double* R2 = v->Mring + (2 * v->N + q) * 4;
+            for (int a = 0; a < 4; ++a) {
+                R0[a] = R1[a];
+                R1[a] = R2[a];
+            }
+            const double* pre = v->pre + q * L->Q;
+            double r = 0.0, j[3] = {0, 0, 0};
+            for (int i = 0; i < L->Q; ++i) {
+                r += pre[i];
+                for (int a = 0; a < L->D; ++a) j[a] += L->xi[i][a] * pre[i];
+            }
+            R2[0] = r;
+            for (int a = 0; a < 3; ++a) R2[1 + a] = a < L->D ? j[a] / r : 0.0;
         }
     }
     v->captures += 1;
@@ -841,92 +887,226 @@ static double Psi(const lattice_t* L, double rho, const double u[3], int a, int 
     return 0.5 * rho * u[sgl] * u[third] * u[third];
 }
 
-static void collide_level_hrr(orc_sim* s, int l)
+/* Macroscopic fields of every active node of level l at the current time:
+ * co-located nodes (TF^f, TF^c) carry X, the others the moments of their
+ * post-streaming (completed) populations. */
+static void hrr_macros(orc_sim* s, int l)
+{
+    const lattice_t* L = &s->L;
+    level_t* v = &s->lv[l];
+#pragma omp parallel for schedule(static)
+    for (long long q = 0; q < v->N; ++q) {
+        const unsigned char c = v->cls[q];
+        double* M = v->M + q * 4;
+        if (c == C_HOLE) {
+            for (int a = 0; a < 4; ++a) M[a] = NAN;
+            continue;
+        }
+        if (c == C_TFF || c == C_TFC) {
+            for (int a = 0; a < 4; ++a) M[a] = v->X[q * 4 + a];
+            continue;
+        }
+        const double* pre = v->pre + q * L->Q;
+        double r = 0.0, j[3] = {0, 0, 0};
+        for (int i = 0; i < L->Q; ++i) {
+            r += pre[i];
+            for (int a = 0; a < L->D; ++a) j[a] += L->xi[i][a] * pre[i];
+        }
+        M[0] = r;
+        for (int a = 0; a < 3; ++a) M[1 + a] = a < L->D ? j[a] / r : 0.0;
+    }
+}
+
+/* (rho, u) of the parent node P of level l's co-located node stencil at the
+ * time of level l's substep: the parent's post-streaming fields interpolated
+ * with the weights of Eq.(TempInt) (the reading of the ring as for the
+ * populations), Sec. 3.3. */
+static void parent_macros(const orc_sim* s, int l, int substep, const int P[3], double out[4])
+{
+    const level_t* pv = &s->lv[l - 1];
+    const long long q = nid(pv, P[0], P[1], P[2]);
+    for (int a = 0; a < 4; ++a)
+        out[a] = time_interp(pv->captures, substep, pv->Mring[q * 4 + a], pv->Mring[(pv->N + q) * 4 + a],
+                             pv->Mring[(2 * pv->N + q) * 4 + a]);
+}
+
+/* Gradient tensors of one node from the macroscopic fields at its stencil
+ * points, at distance h (level-l units) on either side along each axis:
+ *   G[0][a][b] = d_b u_a,   G[1][a][b] = sum_g d_g Psi_abg,
+ * centred differences (v(+) - v(-)) / (2 h), Eq.(a1FD_scheme), Eq.(PSI_FD).
+ * Mm[b], Mp[b] are the (rho, u) at the points -h e_b and +h e_b. */
+static void stencil_gradients(const lattice_t* L, double h, const double Mm[3][4], const double Mp[3][4],
+                              double G[2][3][3])
+{
+    for (int t = 0; t < 2; ++t)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) G[t][a][b] = 0.0;
+    for (int b = 0; b < L->D; ++b)
+        for (int a = 0; a < L->D; ++a) G[0][a][b] = (Mp[b][1 + a] - Mm[b][1 + a]) / (2.0 * h);
+    for (int a = 0; a < L->D; ++a)
+        for (int b = 0; b < L->D; ++b)
+            for (int g = 0; g < L->D; ++g)
+                G[1][a][b] += (Psi(L, Mp[g][0], Mp[g] + 1, a, b, g) - Psi(L, Mm[g][0], Mm[g] + 1, a, b, g)) / (2.0 * h);
+}
+
+/* Gradients of every active node of level l (H-RR), from the fields of
+ * hrr_macros and of the neighbouring levels:
+ *  - bulk nodes and coarse co-located (TF^c) nodes: the level's own stencil,
+ *    h = 1 (periodic on level 0); a neighbour in the hole takes the child's
+ *    node co-located with it at the same time (Sec. 3.5 step 3d: the coarse
+ *    strain tensor on TF^c);
+ *  - fine co-located (TF^f) nodes: the coarse stencil, h = 2 (Sec. 3.3,
+ *    Fig. gradC): points inside the level are its own nodes, points outside
+ *    are parent nodes at the substep's time (interpolated in time at the
+ *    asynchronous substep, Sec. 3.5 step 2f); differences over 2h = 4 fine
+ *    cells give the fine-scale values S^c / 2 and psi^c / 2 of
+ *    Eq.(PijResc) and Eq.(PSIResc) directly;
+ *  - hanging (IE) nodes: interpolated from the TF^f nodes of their line
+ *    stencil with the weights of their populations (Sec. 3.5 steps 2g/3e). */
+static void hrr_gradients(orc_sim* s, int l, int substep)
+{
+    const lattice_t* L = &s->L;
+    level_t* v = &s->lv[l];
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < v->n[2]; ++z)
+        for (int y = 0; y < v->n[1]; ++y)
+            for (int x = 0; x < v->n[0]; ++x) {
+                const long long q = nid(v, x, y, z);
+                const unsigned char c = v->cls[q];
+                if (c == C_HOLE || c == C_IE) continue;
+                const int k[3] = {x, y, z};
+                double Mm[3][4], Mp[3][4];
+                const int h = c == C_TFF ? 2 : 1;
+                for (int b = 0; b < L->D; ++b)
+                    for (int sgn = -1; sgn <= 1; sgn += 2) {
+                        double* out = sgn < 0 ? Mm[b] : Mp[b];
+                        int d[3] = {0, 0, 0};
+                        d[b] = sgn * h;
+                        int kk[3] = {k[0] + d[0], k[1] + d[1], k[2] + d[2]};
+                        if (c == C_TFF && (kk[b] < 0 || kk[b] > v->n[b] - 1)) {
+                            int P[3] = {0, 0, 0};
+                            for (int a = 0; a < L->D; ++a) P[a] = v->plo[a] + k[a] / 2;
+                            P[b] += sgn;
+                            parent_macros(s, l, substep, P, out);
+                            continue;
+                        }
+                        const long long nq = active_at(L, v, k, d);
+                        if (nq >= 0) {
+                            for (int a = 0; a < 4; ++a) out[a] = v->M[nq * 4 + a];
+                            continue;
+                        }
+                        /* a hole: the child's co-located node */
+                        const level_t* cv = &s->lv[l + 1];
+                        int kc[3] = {0, 0, 0};
+                        for (int a = 0; a < L->D; ++a) kc[a] = 2 * (kk[a] - v->clo[a]);
+                        const long long cq = nid(cv, kc[0], kc[1], kc[2]);
+                        for (int a = 0; a < 4; ++a) out[a] = cv->M[cq * 4 + a];
+                    }
+                double G[2][3][3];
+                stencil_gradients(L, (double)h, Mm, Mp, G);
+                memcpy(v->G + q * 18, G, sizeof(G));
+            }
+    if (l == 0) return;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < v->n[2]; ++z)
+        for (int y = 0; y < v->n[1]; ++y)
+            for (int x = 0; x < v->n[0]; ++x) {
+                const long long q = nid(v, x, y, z);
+                if (v->cls[q] != C_IE) continue;
+                const int k[3] = {x, y, z};
+                int npts[3], pos[3][4];
+                double w[3][4];
+                for (int a = 0; a < 3; ++a) {
+                    if (a < L->D && (k[a] % 2)) {
+                        npts[a] = 4;
+                        line_stencil(k[a], v->n[a] - 1, pos[a], w[a]);
+                    } else {
+                        npts[a] = 1;
+                        pos[a][0] = k[a];
+                        w[a][0] = 1.0;
+                    }
+                }
+                double* G = v->G + q * 18;
+                for (int e = 0; e < 18; ++e) G[e] = 0.0;
+                for (int cc = 0; cc < npts[2]; ++cc)
+                    for (int bb = 0; bb < npts[1]; ++bb)
+                        for (int aa = 0; aa < npts[0]; ++aa) {
+                            const long long sq = nid(v, pos[0][aa], pos[1][bb], pos[2][cc]);
+                            const double wt = w[0][aa] * w[1][bb] * w[2][cc];
+                            for (int e = 0; e < 18; ++e) G[e] += wt * v->G[sq * 18 + e];
+                        }
+            }
+}
+
+/* The H-RR collision of every active node of level l from its completed
+ * pre-collision populations, its macroscopic fields (X at co-located nodes)
+ * and its gradients. */
+static void collide_level_hrr(orc_sim* s, int l, int substep)
 {
     const lattice_t* L = &s->L;
     level_t* v = &s->lv[l];
     const int D = L->D, Q = L->Q;
     const double c2 = L->cs2, tau = v->tau;
-    double* rho = (double*)malloc(sizeof(double) * v->N);
-    double* u = (double*)malloc(sizeof(double) * v->N * 3);
+    hrr_macros(s, l);
+    hrr_gradients(s, l, substep);
+#pragma omp parallel for schedule(static)
     for (long long q = 0; q < v->N; ++q) {
+        if (v->cls[q] == C_HOLE) continue;
         const double* pre = v->pre + q * Q;
-        double r = 0.0, j[3] = {0, 0, 0};
+        const double rho = v->M[q * 4];
+        const double uq[3] = {v->M[q * 4 + 1], v->M[q * 4 + 2], v->M[q * 4 + 3]};
+        double G[2][3][3];
+        memcpy(G, v->G + q * 18, sizeof(G));
+        double f0[MAXQ], psi[MAXQ], a1[3][3] = {{0}};
         for (int i = 0; i < Q; ++i) {
-            r += pre[i];
-            for (int a = 0; a < D; ++a) j[a] += L->xi[i][a] * pre[i];
+            f0[i] = feq_i(L, s->eq_order, i, rho, uq);
+            double t = 0.0;
+            if (s->hrr_psi)
+                for (int a = 0; a < D; ++a)
+                    for (int b = 0; b < D; ++b) t += H2(L, i, a, b) * G[1][a][b];
+            psi[i] = -L->w[i] / (2.0 * c2 * c2) * t;
         }
-        rho[q] = r;
-        for (int a = 0; a < 3; ++a) u[q * 3 + a] = a < D ? j[a] / r : 0.0;
-    }
-#pragma omp parallel for collapse(2) schedule(static)
-    for (int z = 0; z < v->n[2]; ++z)
-        for (int y = 0; y < v->n[1]; ++y)
-            for (int x = 0; x < v->n[0]; ++x) {
-                const int k[3] = {x, y, z};
-                const long long q = nid(v, x, y, z);
-                const double* pre = v->pre + q * Q;
-                const double* uq = u + q * 3;
-                /* neighbours at -e_g (index 0) and +e_g (index 1), periodic */
-                long long nb[3][2];
-                for (int g = 0; g < 3; ++g)
-                    for (int sgn = 0; sgn < 2; ++sgn) {
-                        int d[3] = {0, 0, 0};
-                        if (g < D) d[g] = sgn ? 1 : -1;
-                        nb[g][sgn] = active_at(L, v, k, d);
-                    }
-                /* velocity gradients du[a][b] = d_b u_a */
-                double du[3][3] = {{0}};
-                for (int a = 0; a < D; ++a)
-                    for (int b = 0; b < D; ++b)
-                        du[a][b] = 0.5 * (u[nb[b][1] * 3 + a] - u[nb[b][0] * 3 + a]);
-                /* divergence of Psi: dPsi[a][b] = sum_g d_g Psi_abg */
-                double dPsi[3][3] = {{0}};
-                if (s->hrr_psi)
-                    for (int a = 0; a < D; ++a)
-                        for (int b = 0; b < D; ++b)
-                            for (int g = 0; g < D; ++g)
-                                dPsi[a][b] += 0.5 * (Psi(L, rho[nb[g][1]], u + nb[g][1] * 3, a, b, g) -
-                                                     Psi(L, rho[nb[g][0]], u + nb[g][0] * 3, a, b, g));
-                double f0[MAXQ], psi[MAXQ], a1[3][3] = {{0}};
-                for (int i = 0; i < Q; ++i) {
-                    f0[i] = feq_i(L, s->eq_order, i, rho[q], uq);
-                    double t = 0.0;
-                    for (int a = 0; a < D; ++a)
-                        for (int b = 0; b < D; ++b) t += H2(L, i, a, b) * dPsi[a][b];
-                    psi[i] = -L->w[i] / (2.0 * c2 * c2) * t;
-                }
-                for (int a = 0; a < D; ++a)
-                    for (int b = 0; b < D; ++b) {
-                        double pr = 0.0;
-                        for (int i = 0; i < Q; ++i) pr += H2(L, i, a, b) * (pre[i] - f0[i] + 0.5 * psi[i]);
-                        const double fd = -tau * rho[q] * c2 * (du[a][b] + du[b][a]);
-                        a1[a][b] = s->hrr_sigma * pr + (1.0 - s->hrr_sigma) * fd;
-                    }
-                for (int i = 0; i < Q; ++i) {
-                    double t2 = 0.0, t3 = 0.0;
-                    for (int a = 0; a < D; ++a)
-                        for (int b = 0; b < D; ++b) t2 += H2(L, i, a, b) * a1[a][b];
-                    for (int a = 0; a < D; ++a)
-                        for (int b = 0; b < D; ++b) {
-                            if (a == b) continue;
-                            const double H3 = (double)(L->xi[i][a] * L->xi[i][a] * L->xi[i][b]) - c2 * L->xi[i][b];
-                            const double a13 = 2.0 * uq[a] * a1[a][b] + uq[b] * a1[a][a];
-                            t3 += H3 * a13;
-                        }
-                    const double f1 = L->w[i] * (t2 / (2.0 * c2 * c2) + t3 / (2.0 * c2 * c2 * c2));
-                    v->f[q * Q + i] = f0[i] + (1.0 - 1.0 / tau) * f1 + 0.5 * psi[i];
-                }
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) {
+                double pr = 0.0;
+                for (int i = 0; i < Q; ++i) pr += H2(L, i, a, b) * (pre[i] - f0[i] + 0.5 * psi[i]);
+                const double fd = -tau * rho * c2 * (G[0][a][b] + G[0][b][a]);
+                a1[a][b] = s->hrr_sigma * pr + (1.0 - s->hrr_sigma) * fd;
             }
-    free(rho);
-    free(u);
+        for (int i = 0; i < Q; ++i) {
+            double t2 = 0.0, t3 = 0.0;
+            for (int a = 0; a < D; ++a)
+                for (int b = 0; b < D; ++b) t2 += H2(L, i, a, b) * a1[a][b];
+            for (int a = 0; a < D; ++a)
+                for (int b = 0; b < D; ++b) {
+                    if (a == b) continue;
+                    const double H3 = (double)(L->xi[i][a] * L->xi[i][a] * L->xi[i][b]) - c2 * L->xi[i][b];
+                    const double a13 = 2.0 * uq[a] * a1[a][b] + uq[b] * a1[a][a];
+                    t3 += H3 * a13;
+                }
+            const double f1 = L->w[i] * (t2 / (2.0 * c2 * c2) + t3 / (2.0 * c2 * c2 * c2));
+            v->f[q * Q + i] = f0[i] + (1.0 - 1.0 / tau) * f1 + 0.5 * psi[i];
+        }
+    }
+}
+
+/* Gradient tensors of level l from the current state (test access). */
+int orc_hrr_gradients(orc_sim* s, int l, int substep, double* out)
+{
+    if (s->collision != 1 || l < 0 || l >= s->nlev) return -1;
+    level_t* v = &s->lv[l];
+    /* the finer levels first: a coarse co-located node reads its child's fields */
+    for (int k = s->nlev - 1; k >= l; --k) hrr_macros(s, k);
+    hrr_gradients(s, l, substep);
+    memcpy(out, v->G, sizeof(double) * v->N * 18);
+    return 0;
 }
 
 /* BGK collision of every active node of level l; co-located nodes use X. */
-static void collide_level(orc_sim* s, int l)
+static void collide_level(orc_sim* s, int l, int substep)
 {
     if (s->collision == 1) {
-        collide_level_hrr(s, l);
+        collide_level_hrr(s, l, substep);
         return;
     }
     const lattice_t* L = &s->L;
@@ -974,7 +1154,7 @@ static int advance(orc_sim* s, int l, int substep)
         if (advance(s, l + 1, 2) != 0) return -1;
         restrict_tfc(s, l);                   /* 3f */
     }
-    collide_level(s, l);                      /* 2h / 3g */
+    collide_level(s, l, substep);             /* 2h / 3g */
     return 0;
 }
 

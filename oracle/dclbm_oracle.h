@@ -27,6 +27,9 @@ int orc_classes(const orc_sim* s, int l, unsigned char* out);
 void orc_set_newton(orc_sim* s, double tol, int maxit);
 void orc_plant_R(orc_sim* s, double R);
 int orc_set_collision(orc_sim* s, int kind, double sigma, int psi_on);
+/* H-RR gradient tensors of level l from the current state, [N][2][3][3]:
+ * d_b u_a, then sum_g d_g Psi_abg (test access) */
+int orc_hrr_gradients(orc_sim* s, int l, int substep, double* out);
 /* rho: [n], u: [D][n], dense over the level's nodes */
 int orc_init(orc_sim* s, int l, const double* rho, const double* u);
 int orc_run(orc_sim* s, long long n_coarse_steps);

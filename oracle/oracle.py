@@ -66,6 +66,7 @@ def load_library(path: str = None):
             lib.orc_set_newton.argtypes = [P, C.c_double, C.c_int]
             lib.orc_plant_R.argtypes = [P, C.c_double]
             lib.orc_set_collision.argtypes = [P, C.c_int, C.c_double, C.c_int]
+            lib.orc_hrr_gradients.argtypes = [P, C.c_int, C.c_int, dp]
             lib.orc_init.argtypes = [P, C.c_int, dp, dp]
             lib.orc_run.argtypes = [P, C.c_longlong]
             for name in ("orc_get_f", "orc_get_pre", "orc_get_x", "orc_set_f"):
@@ -230,9 +231,18 @@ class Oracle:
         self.lib.orc_plant_R(self.h, R)
 
     def set_collision(self, kind: str = "bgk", sigma: float = 0.98, psi: bool = True):
-        """'bgk' or 'hrr' (Sec. 2; one periodic level only)."""
+        """'bgk' or 'hrr' (Sec. 2, with the interface gradients of Sec. 3.3 on
+        refined meshes); call before init."""
         if self.lib.orc_set_collision(self.h, {"bgk": 0, "hrr": 1}[kind], float(sigma), int(bool(psi))) != 0:
-            raise ValueError("oracle: invalid collision setting (H-RR needs a single level, 0 <= sigma <= 1)")
+            raise ValueError("oracle: invalid collision setting (0 <= sigma <= 1)")
+
+    def hrr_gradients(self, l, substep=2):
+        """H-RR gradient tensors of level l from the current state:
+        [2][3][3][n] (d_b u_a, then sum_g d_g Psi_abg; node index last)."""
+        out = np.zeros((self.n(l), 2, 3, 3))
+        if self.lib.orc_hrr_gradients(self.h, l, int(substep), _dp(out)) != 0:
+            raise RuntimeError("oracle: H-RR gradients need collision 'hrr'")
+        return np.moveaxis(out, 0, -1)
 
     def init(self, l, rho, u):
         rho = np.ascontiguousarray(rho, np.float64).reshape(-1)

@@ -39,12 +39,6 @@ def moments(lat, f):
     return rho, j, xi
 
 
-def test_hrr_is_rejected_on_refined_meshes():
-    o = O.Oracle("D2Q9", (32, 32), [((8, 8), (24, 24))], tau0=0.6)
-    with pytest.raises(ValueError):
-        o.set_collision("hrr", 0.98, True)
-
-
 @pytest.mark.parametrize("lat,dims", [("D2Q9", (16, 12)), ("D3Q19", (10, 9, 8))])
 @pytest.mark.parametrize("sigma", [1.0, 0.98, 0.0])
 def test_uniform_state_is_a_fixed_point(lat, dims, sigma):
