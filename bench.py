@@ -17,6 +17,8 @@ Beside it, in the same run:
   * the 4-level 512^3 D3Q19 workload (64 vortex rings, 8 pulses; refined
     boxes of 30.3%, 10.0% and 1.87% of the volume, about 206 GB) in FP16
     storage;
+  * the H-RR collision of Sec. 2 on the 2048^2 3-level mesh (with the
+    interface gradients of Sec. 3.3), FP32 and FP64;
   * the serving loop (256 seeded requests);
   * the FP64 CPU oracle (single thread and all host cores) on bounded samples.
 
@@ -58,6 +60,7 @@ def parse():
     ap.add_argument("--no-accuracy", action="store_true", help="skip the full-length accuracy runs")
     ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 D3Q19 workload")
     ap.add_argument("--no-4level", action="store_true", help="skip the 4-level 512^3 D3Q19 workload")
+    ap.add_argument("--no-hrr", action="store_true", help="skip the H-RR collision on the 2048^2 3-level mesh")
     ap.add_argument("--workload", default="pulse_vortices_3level",
                     choices=["pulse_vortices_3level", "pulse_ring_3d", "rings_4level"],
                     help="workload of `value`: 3-level 2048^2 D2Q9 (default), 2-level 256^3 D3Q19, or the "
@@ -449,6 +452,27 @@ def four_level_block(steps, warmup):
             "roofline": roofline(f, wl.Q, wl.name)}
 
 
+def hrr_block(steps, warmup, bgk_mlups):
+    """The H-RR collision (Sec. 2) on the 2048^2 3-level mesh with the
+    interface gradients of Sec. 3.3: FP32 and FP64, eager launches (four per
+    refined level substep, two on level 0).  Minimum HBM traffic per node
+    update: the populations read twice (the macroscopic pass and the
+    collision) and written once, and the four macroscopic values written
+    and read once: 3 Q + 8 values."""
+    wl = make_workload("pulse_vortices_3level", steps)
+    wl.collision = "hrr"
+    forms = {p: run_form(wl, p, steps, warmup, min(steps, 20), 0, True) for p in ("fp32", "fp64")}
+    out = {}
+    for p, f in forms.items():
+        bpv = BYTES[p]
+        gbs = f["mlups"] * 1e6 * (3 * wl.Q + 8) * bpv / 1e9
+        out[p] = {"mlups": round(f["mlups"], 1), "ms_per_step": round(f["wall_ms"] / f["steps"], 5),
+                  "min_traffic_gbs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                  "vs_bgk_same_form": round(f["mlups"] / bgk_mlups[p], 3) if bgk_mlups.get(p) else None}
+    return {"config": {"workload": wl.name + "_hrr", "sigma": wl.hrr_sigma, "psi": wl.hrr_psi,
+                       "updates_per_step": forms["fp32"]["updates_per_step"]}, "forms": out}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -496,6 +520,10 @@ def main():
     if name == "pulse_vortices_3level" and not args.no_4level:
         torch.cuda.empty_cache()
         extra["rings_4level_512"] = four_level_block(min(args.steps, 10), min(args.warmup, 2))
+    if name == "pulse_vortices_3level" and args.n0 == 2048 and not args.no_hrr:
+        torch.cuda.empty_cache()
+        extra["hrr_pulse_vortices_3level_2048"] = hrr_block(min(args.steps, 100), min(args.warmup, 5),
+                                                            {p: f["mlups"] for p, f in forms.items()})
     cpu = None
     if not args.no_cpu_baseline and name != "rings_4level":
         log("cpu baseline (oracle)")

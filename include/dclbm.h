@@ -68,9 +68,12 @@ typedef enum { DCLBM_DC1 = 1, DCLBM_DC2 = 2 } dclbm_coupling;
  *        Eq.(a12_HRR) mixing the projection of Eq.(a1Proj) (weight sigma)
  *        and the centred finite differences of Eq.(a1FD_scheme), a_1^(3) of
  *        Eq.(a13RR), the cubic Mach correction psi_i of App. A (optional).
- *        Built for a single periodic level (n_levels = 1); its interface
- *        gradients of Sec. 3.3 are not built, so refined meshes are
- *        rejected (DCLBM_ERR_INVALID). */
+ *        Every mesh.  On refined meshes the steps follow Sec. 3.5: a level
+ *        streams and completes its interface nodes, runs its child's two
+ *        substeps, then collides all its nodes; the gradients at co-located
+ *        and hanging nodes are those of Sec. 3.3 (coarse stencil, rescaled
+ *        by Eq.(PijResc) and Eq.(PSIResc)).  Refined H-RR steps are launched
+ *        eagerly (no graph). */
 typedef enum { DCLBM_BGK = 0, DCLBM_HRR = 1 } dclbm_collision;
 
 typedef struct {

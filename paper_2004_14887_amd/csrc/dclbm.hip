@@ -264,6 +264,7 @@ static dclbm_status build_segments(Sim& s, int l)
     L.seg_tf.clear();
     L.seg_ie.clear();
     L.seg_sten.assign(16 * nie, 0);
+    L.ie_tf.assign(16 * nie, 0);
     const int TFM = D == 2 ? SegLimits<2>::TF : SegLimits<3>::TF;
     for (auto& kv : segs) {
         Seg& sg = kv.second;
@@ -309,6 +310,7 @@ static dclbm_status build_segments(Sim& s, int l)
                     li = it->second;
                 }
                 L.seg_sten[(size_t)q * nie + slot] = li;
+                L.ie_tf[(size_t)q * nie + e] = t;
             }
             L.seg_ie.push_back(e);
         }
@@ -348,9 +350,6 @@ dclbm_status build_geometry(Sim& s)
         return fail(DCLBM_ERR_INVALID, "probes need coordinates and a capacity");
     if (c.collision != DCLBM_BGK && c.collision != DCLBM_HRR) return fail(DCLBM_ERR_INVALID, "unknown collision model %d", c.collision);
     if (c.collision == DCLBM_HRR) {
-        if (c.n_levels != 1)
-            return fail(DCLBM_ERR_INVALID, "H-RR collision is built for a single periodic level (its interface "
-                                           "gradients are not built)");
         if (!(c.hrr_sigma >= 0.0 && c.hrr_sigma <= 1.0)) return fail(DCLBM_ERR_INVALID, "hrr_sigma must be in [0, 1]");
     }
     s.hrr = c.collision == DCLBM_HRR ? 1 : 0;
@@ -596,7 +595,14 @@ dclbm_status build_geometry(Sim& s)
     s.off_flags = take(8);
     s.off_partial = take((int64_t)DCLBM_MAX_LEVELS * s.partial_blocks * 5 * 8);
     s.off_bal = take(DCLBM_MAX_LEVELS * 5 * 8);
-    if (s.hrr) s.off_M = take(4 * s.lv[0].n_dense() * (int64_t)s.rsize);
+    if (s.hrr)
+        for (size_t l = 0; l < s.lv.size(); ++l) {
+            HostLevel& L = s.lv[l];
+            L.off_M = take(4 * L.n_dense() * (int64_t)s.rsize);
+            if (L.has_child) L.off_Mring = take(3 * 4 * L.n_dense() * (int64_t)s.rsize);
+            if (!L.tf_meta.empty()) L.off_Gtf = take(18 * (int64_t)L.tf_meta.size() * (int64_t)s.rsize);
+            if (!L.ie_meta.empty()) L.off_ie_tf = take((int64_t)L.ie_tf.size() * 4);
+        }
     s.need_bytes = (size_t)off;
     return DCLBM_OK;
 }
@@ -651,7 +657,14 @@ dclbm_status sim_attach(Sim& s, void* d_workspace, size_t bytes, hipStream_t str
         HIPCHECK(upload(s, s.d_probe_args, s.h_probe_args));
     }
     s.d_flags = s.at<int>(s.off_flags);
-    s.d_M = s.hrr ? (void*)(s.ws + s.off_M) : nullptr;
+    if (s.hrr)
+        for (auto& L : s.lv) {
+            L.d_M = s.ws + L.off_M;
+            L.d_Mring = L.has_child ? (void*)(s.ws + L.off_Mring) : nullptr;
+            L.d_Gtf = L.tf_meta.empty() ? nullptr : (void*)(s.ws + L.off_Gtf);
+            L.d_ie_tf = L.ie_meta.empty() ? nullptr : s.at<int>(L.off_ie_tf);
+            if (L.d_ie_tf) HIPCHECK(upload(s, L.d_ie_tf, L.ie_tf));
+        }
     s.d_partial = s.at<double>(s.off_partial);
     s.d_bal = s.at<double>(s.off_bal);
     s.eng.reset(make_engine(s.D, s.EQ, s.P));
@@ -686,6 +699,24 @@ static void advance(Sim& s, int l, int substep)
     walk(s, l, substep, [&](int lv, int sub, int first) { s.eng->level_step(s, lv, sub, first); });
 }
 
+// H-RR on a refined mesh (Sec. 3.5): a level opens its substep (streaming,
+// macroscopic fields, interface completion), runs its child's two substeps
+// (the synchronous one restricting into its coarse co-located nodes), and
+// only then closes it (gradients, collision of all its nodes).
+static void advance_hrr(Sim& s, int l, int substep)
+{
+    HostLevel& L = s.lv[l];
+    const int first = (l > 0 && s.lv[l - 1].captures <= 1) ? 1 : 0;
+    s.eng->hrr_open(s, l, substep, first);
+    if (L.has_child) {
+        L.captures++;
+        advance_hrr(s, l + 1, 1);
+        advance_hrr(s, l + 1, 2);
+    }
+    s.eng->hrr_close(s, l, substep, first);
+    L.parity ^= 1;
+}
+
 void record_coarse_step(Sim& s, std::vector<StepRecord>& out, ProbeArgs& probe_after)
 {
     out.clear();
@@ -712,7 +743,10 @@ static void advance_state(Sim& s)
 // the flush before they are read.
 static void one_coarse_step(Sim& s)
 {
-    advance(s, 0, 0);
+    if (s.hrr && s.lv.size() > 1)
+        advance_hrr(s, 0, 0);
+    else
+        advance(s, 0, 0);
 }
 
 // The first HIP error of a step's launch sequence, if any, as a status.
@@ -740,7 +774,8 @@ static bool all_first_steps_done(const Sim& s)
 
 static dclbm_status coarse_step(Sim& s)
 {
-    if (s.timing || s.stream == nullptr || !all_first_steps_done(s)) return coarse_step_eager(s);
+    if (s.timing || s.stream == nullptr || !all_first_steps_done(s) || (s.hrr && s.lv.size() > 1))
+        return coarse_step_eager(s);
     const int par = s.lv[0].parity;
     if (!s.gexec[par]) {
         // the coarse step's launches, recorded from the host state (which
@@ -855,6 +890,7 @@ static void state_regions(const Sim& s, Fn&& fn)
         if (L.xface) fn(L.xf[L.parity], L.xf_elems * (int64_t)s.tsize);
         if (!L.tf_meta.empty()) fn(L.X, (int64_t)L.tf_meta.size() * 4 * (int64_t)s.rsize);
         if (!L.tfc_meta.empty()) fn(L.H, (int64_t)L.tfc_meta.size() * 3 * s.Q * (int64_t)s.rsize);
+        if (L.d_Mring) fn(L.d_Mring, 3 * 4 * L.n_dense() * (int64_t)s.rsize);
     }
     fn((void*)s.d_series, std::max<int64_t>(1, s.cfg.probe_capacity) * std::max(1, s.cfg.n_probes) * 8);
     fn((void*)s.d_counter, (int64_t)16);
@@ -945,7 +981,6 @@ dclbm_status dclbm_create(const dclbm_config* cfg, void* d_workspace, size_t byt
         s.off_partial = tmp.off_partial;
         s.off_bal = tmp.off_bal;
         s.hrr = tmp.hrr;
-        s.off_M = tmp.off_M;
     }
     dclbm_status st = sim_attach(s, d_workspace, bytes, (hipStream_t)stream);
     if (st != DCLBM_OK) return st;
@@ -1013,6 +1048,7 @@ dclbm_status dclbm_init_equilibrium(dclbm_sim* sim, int32_t level, const double*
     Sim& s = sim->s;
     s.eng->init(s, level, d_rho, d_u);
     if (s.lv[level].has_child) s.eng->ring_init(s, level);
+    if (s.hrr && s.lv[level].has_child) s.eng->hrr_ring_init(s, level, d_rho, d_u);
     s.lv[level].captures = 0;
     HIPCHECK(hipGetLastError());
     return DCLBM_OK;

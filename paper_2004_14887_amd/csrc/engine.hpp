@@ -44,17 +44,24 @@ struct HostLevel {
     int mx = 1, my = 1, mz = 1;
     std::vector<int4> seg_info;           // (tf_off, tf_cnt, ie_off, ie_cnt)
     std::vector<int> seg_tf, seg_ie, seg_sten;
+    std::vector<int> ie_tf;               // [16][n_ie] co-located indices of each hanging node's stencil
     // interface with the child (coarse co-located nodes, child's order)
     std::vector<int4> tfc_meta;
     // workspace offsets
     int64_t off_f[2] = {0, 0}, off_xf[2] = {0, 0}, off_tf = 0, off_ie = 0, off_X = 0, off_tfc = 0, off_H = 0, off_seg_info = 0,
             off_seg_tf = 0, off_seg_ie = 0, off_seg_sten = 0;
+    int64_t off_M = 0, off_Mring = 0, off_Gtf = 0, off_ie_tf = 0;   // H-RR
     // device pointers
     void* f[2] = {nullptr, nullptr};
     void* xf[2] = {nullptr, nullptr};
     int4 *d_tf = nullptr, *d_ie = nullptr, *d_tfc = nullptr, *d_seg_info = nullptr;
     int *d_seg_tf = nullptr, *d_seg_ie = nullptr, *d_seg_sten = nullptr;
     void *X = nullptr, *H = nullptr;
+    // H-RR: (drho, du) of every node [4][n]; its post-streaming values at the
+    // coarse times t-dt, t, t+dt [3][4][n] (level with a child); gradients of
+    // the co-located nodes [18][n_tf]; hanging-node stencils [16][n_ie]
+    void *d_M = nullptr, *d_Mring = nullptr, *d_Gtf = nullptr;
+    int* d_ie_tf = nullptr;
     int parity = 0;
     int64_t captures = 0;
 
@@ -109,6 +116,13 @@ struct Sim;
 struct Engine {
     virtual ~Engine() {}
     virtual void level_step(Sim& s, int l, int substep, int first) = 0;
+    // H-RR on a refined mesh: a level substep opens (macroscopic fields,
+    // interface completion) before its child's substeps and closes
+    // (gradients, collision of every node) after them
+    virtual void hrr_open(Sim& s, int l, int substep, int first) = 0;
+    virtual void hrr_close(Sim& s, int l, int substep, int first) = 0;
+    // the three slots of level l's macroscopic-field ring from its initial fields
+    virtual void hrr_ring_init(Sim& s, int l, const double* rho, const double* u) = 0;
     virtual void probe(Sim& s) = 0;
     virtual void init(Sim& s, int l, const double* rho, const double* u) = 0;
     virtual void ring_init(Sim& s, int l) = 0;
@@ -152,9 +166,7 @@ struct Sim {
     double* d_partial = nullptr;
     double* d_bal = nullptr;
     int partial_blocks = 1024;
-    int hrr = 0;                      // H-RR collision (single periodic level)
-    int64_t off_M = 0;
-    void* d_M = nullptr;              // [4][n] macroscopic state of level 0 between the two H-RR launches
+    int hrr = 0;                      // H-RR collision
     int device = -1;                  // device current at creation
     double* d_scratch = nullptr;      // that device's static scratch array (dclbm_balance_static)
     std::unique_ptr<Engine> eng;

@@ -32,7 +32,7 @@ struct EngineImpl final : Engine {
         if (s.hrr) {
             // H-RR on one periodic level: macroscopic fields (with the probe
             // workgroup in front), then the collision
-            const HrrArgs h = hrr_args(s, a);
+            const HrrArgs h = hrr_args(s, a, l);
             const unsigned g_bulk = (unsigned)bulk_groups(h.a.tm.per, 1);
             if (s.timing) {
                 hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -129,7 +129,7 @@ struct EngineImpl final : Engine {
         hipGraphNode_t n0 = nullptr, n1 = nullptr;
         hipError_t e = hipSuccess;
         if (s.hrr) {
-            HrrArgs h = hrr_args(s, a);
+            HrrArgs h = hrr_args(s, a, r.level);
             const unsigned g_bulk = (unsigned)bulk_groups(h.a.tm.per, 1);
             e = kernel_node(g, reinterpret_cast<const void*>(&k_hrr_macros<DIM, EQ, P>), a.nb_probe + g_bulk, &h, deps, &n0);
             if (e != hipSuccess) return e;
@@ -162,20 +162,66 @@ struct EngineImpl final : Engine {
         deps.assign(1, n0);
         return e;
     }
-    static HrrArgs hrr_args(const Sim& s, const LevelArgs& a)
+    static HrrArgs hrr_args(const Sim& s, const LevelArgs& a, int l)
     {
+        const HostLevel& L = s.lv[l];
         HrrArgs h;
+        memset(&h, 0, sizeof(h));
         h.a = a;
+        h.a.M = L.d_M;
+        h.a.M_parent = l > 0 ? s.lv[l - 1].d_M : nullptr;
         // each node's macroscopic state is read again by its 2 D axis
         // neighbours: rows go to the XCDs in slabs of 8 consecutive tile
         // rows, so the neighbour rows of a tile are read by the same L2
         h.a.tm.blk = 8;
         h.a.tm.per = h.a.tm.tx * (((h.a.tm.nrows + 63) / 64) * 8);
-        h.M = s.d_M;
-        h.tau = s.lv[0].tau;
+        h.M = L.d_M;
+        h.tau = L.tau;
         h.sigma = s.cfg.hrr_sigma;
         h.psi = s.cfg.hrr_psi ? 1 : 0;
+        h.Mring = L.d_Mring;
+        if (L.has_child) {
+            const HostLevel& C = s.lv[l + 1];
+            h.M_child = C.d_M;
+            h.cn[0] = C.nx;
+            h.cn[1] = C.ny;
+            h.cn[2] = C.nz;
+        }
+        if (l > 0) h.Mring_parent = s.lv[l - 1].d_Mring;
+        for (int e = 0; e < 3; ++e) h.plo[e] = L.plo[e];
+        h.Gtf = L.d_Gtf;
+        h.ie_tf = L.d_ie_tf;
+        h.nb_bulk = bulk_groups(h.a.tm.per, 1);
         return h;
+    }
+    void hrr_open(Sim& s, int l, int substep, int first) override
+    {
+        unsigned grid = 0;
+        const LevelArgs a = level_args(s, l, substep, first, &grid);
+        const HrrArgs h = hrr_args(s, a, l);
+        hipLaunchKernelGGL((k_hrr_macros<DIM, EQ, P>), dim3(a.nb_probe + a.nb_cap + h.nb_bulk), dim3(kBlock), 0, s.stream,
+                           h);
+        if (l > 0 && a.nb_seg > 0)
+            hipLaunchKernelGGL((k_hrr_iface<DIM, EQ, P>), dim3(a.nb_seg), dim3(kBlock), 0, s.stream, h.a);
+    }
+    void hrr_close(Sim& s, int l, int substep, int first) override
+    {
+        unsigned grid = 0;
+        const LevelArgs a = level_args(s, l, substep, first, &grid);
+        const HrrArgs h = hrr_args(s, a, l);
+        const unsigned gtf = (unsigned)((a.n_tf + kBlock - 1) / kBlock);
+        const unsigned gie = (unsigned)((a.n_ie + kBlock - 1) / kBlock);
+        const unsigned gtfc = (unsigned)((a.n_cap + kBlock - 1) / kBlock);
+        if (l > 0 && gtf > 0)
+            hipLaunchKernelGGL((k_hrr_grad_tf<DIM, EQ, P>), dim3(gtf), dim3(kBlock), 0, s.stream, h);
+        hipLaunchKernelGGL((k_hrr_collide<DIM, EQ, P>), dim3(h.nb_bulk + gtf + gie + gtfc), dim3(kBlock), 0, s.stream, h);
+    }
+    void hrr_ring_init(Sim& s, int l, const double* rho, const double* u) override
+    {
+        const HostLevel& L = s.lv[l];
+        const int64_t n = L.n_dense();
+        hipLaunchKernelGGL((k_hrr_ring_init<DIM, P>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s.stream, L.dev(),
+                           L.d_Mring, rho, u);
     }
     void probe(Sim& s) override
     {

@@ -418,6 +418,11 @@ struct LevelArgs {
     const ProbeArgs* probe; // the probe buffers of the state this launch starts from
     double* series;
     int64_t* counter;       // [0] steps sampled, [1] coarse steps started
+    // H-RR on refined meshes: the interface role stores completed
+    // pre-collision populations and their macroscopic state instead of
+    // colliding (the level collides after its child's substeps)
+    void* M;                // this level's (drho, du) [4][n]
+    void* M_parent;         // the parent's, for its co-located nodes at the synchronous substep
 };
 
 // A non-finite or non-positive density (a run that has become unstable)
@@ -477,7 +482,25 @@ __device__ __forceinline__ void role_capture(const LevelArgs& a, int b)
     }
 }
 
-template <int DIM, int EQ, int P, bool ROLLED>
+template <int DIM>
+__device__ __forceinline__ int64_t dense_index(const LevelDev& g, int x, int y, int z)
+{
+    return ((int64_t)z * g.ny + y) * g.nx + x;
+}
+
+// (drho, du) of node d into a [4][n] array
+template <typename R>
+__device__ __forceinline__ void put_mac(void* Mv, int64_t n, int64_t d, R drho, const R du[3])
+{
+    R* M = (R*)Mv;
+    M[d] = drho;
+    M[n + d] = du[0];
+    M[2 * n + d] = du[1];
+    M[3 * n + d] = du[2];
+}
+
+// HRR: the H-RR refined-mesh mode (no collision; see LevelArgs::M).
+template <int DIM, int EQ, int P, bool ROLLED, bool HRR = false>
 __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typename Form<P>::R* lds,
                                              std::bool_constant<ROLLED> = {})
 {
@@ -577,7 +600,8 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
             X[3 * n + t] = mx.du[2];
             if (a.substep == 2) {
                 // Eq.(rescfc): every coarse population from the completed fine
-                // ones, then the coarse collision with X
+                // ones, then the coarse collision with X (H-RR: the coarse
+                // level collides them later, from these values and X)
                 const int4 pm = a.tfc_meta[t];
                 const R invR = R(1.0 / a.Rfac), keepp = R(a.keep_parent);
                 T* dp = (T*)a.dst_parent;
@@ -585,15 +609,22 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
                 for (int i = 0; i < Q; ++i) {
                     const R e0 = eq0(i);
                     const R c = e0 + invR * (col[i * TFM] - e0);
-                    F::store_wb(dp + eoff<DIM>(a.gp, i, pm.x, pm.y, pm.z), e0 + keepp * (c - e0));
+                    F::store_wb(dp + eoff<DIM>(a.gp, i, pm.x, pm.y, pm.z), HRR ? c : e0 + keepp * (c - e0));
                 }
+                if constexpr (HRR)
+                    put_mac<R>(a.M_parent, (int64_t)a.gp.nx * a.gp.ny * a.gp.nz,
+                               dense_index<DIM>(a.gp, pm.x, pm.y, pm.z), mx.drho, mx.du);
             }
             const R keep = R(a.keep);
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const R e0 = eq0(i);
-                F::store_wb(node_elem<DIM>(a.g, dst, a.par ^ 1, i, m.x, m.y, m.z), e0 + keep * (col[i * TFM] - e0));
+                F::store_wb(node_elem<DIM>(a.g, dst, a.par ^ 1, i, m.x, m.y, m.z),
+                            HRR ? R(col[i * TFM]) : e0 + keep * (col[i * TFM] - e0));
             }
+            if constexpr (HRR)
+                put_mac<R>(a.M, (int64_t)a.g.nx * a.g.ny * a.g.nz, dense_index<DIM>(a.g, m.x, m.y, m.z), mx.drho,
+                           mx.du);
         }
     }
     __syncthreads();
@@ -642,7 +673,10 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
         moments<DIM, R>(s, drho, jj);
         flag_unstable((SH ? R(1) : R(0)) + drho, a.flags);
         velocity<DIM, SH, R>(rf, drho, jj, du);
-        bgk<DIM, EQ, SH, R>(s, rf, make_mac<DIM, SH, R>(rf, drho, du), R(a.keep));
+        if constexpr (HRR)
+            put_mac<R>(a.M, (int64_t)a.g.nx * a.g.ny * a.g.nz, dense_index<DIM>(a.g, m.x, m.y, m.z), drho, du);
+        else
+            bgk<DIM, EQ, SH, R>(s, rf, make_mac<DIM, SH, R>(rf, drho, du), R(a.keep));
 #pragma unroll
         for (int i = 0; i < Q; ++i) F::store_wb(node_elem<DIM>(a.g, dst, a.par ^ 1, i, m.x, m.y, m.z), s[i]);
     }
@@ -1101,13 +1135,17 @@ __global__ __launch_bounds__(kBlock) void k_level_top(LevelArgs a)
     level_block<DIM, EQ, P, true, false>(a, blockIdx.x, nullptr);
 }
 
-// ---------------------------------------------------------------- H-RR collision (one periodic level)
+// ---------------------------------------------------------------- H-RR collision
 // The hybrid recursive regularised collision of Sec. 2 needs the velocity
-// and third-order moment gradients of the post-streaming state, so a step is
-// two launches over the bulk tiles: k_hrr_macros pulls and writes each
-// node's (drho, du) into M; k_hrr_collide pulls again, reads M at the node
-// and its 2 D axis neighbours (centred differences, Eq.(a1FD_scheme),
-// Eq.(PSI_FD)) and collides:
+// and third-order moment gradients of the post-streaming state, so a level
+// substep takes separate launches: k_hrr_macros pulls and writes each bulk
+// node's (drho, du) into M; on a refined level the interface tiles
+// (role_segment in its H-RR mode) complete the co-located and hanging nodes
+// and write their populations and M without colliding; after the child's
+// substeps k_hrr_grad_tf forms the co-located nodes' gradients on the
+// coarse stencil, and k_hrr_collide pulls the bulk again, reads M at each
+// node and its 2 D axis neighbours (centred differences, Eq.(a1FD_scheme),
+// Eq.(PSI_FD)) and collides every node:
 //   psi_i   = -w_i/(2c^4) H2_i:(div Psi)          (App. A; the sign that
 //             cancels the lattice's missing third-order moments Psi)
 //   a1      = sigma sum_i H2_i (f_i - f0_i + psi_i/2) + (1 - sigma) a1FD
@@ -1115,19 +1153,29 @@ __global__ __launch_bounds__(kBlock) void k_level_top(LevelArgs a)
 //   f*_i    = f0_i + (1 - 1/tau) w_i [H2_i:a1/(2c^4)
 //             + sum_{a!=b} H3_{i,aab} (2 u_a a1_ab + u_b a1_aa)/(2c^6)] + psi_i/2
 // with Psi = rho u_a^3 on aaa and, in D3Q19, rho u_b u_g^2/2 on aab (g the
-// remaining axis) and rho u_x u_y u_z on xyz.
+// remaining axis) and rho u_x u_y u_z on xyz.  Gradients by node class
+// (Sec. 3.3, Sec. 3.5): bulk and coarse co-located nodes use the level's
+// stencil (a neighbour in the hole takes the child node co-located with
+// it); fine co-located nodes the coarse stencil of +-2 fine cells, whose
+// points outside the level are parent nodes (time-interpolated at the
+// asynchronous substep), so that the difference over 4 fine cells is the
+// S^c/2, psi^c/2 of Eq.(PijResc), Eq.(PSIResc); hanging nodes interpolate
+// the co-located nodes' gradients with their populations' weights.
 struct HrrArgs {
-    LevelArgs a;          // level 0 of a single simulation: source, destination, tiles, probes, flags
+    LevelArgs a;          // the level substep: source, destination, tiles, probes, captures, flags
     void* M;              // [4][n] (drho, du) of every node, arithmetic type, x fastest
     double tau, sigma;
     int psi;              // cubic Mach correction on
+    // refined meshes (null / 0 on a single level)
+    void* Mring;              // this level's post-streaming (drho, du) at the coarse times t-dt, t, t+dt, [3][4][n]
+    const void* M_child;      // the child's M (gradients of this level's coarse co-located nodes)
+    int cn[3];                // the child's extents
+    const void* Mring_parent; // the parent's ring (gradients of this level's co-located nodes)
+    int plo[3];               // this level's box origin in the parent's node coordinates
+    void* Gtf;                // [18][n_tf] gradients of this level's co-located nodes (d_b u_a, div Psi)
+    const int* ie_tf;         // [16][n_ie] co-located indices of each hanging node's stencil
+    int nb_bulk;              // bulk workgroups of the collide launch (then co-located, hanging, coarse co-located)
 };
-
-template <int DIM>
-__device__ __forceinline__ int64_t dense_index(const LevelDev& g, int x, int y, int z)
-{
-    return ((int64_t)z * g.ny + y) * g.nx + x;
-}
 
 // Psi_abg of Eq.(Psi) at one node, for the index pattern (a, b, g).
 template <int DIM, typename R>
@@ -1142,98 +1190,56 @@ __device__ __forceinline__ R hrr_Psi(int a, int b, int g, R rho, const R u[3])
     return R(0.5) * rho * u[sgl] * u[third] * u[third];
 }
 
-template <int DIM, int EQ, int P>
-__global__ __launch_bounds__(kBlock) void k_hrr_macros(HrrArgs h)
+// (rho, u) of the carried (drho, du) at a [4][n] array's entry d.
+template <int DIM, bool SH, typename R>
+__device__ __forceinline__ void rho_u_at(const R* M, int64_t n, int64_t d, const Ref<R>& rf, R& rho, R u[3])
 {
-    using F = Form<P>;
-    using R = typename F::R;
-    constexpr int Q = Lat<DIM>::Q;
-    const LevelArgs& a = h.a;
-    int b = blockIdx.x;
-    if (b < a.nb_probe) {
-        // the previous coarse step's probes, from the state this step reads
-        const int64_t started = a.counter[1];
-        probe_pending<DIM, P>(*a.probe, a.series, a.counter);
-        __syncthreads();
-        if (threadIdx.x == 0) a.counter[1] = started + 1;
-        return;
-    }
-    b -= a.nb_probe;
-    R s[Q];
-    int64_t e0 = 0;
-    int xyz[3];
-    if (!bulk_load<DIM, P>(a, b, s, e0, xyz)) return;
-    const LevelDev& g = a.g;
-    const int x = xyz[0], y = xyz[1], z = xyz[2];
-    constexpr bool SH = F::shifted;
-    const Ref<R> rf = ref_of<R>(g);
-    R drho, j[3], du[3];
-    moments<DIM, R>(s, drho, j);
-    flag_unstable((SH ? R(1) : R(0)) + drho, a.flags);
-    velocity<DIM, SH, R>(rf, drho, j, du);
-    R* M = (R*)h.M;
-    const int64_t n = (int64_t)g.nx * g.ny * g.nz, d = dense_index<DIM>(g, x, y, z);
-    M[d] = drho;
-    M[n + d] = du[0];
-    M[2 * n + d] = du[1];
-    M[3 * n + d] = du[2];
+    rho = (SH ? R(1) : R(0)) + M[d];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = (k < DIM ? M[(1 + k) * n + d] : R(0)) + (SH ? rf.ur[k] : R(0));
 }
 
-template <int DIM, int EQ, int P>
-__global__ __launch_bounds__(kBlock) void k_hrr_collide(HrrArgs h)
+// Centred differences along axis c from the two stencil points (index 0 at
+// -h, 1 at +h): inv2h = 1 / (2 h).
+template <int DIM, typename R>
+__device__ __forceinline__ void hrr_axis(int c, R inv2h, const R rn[2], const R un[2][3], int psi, R gradu[3][3],
+                                         R dPsi[3][3])
 {
-    using F = Form<P>;
-    using T = typename F::T;
-    using R = typename F::R;
-    constexpr int Q = Lat<DIM>::Q;
-    constexpr bool SH = F::shifted;
-    const LevelArgs& a = h.a;
-    const int b = blockIdx.x;
-    R s[Q];
-    int64_t e0 = 0;
-    int xyz[3];
-    if (!bulk_load<DIM, P>(a, b, s, e0, xyz)) return;
-    const LevelDev& g = a.g;
-    const int x = xyz[0], y = xyz[1], z = xyz[2];
-    const Ref<R> rf = ref_of<R>(g);
-    const R* M = (const R*)h.M;
-    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
-    // this node's macroscopic state (as written by k_hrr_macros from the same pulls)
-    const int64_t d0 = dense_index<DIM>(g, x, y, z);
-    R du0[3] = {M[n + d0], M[2 * n + d0], M[3 * n + d0]};
-    const Mac<R> mc = make_mac<DIM, SH, R>(rf, M[d0], du0);
-    const R rho = (SH ? R(1) : R(0)) + mc.drho;
-    // neighbours -e_c (0) and +e_c (1) along each axis, periodic
-    const int p3[3] = {x, y, z}, n3[3] = {g.nx, g.ny, g.nz};
-    R gradu[3][3], dPsi[3][3];
+    // d_c u_a (du differences equal u differences)
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) gradu[k][c] = inv2h * (un[1][k] - un[0][k]);
+    if (psi) {
+#pragma unroll
+        for (int p = 0; p < DIM; ++p)
+#pragma unroll
+            for (int q = p; q < DIM; ++q)
+                dPsi[p][q] += inv2h * (hrr_Psi<DIM, R>(p, q, c, rn[1], un[1]) - hrr_Psi<DIM, R>(p, q, c, rn[0], un[0]));
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void zero33(R a[3][3])
+{
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) gradu[r][c] = dPsi[r][c] = R(0);
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-        R un[2][3], rn[2];
-#pragma unroll
-        for (int sg = 0; sg < 2; ++sg) {
-            int q3[3] = {p3[0], p3[1], p3[2]};
-            q3[c] += sg ? 1 : -1;
-            q3[c] = q3[c] < 0 ? q3[c] + n3[c] : (q3[c] >= n3[c] ? q3[c] - n3[c] : q3[c]);
-            const int64_t dn = dense_index<DIM>(g, q3[0], q3[1], q3[2]);
-            rn[sg] = (SH ? R(1) : R(0)) + M[dn];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) un[sg][k] = (k < DIM ? M[(1 + k) * n + dn] : R(0)) + (SH ? rf.ur[k] : R(0));
-        }
-        // d_c u_a (du differences equal u differences)
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) gradu[k][c] = R(0.5) * (un[1][k] - un[0][k]);
-        if (h.psi) {
-#pragma unroll
-            for (int p = 0; p < DIM; ++p)
-#pragma unroll
-                for (int q = p; q < DIM; ++q)
-                    dPsi[p][q] += R(0.5) * (hrr_Psi<DIM, R>(p, q, c, rn[1], un[1]) - hrr_Psi<DIM, R>(p, q, c, rn[0], un[0]));
-        }
-    }
+        for (int c = 0; c < 3; ++c) a[r][c] = R(0);
+}
+
+// The H-RR collision of one node in place: s holds its (completed)
+// pre-collision populations, mc its macroscopic state, gradu its velocity
+// gradients d_c u_a, dPsi the upper triangle of sum_g d_g Psi_abg.
+template <int DIM, int EQ, int P>
+__device__ __forceinline__ void hrr_collide_node(const LevelDev& g, const Ref<typename Form<P>::R>& rf,
+                                                 const Mac<typename Form<P>::R>& mc, typename Form<P>::R s[],
+                                                 typename Form<P>::R gradu[3][3], typename Form<P>::R dPsi[3][3],
+                                                 double keepd, double taud, double sigd, int psi_on)
+{
+    using F = Form<P>;
+    using R = typename F::R;
+    constexpr int Q = Lat<DIM>::Q;
+    constexpr bool SH = F::shifted;
+    const R rho = (SH ? R(1) : R(0)) + mc.drho;
 #pragma unroll
     for (int p = 0; p < DIM; ++p)
 #pragma unroll
@@ -1243,7 +1249,7 @@ __global__ __launch_bounds__(kBlock) void k_hrr_collide(HrrArgs h)
     //   sum_i H2_{i,pq} x_i = sum_{xi_p xi_q != 0} xi_p xi_q x_i - c^2 delta_pq sum_i x_i
     //   H2_i : A            = sum_{xi_p, xi_q != 0} xi_p xi_q A_pq - c^2 tr A
     constexpr R c2 = R(1) / R(3);
-    const R keep = R(a.keep), tau = R(h.tau), sig = R(h.sigma);
+    const R keep = R(keepd), tau = R(taud), sig = R(sigd);
     R trP = R(0);
 #pragma unroll
     for (int p = 0; p < DIM; ++p) trP += dPsi[p][p];
@@ -1260,14 +1266,11 @@ __global__ __launch_bounds__(kBlock) void k_hrr_collide(HrrArgs h)
                 if (cc == 1) t += dPsi[p][q];
                 if (cc == -1) t -= dPsi[p][q];
             }
-        psi[i] = h.psi ? -R(Lat<DIM>::w[i]) * R(4.5) * t : R(0);   // w_i / (2 c^4) = 4.5 w_i
+        psi[i] = psi_on ? -R(Lat<DIM>::w[i]) * R(4.5) * t : R(0);   // w_i / (2 c^4) = 4.5 w_i
     }
     // second moments of x_i = s_i - f0_i + psi_i / 2
     R m0 = R(0), m2[3][3];
-#pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) m2[p][q] = R(0);
+    zero33(m2);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const R xv = s[i] - f0[i] + R(0.5) * psi[i];
@@ -1320,10 +1323,303 @@ __global__ __launch_bounds__(kBlock) void k_hrr_collide(HrrArgs h)
         const R f1 = R(Lat<DIM>::w[i]) * (R(4.5) * t2 + R(13.5) * t3);   // 1/(2c^4), 1/(2c^6)
         s[i] = f0[i] + keep * f1 + R(0.5) * psi[i];
     }
-    T* dst = (T*)a.dst + e0;
-    const int64_t BX = (int64_t)1 << g.xsh;
+}
+
+// Probe, coarse capture and bulk workgroups of an H-RR level substep: each
+// bulk node's post-streaming (drho, du) into M (and, on a level with a child,
+// into the newest slot of its ring, the older slots shifted as the
+// population ring is).
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(kBlock) void k_hrr_macros(HrrArgs h)
+{
+    using F = Form<P>;
+    using R = typename F::R;
+    constexpr int Q = Lat<DIM>::Q;
+    const LevelArgs& a = h.a;
+    int b = blockIdx.x;
+    if (b < a.nb_probe) {
+        // the previous coarse step's probes, from the state this step reads
+        const int64_t started = a.counter[1];
+        probe_pending<DIM, P>(*a.probe, a.series, a.counter);
+        __syncthreads();
+        if (threadIdx.x == 0) a.counter[1] = started + 1;
+        return;
+    }
+    b -= a.nb_probe;
+    if (b < a.nb_cap) {
+        role_capture<DIM, P>(a, b);
+        return;
+    }
+    b -= a.nb_cap;
+    R s[Q];
+    int64_t e0 = 0;
+    int xyz[3];
+    if (!bulk_load<DIM, P>(a, b, s, e0, xyz)) return;
+    const LevelDev& g = a.g;
+    const int x = xyz[0], y = xyz[1], z = xyz[2];
+    constexpr bool SH = F::shifted;
+    const Ref<R> rf = ref_of<R>(g);
+    R drho, j[3], du[3];
+    moments<DIM, R>(s, drho, j);
+    flag_unstable((SH ? R(1) : R(0)) + drho, a.flags);
+    velocity<DIM, SH, R>(rf, drho, j, du);
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz, d = dense_index<DIM>(g, x, y, z);
+    put_mac<R>(h.M, n, d, drho, du);
+    if (h.Mring) {
+        R* Rg = (R*)h.Mring;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) F::store(dst + i * BX, s[i]);
+        for (int c = 0; c < 4; ++c) {
+            const R r1 = Rg[(4 + c) * n + d], r2 = Rg[(8 + c) * n + d];
+            Rg[c * n + d] = r1;
+            Rg[(4 + c) * n + d] = r2;
+        }
+        put_mac<R>(Rg + 8 * n, n, d, drho, du);
+    }
+}
+
+// The interface tiles of an H-RR refined level substep (no collision).
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(kBlock) void k_hrr_iface(LevelArgs a)
+{
+    using R = typename Form<P>::R;
+    __shared__ R lds[Lat<DIM>::Q * SegLimits<DIM>::TF];
+    if ((int)blockIdx.x < a.nb_seg) role_segment<DIM, EQ, P, true, true>(a, blockIdx.x, lds);
+}
+
+// Gradients of the co-located nodes of a refined level (one thread each), on
+// the coarse stencil: the points +-2 fine cells along each axis inside the
+// level are its own nodes, those outside are parent nodes, whose ring is
+// read with the weights of Eq.(TempInt) at the asynchronous substep (linear
+// while the parent has one capture) and at t + dt^c at the synchronous one.
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(kBlock) void k_hrr_grad_tf(HrrArgs h)
+{
+    using F = Form<P>;
+    using R = typename F::R;
+    constexpr bool SH = F::shifted;
+    const LevelArgs& a = h.a;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= a.n_tf) return;
+    const int4 m = a.tf_meta[t];
+    const LevelDev& g = a.g;
+    const LevelDev& gp = a.gp;
+    const Ref<R> rf = ref_of<R>(g);
+    const R* M = (const R*)h.M;
+    const R* Rp = (const R*)h.Mring_parent;
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz, np = (int64_t)gp.nx * gp.ny * gp.nz;
+    const int k[3] = {m.x, m.y, m.z}, n3[3] = {g.nx, g.ny, g.nz};
+    R gradu[3][3], dPsi[3][3];
+    zero33(gradu);
+    zero33(dPsi);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        R rn[2], un[2][3];
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+            int q3[3] = {k[0], k[1], k[2]};
+            q3[c] += sg ? 2 : -2;
+            if (q3[c] >= 0 && q3[c] < n3[c]) {
+                rho_u_at<DIM, SH, R>(M, n, dense_index<DIM>(g, q3[0], q3[1], q3[2]), rf, rn[sg], un[sg]);
+            } else {
+                int P3[3] = {0, 0, 0};
+#pragma unroll
+                for (int e = 0; e < DIM; ++e) P3[e] = h.plo[e] + k[e] / 2;
+                P3[c] += sg ? 1 : -1;
+                const int64_t dp = dense_index<DIM>(gp, P3[0], P3[1], P3[2]);
+                R v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const R Hm = Rp[e * np + dp], H0 = Rp[(4 + e) * np + dp], Hp = Rp[(8 + e) * np + dp];
+                    v[e] = a.substep == 2 ? Hp
+                                          : (a.first ? R(0.5) * H0 + R(0.5) * Hp
+                                                     : R(-0.125) * Hm + R(0.75) * H0 + R(0.375) * Hp);
+                }
+                rn[sg] = (SH ? R(1) : R(0)) + v[0];
+#pragma unroll
+                for (int e = 0; e < 3; ++e) un[sg][e] = (e < DIM ? v[1 + e] : R(0)) + (SH ? rf.ur[e] : R(0));
+            }
+        }
+        hrr_axis<DIM, R>(c, R(0.25), rn, un, h.psi, gradu, dPsi);
+    }
+    R* G = (R*)h.Gtf;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            G[(3 * p + q) * (int64_t)a.n_tf + t] = gradu[p][q];
+            G[(9 + 3 * p + q) * (int64_t)a.n_tf + t] = dPsi[p][q];
+        }
+}
+
+// Macroscopic state of a node from M.
+template <int DIM, bool SH, typename R>
+__device__ __forceinline__ Mac<R> mac_at(const R* M, int64_t n, int64_t d, const Ref<R>& rf)
+{
+    R du[3] = {M[n + d], M[2 * n + d], M[3 * n + d]};
+    return make_mac<DIM, SH, R>(rf, M[d], du);
+}
+
+// Workgroups of an H-RR collide launch: the bulk tiles (pulled again), then
+// on a refined level its co-located nodes, its hanging nodes, and, on a
+// level with a child, its coarse co-located nodes (these three read their
+// completed populations back from the destination).
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(kBlock) void k_hrr_collide(HrrArgs h)
+{
+    using F = Form<P>;
+    using T = typename F::T;
+    using R = typename F::R;
+    constexpr int Q = Lat<DIM>::Q;
+    constexpr bool SH = F::shifted;
+    const LevelArgs& a = h.a;
+    const LevelDev& g = a.g;
+    const Ref<R> rf = ref_of<R>(g);
+    const R* M = (const R*)h.M;
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const int n3[3] = {g.nx, g.ny, g.nz};
+    int b = blockIdx.x;
+    R s[Q], gradu[3][3], dPsi[3][3];
+    zero33(gradu);
+    zero33(dPsi);
+    if (b < h.nb_bulk) {
+        int64_t e0 = 0;
+        int xyz[3];
+        if (!bulk_load<DIM, P>(a, b, s, e0, xyz)) return;
+        // this node's macroscopic state (as written by k_hrr_macros from the same pulls)
+        const int64_t d0 = dense_index<DIM>(g, xyz[0], xyz[1], xyz[2]);
+        const Mac<R> mc = mac_at<DIM, SH, R>(M, n, d0, rf);
+        // neighbours -e_c (0) and +e_c (1) along each axis, periodic on level 0
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            R un[2][3], rn[2];
+#pragma unroll
+            for (int sg = 0; sg < 2; ++sg) {
+                int q3[3] = {xyz[0], xyz[1], xyz[2]};
+                q3[c] += sg ? 1 : -1;
+                q3[c] = q3[c] < 0 ? q3[c] + n3[c] : (q3[c] >= n3[c] ? q3[c] - n3[c] : q3[c]);
+                rho_u_at<DIM, SH, R>(M, n, dense_index<DIM>(g, q3[0], q3[1], q3[2]), rf, rn[sg], un[sg]);
+            }
+            hrr_axis<DIM, R>(c, R(0.5), rn, un, h.psi, gradu, dPsi);
+        }
+        hrr_collide_node<DIM, EQ, P>(g, rf, mc, s, gradu, dPsi, a.keep, h.tau, h.sigma, h.psi);
+        T* dst = (T*)a.dst + e0;
+        const int64_t BX = (int64_t)1 << g.xsh;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) F::store(dst + i * BX, s[i]);
+        return;
+    }
+    b -= h.nb_bulk;
+    const int ntf = a.tf_meta ? a.n_tf : 0, nie = a.ie_meta ? a.n_ie : 0;
+    const int gtf = (ntf + kBlock - 1) / kBlock, gie = (nie + kBlock - 1) / kBlock;
+    const R* G = (const R*)h.Gtf;
+    T* dst = (T*)a.dst;
+    int4 m;
+    if (b < gtf) {
+        // co-located nodes: gradients from k_hrr_grad_tf
+        const int t = b * kBlock + threadIdx.x;
+        if (t >= ntf) return;
+        m = a.tf_meta[t];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                gradu[p][q] = G[(3 * p + q) * (int64_t)ntf + t];
+                dPsi[p][q] = G[(9 + 3 * p + q) * (int64_t)ntf + t];
+            }
+    } else if (b < gtf + gie) {
+        // hanging nodes: the co-located nodes' gradients with the weights of
+        // their populations' 4-point stencils (the first odd axis fastest)
+        const int q0 = (b - gtf) * kBlock + threadIdx.x;
+        if (q0 >= nie) return;
+        m = a.ie_meta[q0];
+        const int k[3] = {m.x, m.y, m.z};
+        const int N[3] = {g.nx - 1, g.ny - 1, g.nz - 1};
+        int ka = 0, Na = 0, kb = 0, Nb = 0, no = 0;
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) {
+            if (k[ax] & 1) {
+                if (no == 0) {
+                    ka = k[ax];
+                    Na = N[ax];
+                } else {
+                    kb = k[ax];
+                    Nb = N[ax];
+                }
+                ++no;
+            }
+        }
+        float w0[4], w1[4] = {1.f, 0.f, 0.f, 0.f};
+        line_weights(ka, Na, w0);
+        if (no == 2) line_weights(kb, Nb, w1);
+        const int ns = no == 2 ? 16 : 4;
+        for (int qq = 0; qq < ns; ++qq) {
+            const int t = h.ie_tf[(int64_t)qq * nie + q0];
+            const R wq = R(w0[qq & 3]) * R(w1[qq >> 2]);
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    gradu[p][q] += wq * G[(3 * p + q) * (int64_t)ntf + t];
+                    dPsi[p][q] += wq * G[(9 + 3 * p + q) * (int64_t)ntf + t];
+                }
+        }
+    } else {
+        // coarse co-located nodes: the level's stencil, a neighbour in the
+        // hole taken from the child node co-located with it
+        const int t = (b - gtf - gie) * kBlock + threadIdx.x;
+        if (t >= a.n_cap) return;
+        m = a.cap_meta[t];
+        const R* Mc = (const R*)h.M_child;
+        const int64_t nc = (int64_t)h.cn[0] * h.cn[1] * h.cn[2];
+        const int k[3] = {m.x, m.y, m.z};
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            R un[2][3], rn[2];
+#pragma unroll
+            for (int sg = 0; sg < 2; ++sg) {
+                int q3[3] = {k[0], k[1], k[2]};
+                q3[c] += sg ? 1 : -1;
+                q3[c] = q3[c] < 0 ? q3[c] + n3[c] : (q3[c] >= n3[c] ? q3[c] - n3[c] : q3[c]);
+                if (is_hole<DIM>(g, q3[0], q3[1], q3[2])) {
+                    const int cx = 2 * (q3[0] - g.clo[0]), cy = 2 * (q3[1] - g.clo[1]),
+                              cz = DIM == 3 ? 2 * (q3[2] - g.clo[2]) : 0;
+                    rho_u_at<DIM, SH, R>(Mc, nc, ((int64_t)cz * h.cn[1] + cy) * h.cn[0] + cx, rf, rn[sg], un[sg]);
+                } else {
+                    rho_u_at<DIM, SH, R>(M, n, dense_index<DIM>(g, q3[0], q3[1], q3[2]), rf, rn[sg], un[sg]);
+                }
+            }
+            hrr_axis<DIM, R>(c, R(0.5), rn, un, h.psi, gradu, dPsi);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) s[i] = F::load(node_elem<DIM>(g, dst, a.par ^ 1, i, m.x, m.y, m.z));
+    const Mac<R> mc = mac_at<DIM, SH, R>(M, n, dense_index<DIM>(g, m.x, m.y, m.z), rf);
+    hrr_collide_node<DIM, EQ, P>(g, rf, mc, s, gradu, dPsi, a.keep, h.tau, h.sigma, h.psi);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) F::store_wb(node_elem<DIM>(g, dst, a.par ^ 1, i, m.x, m.y, m.z), s[i]);
+}
+
+// The three slots of an H-RR level's macroscopic-field ring from its initial
+// fields (dense FP64 rho [n], u [D][n]), in the carried variables.
+template <int DIM, int P>
+__global__ __launch_bounds__(256) void k_hrr_ring_init(LevelDev g, void* Mring, const double* __restrict__ rho,
+                                                       const double* __restrict__ u)
+{
+    using F = Form<P>;
+    using R = typename F::R;
+    constexpr bool SH = F::shifted;
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= n) return;
+    R v[4];
+    v[0] = R(SH ? rho[d] - 1.0 : rho[d]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[1 + k] = k < DIM ? R(u[k * n + d] - (SH ? g.ur[k] : 0.0)) : R(0);
+    R* Rg = (R*)Mring;
+#pragma unroll
+    for (int slot = 0; slot < 3; ++slot)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Rg[(4 * slot + c) * n + d] = v[c];
 }
 
 // ---------------------------------------------------------------- history ring init

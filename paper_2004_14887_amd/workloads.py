@@ -44,7 +44,7 @@ class Workload:
     pulses: List[dict] = dataclasses.field(default_factory=list)
     rings: List[dict] = dataclasses.field(default_factory=list)      # 3-D vortex rings
     seed: int = 0
-    collision: str = "bgk"            # "bgk" | "hrr" (Sec. 2; single periodic level)
+    collision: str = "bgk"            # "bgk" | "hrr" (Sec. 2; Sec. 3.3 and 3.5 on refined meshes)
     hrr_sigma: float = 0.98
     hrr_psi: bool = True
 
