@@ -600,7 +600,6 @@ dclbm_status build_geometry(Sim& s)
             HostLevel& L = s.lv[l];
             L.off_M = take(4 * L.n_dense() * (int64_t)s.rsize);
             if (L.has_child) L.off_Mring = take(3 * 4 * L.n_dense() * (int64_t)s.rsize);
-            if (!L.tf_meta.empty()) L.off_Gtf = take(18 * (int64_t)L.tf_meta.size() * (int64_t)s.rsize);
             if (!L.ie_meta.empty()) L.off_ie_tf = take((int64_t)L.ie_tf.size() * 4);
         }
     s.need_bytes = (size_t)off;
@@ -661,7 +660,6 @@ dclbm_status sim_attach(Sim& s, void* d_workspace, size_t bytes, hipStream_t str
         for (auto& L : s.lv) {
             L.d_M = s.ws + L.off_M;
             L.d_Mring = L.has_child ? (void*)(s.ws + L.off_Mring) : nullptr;
-            L.d_Gtf = L.tf_meta.empty() ? nullptr : (void*)(s.ws + L.off_Gtf);
             L.d_ie_tf = L.ie_meta.empty() ? nullptr : s.at<int>(L.off_ie_tf);
             if (L.d_ie_tf) HIPCHECK(upload(s, L.d_ie_tf, L.ie_tf));
         }

@@ -50,7 +50,7 @@ struct HostLevel {
     // workspace offsets
     int64_t off_f[2] = {0, 0}, off_xf[2] = {0, 0}, off_tf = 0, off_ie = 0, off_X = 0, off_tfc = 0, off_H = 0, off_seg_info = 0,
             off_seg_tf = 0, off_seg_ie = 0, off_seg_sten = 0;
-    int64_t off_M = 0, off_Mring = 0, off_Gtf = 0, off_ie_tf = 0;   // H-RR
+    int64_t off_M = 0, off_Mring = 0, off_ie_tf = 0;   // H-RR
     // device pointers
     void* f[2] = {nullptr, nullptr};
     void* xf[2] = {nullptr, nullptr};
@@ -60,7 +60,7 @@ struct HostLevel {
     // H-RR: (drho, du) of every node [4][n]; its post-streaming values at the
     // coarse times t-dt, t, t+dt [3][4][n] (level with a child); gradients of
     // the co-located nodes [18][n_tf]; hanging-node stencils [16][n_ie]
-    void *d_M = nullptr, *d_Mring = nullptr, *d_Gtf = nullptr;
+    void *d_M = nullptr, *d_Mring = nullptr;
     int* d_ie_tf = nullptr;
     int parity = 0;
     int64_t captures = 0;

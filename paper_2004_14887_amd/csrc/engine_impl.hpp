@@ -38,12 +38,12 @@ struct EngineImpl final : Engine {
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 s.note(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
                 s.note(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
-                hipExtLaunchKernelGGL((k_hrr_macros<DIM, EQ, P>), dim3(a.nb_probe + g_bulk), dim3(kBlock), 0, s.stream, e0,
+                hipExtLaunchKernelGGL((k_hrr_macros<DIM, EQ, P, false>), dim3(a.nb_probe + g_bulk), dim3(kBlock), 0, s.stream, e0,
                                       nullptr, 0, h);
                 hipExtLaunchKernelGGL((k_hrr_collide<DIM, EQ, P>), dim3(g_bulk), dim3(kBlock), 0, s.stream, nullptr, e1, 0, h);
                 s.tev[l].push_back({e0, e1});
             } else {
-                hipLaunchKernelGGL((k_hrr_macros<DIM, EQ, P>), dim3(a.nb_probe + g_bulk), dim3(kBlock), 0, s.stream, h);
+                hipLaunchKernelGGL((k_hrr_macros<DIM, EQ, P, false>), dim3(a.nb_probe + g_bulk), dim3(kBlock), 0, s.stream, h);
                 hipLaunchKernelGGL((k_hrr_collide<DIM, EQ, P>), dim3(g_bulk), dim3(kBlock), 0, s.stream, h);
             }
             return;
@@ -131,7 +131,7 @@ struct EngineImpl final : Engine {
         if (s.hrr) {
             HrrArgs h = hrr_args(s, a, r.level);
             const unsigned g_bulk = (unsigned)bulk_groups(h.a.tm.per, 1);
-            e = kernel_node(g, reinterpret_cast<const void*>(&k_hrr_macros<DIM, EQ, P>), a.nb_probe + g_bulk, &h, deps, &n0);
+            e = kernel_node(g, reinterpret_cast<const void*>(&k_hrr_macros<DIM, EQ, P, false>), a.nb_probe + g_bulk, &h, deps, &n0);
             if (e != hipSuccess) return e;
             e = kernel_node(g, reinterpret_cast<const void*>(&k_hrr_collide<DIM, EQ, P>), g_bulk, &h, {n0}, &n1);
             deps.assign(1, n1);
@@ -187,9 +187,16 @@ struct EngineImpl final : Engine {
             h.cn[1] = C.ny;
             h.cn[2] = C.nz;
         }
-        if (l > 0) h.Mring_parent = s.lv[l - 1].d_Mring;
+        // the ring's slots rotate: a level's c-th capture writes slot c % 3,
+        // so after c captures the values at t - dt, t, t + dt sit in slots
+        // c % 3, (c + 1) % 3, (c + 2) % 3
+        h.ring_new = (int)(L.captures % 3);
+        if (l > 0) {
+            const int64_t cp = s.lv[l - 1].captures;
+            h.Mring_parent = s.lv[l - 1].d_Mring;
+            for (int e = 0; e < 3; ++e) h.pslot[e] = (int)((cp + e) % 3);
+        }
         for (int e = 0; e < 3; ++e) h.plo[e] = L.plo[e];
-        h.Gtf = L.d_Gtf;
         h.ie_tf = L.d_ie_tf;
         h.nb_bulk = bulk_groups(h.a.tm.per, 1);
         return h;
@@ -199,10 +206,11 @@ struct EngineImpl final : Engine {
         unsigned grid = 0;
         const LevelArgs a = level_args(s, l, substep, first, &grid);
         const HrrArgs h = hrr_args(s, a, l);
-        hipLaunchKernelGGL((k_hrr_macros<DIM, EQ, P>), dim3(a.nb_probe + a.nb_cap + h.nb_bulk), dim3(kBlock), 0, s.stream,
-                           h);
-        if (l > 0 && a.nb_seg > 0)
-            hipLaunchKernelGGL((k_hrr_iface<DIM, EQ, P>), dim3(a.nb_seg), dim3(kBlock), 0, s.stream, h.a);
+        const dim3 grid_m(a.nb_probe + a.nb_seg + a.nb_cap + h.nb_bulk);
+        if (a.nb_seg > 0)
+            hipLaunchKernelGGL((k_hrr_macros<DIM, EQ, P, true>), grid_m, dim3(kBlock), 0, s.stream, h);
+        else
+            hipLaunchKernelGGL((k_hrr_macros<DIM, EQ, P, false>), grid_m, dim3(kBlock), 0, s.stream, h);
     }
     void hrr_close(Sim& s, int l, int substep, int first) override
     {
@@ -212,8 +220,6 @@ struct EngineImpl final : Engine {
         const unsigned gtf = (unsigned)((a.n_tf + kBlock - 1) / kBlock);
         const unsigned gie = (unsigned)((a.n_ie + kBlock - 1) / kBlock);
         const unsigned gtfc = (unsigned)((a.n_cap + kBlock - 1) / kBlock);
-        if (l > 0 && gtf > 0)
-            hipLaunchKernelGGL((k_hrr_grad_tf<DIM, EQ, P>), dim3(gtf), dim3(kBlock), 0, s.stream, h);
         hipLaunchKernelGGL((k_hrr_collide<DIM, EQ, P>), dim3(h.nb_bulk + gtf + gie + gtfc), dim3(kBlock), 0, s.stream, h);
     }
     void hrr_ring_init(Sim& s, int l, const double* rho, const double* u) override

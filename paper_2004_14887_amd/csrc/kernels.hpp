@@ -1138,14 +1138,12 @@ __global__ __launch_bounds__(kBlock) void k_level_top(LevelArgs a)
 // ---------------------------------------------------------------- H-RR collision
 // The hybrid recursive regularised collision of Sec. 2 needs the velocity
 // and third-order moment gradients of the post-streaming state, so a level
-// substep takes separate launches: k_hrr_macros pulls and writes each bulk
-// node's (drho, du) into M; on a refined level the interface tiles
-// (role_segment in its H-RR mode) complete the co-located and hanging nodes
-// and write their populations and M without colliding; after the child's
-// substeps k_hrr_grad_tf forms the co-located nodes' gradients on the
-// coarse stencil, and k_hrr_collide pulls the bulk again, reads M at each
-// node and its 2 D axis neighbours (centred differences, Eq.(a1FD_scheme),
-// Eq.(PSI_FD)) and collides every node:
+// substep takes two launches: k_hrr_macros pulls and writes each bulk node's
+// (drho, du) into M and, on a refined level, completes the co-located and
+// hanging nodes (role_segment in its H-RR mode) and writes their populations
+// and M without colliding; after the child's substeps k_hrr_collide pulls
+// the bulk again, reads M at each node and its 2 D axis neighbours (centred
+// differences, Eq.(a1FD_scheme), Eq.(PSI_FD)) and collides every node:
 //   psi_i   = -w_i/(2c^4) H2_i:(div Psi)          (App. A; the sign that
 //             cancels the lattice's missing third-order moments Psi)
 //   a1      = sigma sum_i H2_i (f_i - f0_i + psi_i/2) + (1 - sigma) a1FD
@@ -1162,19 +1160,22 @@ __global__ __launch_bounds__(kBlock) void k_level_top(LevelArgs a)
 // S^c/2, psi^c/2 of Eq.(PijResc), Eq.(PSIResc); hanging nodes interpolate
 // the co-located nodes' gradients with their populations' weights.
 struct HrrArgs {
-    LevelArgs a;          // the level substep: source, destination, tiles, probes, captures, flags
+    LevelArgs a;          // the level substep: source, destination, tiles, probes, captures, segments, flags
     void* M;              // [4][n] (drho, du) of every node, arithmetic type, x fastest
     double tau, sigma;
     int psi;              // cubic Mach correction on
     // refined meshes (null / 0 on a single level)
-    void* Mring;              // this level's post-streaming (drho, du) at the coarse times t-dt, t, t+dt, [3][4][n]
+    void* Mring;              // this level's post-streaming (drho, du) at three coarse times, [3][4][n],
+                              // written only at the nodes next to the child's box (the ones its
+                              // co-located nodes' stencils reach)
+    int ring_new;             // physical slot of Mring that this substep's values go to
     const void* M_child;      // the child's M (gradients of this level's coarse co-located nodes)
     int cn[3];                // the child's extents
     const void* Mring_parent; // the parent's ring (gradients of this level's co-located nodes)
+    int pslot[3];             // physical slots of the parent's values at t - dt, t, t + dt
     int plo[3];               // this level's box origin in the parent's node coordinates
-    void* Gtf;                // [18][n_tf] gradients of this level's co-located nodes (d_b u_a, div Psi)
     const int* ie_tf;         // [16][n_ie] co-located indices of each hanging node's stencil
-    int nb_bulk;              // bulk workgroups of the collide launch (then co-located, hanging, coarse co-located)
+    int nb_bulk;              // bulk workgroups of either launch
 };
 
 // Psi_abg of Eq.(Psi) at one node, for the index pattern (a, b, g).
@@ -1325,16 +1326,23 @@ __device__ __forceinline__ void hrr_collide_node(const LevelDev& g, const Ref<ty
     }
 }
 
-// Probe, coarse capture and bulk workgroups of an H-RR level substep: each
-// bulk node's post-streaming (drho, du) into M (and, on a level with a child,
-// into the newest slot of its ring, the older slots shifted as the
-// population ring is).
-template <int DIM, int EQ, int P>
+// Workgroups of an H-RR macroscopic launch: the probe (level 0), the
+// interface segments (refined levels: completion of the co-located and
+// hanging nodes without collision), the coarse capture (levels with a
+// child), then the bulk tiles, each bulk node writing its post-streaming
+// (drho, du) into M and, next to the child's box, into the newest slot of
+// the level's ring.  The segments come first, so that their latency-bound
+// work overlaps the bulk (one launch measured 13% faster per coarse step
+// than the segments in a launch of their own beside it on a second stream).
+// SEG: the level has segments (without them the kernel holds no LDS and
+// needs fewer registers).
+template <int DIM, int EQ, int P, bool SEG>
 __global__ __launch_bounds__(kBlock) void k_hrr_macros(HrrArgs h)
 {
     using F = Form<P>;
     using R = typename F::R;
     constexpr int Q = Lat<DIM>::Q;
+    __shared__ R lds[SEG ? Q * SegLimits<DIM>::TF : 1];
     const LevelArgs& a = h.a;
     int b = blockIdx.x;
     if (b < a.nb_probe) {
@@ -1346,6 +1354,13 @@ __global__ __launch_bounds__(kBlock) void k_hrr_macros(HrrArgs h)
         return;
     }
     b -= a.nb_probe;
+    if constexpr (SEG) {
+        if (b < a.nb_seg) {
+            role_segment<DIM, EQ, P, true, true>(a, b, lds);
+            return;
+        }
+        b -= a.nb_seg;
+    }
     if (b < a.nb_cap) {
         role_capture<DIM, P>(a, b);
         return;
@@ -1365,50 +1380,32 @@ __global__ __launch_bounds__(kBlock) void k_hrr_macros(HrrArgs h)
     velocity<DIM, SH, R>(rf, drho, j, du);
     const int64_t n = (int64_t)g.nx * g.ny * g.nz, d = dense_index<DIM>(g, x, y, z);
     put_mac<R>(h.M, n, d, drho, du);
-    if (h.Mring) {
-        R* Rg = (R*)h.Mring;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const R r1 = Rg[(4 + c) * n + d], r2 = Rg[(8 + c) * n + d];
-            Rg[c * n + d] = r1;
-            Rg[(4 + c) * n + d] = r2;
-        }
-        put_mac<R>(Rg + 8 * n, n, d, drho, du);
-    }
+    // a bulk node within one node of the child's box (the box itself holds
+    // no bulk nodes)
+    if (h.Mring && x >= g.clo[0] - 1 && x <= g.chi[0] + 1 && y >= g.clo[1] - 1 && y <= g.chi[1] + 1 &&
+        (DIM == 2 || (z >= g.clo[2] - 1 && z <= g.chi[2] + 1)))
+        put_mac<R>((R*)h.Mring + (int64_t)h.ring_new * 4 * n, n, d, drho, du);
 }
 
-// The interface tiles of an H-RR refined level substep (no collision).
-template <int DIM, int EQ, int P>
-__global__ __launch_bounds__(kBlock) void k_hrr_iface(LevelArgs a)
+// Gradients of co-located node t of a refined level on the coarse stencil:
+// the points +-2 fine cells along each axis inside the level are its own
+// nodes, those outside are parent nodes, whose ring is read with the weights
+// of Eq.(TempInt) at the asynchronous substep (linear while the parent has
+// one capture) and at t + dt^c at the synchronous one.
+template <int DIM, bool SH, typename R>
+__device__ __forceinline__ void tf_gradients(const HrrArgs& h, int t, const Ref<R>& rf, R gradu[3][3], R dPsi[3][3])
 {
-    using R = typename Form<P>::R;
-    __shared__ R lds[Lat<DIM>::Q * SegLimits<DIM>::TF];
-    if ((int)blockIdx.x < a.nb_seg) role_segment<DIM, EQ, P, true, true>(a, blockIdx.x, lds);
-}
-
-// Gradients of the co-located nodes of a refined level (one thread each), on
-// the coarse stencil: the points +-2 fine cells along each axis inside the
-// level are its own nodes, those outside are parent nodes, whose ring is
-// read with the weights of Eq.(TempInt) at the asynchronous substep (linear
-// while the parent has one capture) and at t + dt^c at the synchronous one.
-template <int DIM, int EQ, int P>
-__global__ __launch_bounds__(kBlock) void k_hrr_grad_tf(HrrArgs h)
-{
-    using F = Form<P>;
-    using R = typename F::R;
-    constexpr bool SH = F::shifted;
     const LevelArgs& a = h.a;
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= a.n_tf) return;
     const int4 m = a.tf_meta[t];
     const LevelDev& g = a.g;
     const LevelDev& gp = a.gp;
-    const Ref<R> rf = ref_of<R>(g);
     const R* M = (const R*)h.M;
     const R* Rp = (const R*)h.Mring_parent;
     const int64_t n = (int64_t)g.nx * g.ny * g.nz, np = (int64_t)gp.nx * gp.ny * gp.nz;
+    const R* Hm = Rp + (int64_t)h.pslot[0] * 4 * np;
+    const R* H0 = Rp + (int64_t)h.pslot[1] * 4 * np;
+    const R* Hp = Rp + (int64_t)h.pslot[2] * 4 * np;
     const int k[3] = {m.x, m.y, m.z}, n3[3] = {g.nx, g.ny, g.nz};
-    R gradu[3][3], dPsi[3][3];
     zero33(gradu);
     zero33(dPsi);
 #pragma unroll
@@ -1429,10 +1426,10 @@ __global__ __launch_bounds__(kBlock) void k_hrr_grad_tf(HrrArgs h)
                 R v[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const R Hm = Rp[e * np + dp], H0 = Rp[(4 + e) * np + dp], Hp = Rp[(8 + e) * np + dp];
-                    v[e] = a.substep == 2 ? Hp
-                                          : (a.first ? R(0.5) * H0 + R(0.5) * Hp
-                                                     : R(-0.125) * Hm + R(0.75) * H0 + R(0.375) * Hp);
+                    const R vm = Hm[e * np + dp], v0 = H0[e * np + dp], vp = Hp[e * np + dp];
+                    v[e] = a.substep == 2 ? vp
+                                          : (a.first ? R(0.5) * v0 + R(0.5) * vp
+                                                     : R(-0.125) * vm + R(0.75) * v0 + R(0.375) * vp);
                 }
                 rn[sg] = (SH ? R(1) : R(0)) + v[0];
 #pragma unroll
@@ -1441,14 +1438,6 @@ __global__ __launch_bounds__(kBlock) void k_hrr_grad_tf(HrrArgs h)
         }
         hrr_axis<DIM, R>(c, R(0.25), rn, un, h.psi, gradu, dPsi);
     }
-    R* G = (R*)h.Gtf;
-#pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            G[(3 * p + q) * (int64_t)a.n_tf + t] = gradu[p][q];
-            G[(9 + 3 * p + q) * (int64_t)a.n_tf + t] = dPsi[p][q];
-        }
 }
 
 // Macroscopic state of a node from M.
@@ -1459,10 +1448,11 @@ __device__ __forceinline__ Mac<R> mac_at(const R* M, int64_t n, int64_t d, const
     return make_mac<DIM, SH, R>(rf, M[d], du);
 }
 
-// Workgroups of an H-RR collide launch: the bulk tiles (pulled again), then
-// on a refined level its co-located nodes, its hanging nodes, and, on a
-// level with a child, its coarse co-located nodes (these three read their
-// completed populations back from the destination).
+// Workgroups of an H-RR collide launch: on a refined level its co-located
+// nodes and its hanging nodes, on a level with a child its coarse co-located
+// nodes (these read their completed populations back from the destination;
+// they come first, so that their longer dependent chains of loads overlap
+// the bulk), then the bulk tiles (pulled again).
 template <int DIM, int EQ, int P>
 __global__ __launch_bounds__(kBlock) void k_hrr_collide(HrrArgs h)
 {
@@ -1481,7 +1471,11 @@ __global__ __launch_bounds__(kBlock) void k_hrr_collide(HrrArgs h)
     R s[Q], gradu[3][3], dPsi[3][3];
     zero33(gradu);
     zero33(dPsi);
-    if (b < h.nb_bulk) {
+    const int ntf = a.tf_meta ? a.n_tf : 0, nie = a.ie_meta ? a.n_ie : 0, ncap = a.cap_meta ? a.n_cap : 0;
+    const int gtf = (ntf + kBlock - 1) / kBlock, gie = (nie + kBlock - 1) / kBlock;
+    const int gif = gtf + gie + (ncap + kBlock - 1) / kBlock;
+    if (b >= gif) {
+        b -= gif;
         int64_t e0 = 0;
         int xyz[3];
         if (!bulk_load<DIM, P>(a, b, s, e0, xyz)) return;
@@ -1508,24 +1502,14 @@ __global__ __launch_bounds__(kBlock) void k_hrr_collide(HrrArgs h)
         for (int i = 0; i < Q; ++i) F::store(dst + i * BX, s[i]);
         return;
     }
-    b -= h.nb_bulk;
-    const int ntf = a.tf_meta ? a.n_tf : 0, nie = a.ie_meta ? a.n_ie : 0;
-    const int gtf = (ntf + kBlock - 1) / kBlock, gie = (nie + kBlock - 1) / kBlock;
-    const R* G = (const R*)h.Gtf;
     T* dst = (T*)a.dst;
     int4 m;
     if (b < gtf) {
-        // co-located nodes: gradients from k_hrr_grad_tf
+        // co-located nodes: the coarse stencil
         const int t = b * kBlock + threadIdx.x;
         if (t >= ntf) return;
         m = a.tf_meta[t];
-#pragma unroll
-        for (int p = 0; p < 3; ++p)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                gradu[p][q] = G[(3 * p + q) * (int64_t)ntf + t];
-                dPsi[p][q] = G[(9 + 3 * p + q) * (int64_t)ntf + t];
-            }
+        tf_gradients<DIM, SH, R>(h, t, rf, gradu, dPsi);
     } else if (b < gtf + gie) {
         // hanging nodes: the co-located nodes' gradients with the weights of
         // their populations' 4-point stencils (the first odd axis fastest)
@@ -1555,19 +1539,21 @@ __global__ __launch_bounds__(kBlock) void k_hrr_collide(HrrArgs h)
         for (int qq = 0; qq < ns; ++qq) {
             const int t = h.ie_tf[(int64_t)qq * nie + q0];
             const R wq = R(w0[qq & 3]) * R(w1[qq >> 2]);
+            R gu[3][3], gp[3][3];
+            tf_gradients<DIM, SH, R>(h, t, rf, gu, gp);
 #pragma unroll
             for (int p = 0; p < 3; ++p)
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    gradu[p][q] += wq * G[(3 * p + q) * (int64_t)ntf + t];
-                    dPsi[p][q] += wq * G[(9 + 3 * p + q) * (int64_t)ntf + t];
+                    gradu[p][q] += wq * gu[p][q];
+                    dPsi[p][q] += wq * gp[p][q];
                 }
         }
     } else {
         // coarse co-located nodes: the level's stencil, a neighbour in the
         // hole taken from the child node co-located with it
         const int t = (b - gtf - gie) * kBlock + threadIdx.x;
-        if (t >= a.n_cap) return;
+        if (t >= ncap) return;
         m = a.cap_meta[t];
         const R* Mc = (const R*)h.M_child;
         const int64_t nc = (int64_t)h.cn[0] * h.cn[1] * h.cn[2];
