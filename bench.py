@@ -19,6 +19,8 @@ Beside it, in the same run:
     storage;
   * the H-RR collision of Sec. 2 on the 2048^2 3-level mesh (with the
     interface gradients of Sec. 3.3), FP32 and FP64;
+  * the reflection and spurious-noise studies of Sec. 4.1.1 and 4.2.1, DC1
+    against DC2;
   * the serving loop (256 seeded requests);
   * the FP64 CPU oracle (single thread and all host cores) on bounded samples.
 
@@ -61,6 +63,7 @@ def parse():
     ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 D3Q19 workload")
     ap.add_argument("--no-4level", action="store_true", help="skip the 4-level 512^3 D3Q19 workload")
     ap.add_argument("--no-hrr", action="store_true", help="skip the H-RR collision on the 2048^2 3-level mesh")
+    ap.add_argument("--no-studies", action="store_true", help="skip the reflection and spurious-noise studies")
     ap.add_argument("--workload", default="pulse_vortices_3level",
                     choices=["pulse_vortices_3level", "pulse_ring_3d", "rings_4level"],
                     help="workload of `value`: 3-level 2048^2 D2Q9 (default), 2-level 256^3 D3Q19, or the "
@@ -473,6 +476,33 @@ def hrr_block(steps, warmup, bgk_mlups):
                        "updates_per_step": forms["fp32"]["updates_per_step"]}, "forms": out}
 
 
+def studies_block():
+    """The paper's two acoustic studies on the GPU path, DC1 against DC2
+    (FP64): the pulse reflected by plane interfaces (Sec. 4.1.1; largest and
+    RMS reflected velocity divergence relative to the uniform-fine
+    reference's peak, after 90 coarse steps) and the spurious noise of a
+    vortex convected across a plane interface (Sec. 4.2.1; OASPL over 36
+    probes, H-RR at the physical viscosity, 512^2 periodic domain, coarse
+    steps 200-650), with the same vortex on the unrefined mesh beside it."""
+    from paper_2004_14887_amd import studies
+
+    refl, noise = {}, {}
+    for cp in (1, 2):
+        t0 = time.perf_counter()
+        r = studies.reflection(steps=90, coupling=cp)
+        refl[f"DC{cp}"] = {"max": float(f"{r['max']:.4g}"), "l2": float(f"{r['l2']:.4g}")}
+        v = studies.vortex_oaspl(coupling=cp)
+        noise[f"DC{cp}"] = {"max_db": round(v["max"], 2), "mean_db": round(v["mean"], 2)}
+        log(f"studies DC{cp}: reflection {r['max']:.3e}, OASPL max {v['max']:.2f} dB "
+            f"({time.perf_counter() - t0:.1f} s)")
+    v = studies.vortex_oaspl(coupling=2, boxes=[])
+    noise["no_refinement"] = {"max_db": round(v["max"], 2), "mean_db": round(v["mean"], 2)}
+    noise["paper_table"] = {"note": "context only: 3 m domain with absorbing layers, window not stated",
+                            "STD": {"max_db": 80.7, "mean_db": 77.0}, "DC1": {"max_db": 68.9, "mean_db": 65.6},
+                            "DC2": {"max_db": 69.8, "mean_db": 66.5}}
+    return {"reflection_pulse_plane_150": refl, "oaspl_vortex_plane_512": noise}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -524,6 +554,9 @@ def main():
         torch.cuda.empty_cache()
         extra["hrr_pulse_vortices_3level_2048"] = hrr_block(min(args.steps, 100), min(args.warmup, 5),
                                                             {p: f["mlups"] for p, f in forms.items()})
+    if name == "pulse_vortices_3level" and not args.no_studies:
+        torch.cuda.empty_cache()
+        extra["studies"] = studies_block()
     cpu = None
     if not args.no_cpu_baseline and name != "rings_4level":
         log("cpu baseline (oracle)")

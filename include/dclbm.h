@@ -90,7 +90,7 @@ typedef struct {
     int32_t box_lo[DCLBM_MAX_LEVELS - 1][3];
     int32_t box_hi[DCLBM_MAX_LEVELS - 1][3];
     double tau0;              /* level-0 relaxation time (> 1/2); tau_{l+1} = 2 tau_l - 1/2, Eq.(rescTau) */
-    int32_t n_probes;         /* pressure probes, p' = (rho - 1)/3 after each coarse step */
+    int32_t n_probes;         /* pressure probes, 0..64, p' = (rho - 1)/3 after each coarse step */
     const int32_t* h_probe_xyz; /* [n_probes][3] level-0 node coordinates (host) */
     int64_t probe_capacity;   /* coarse steps of probe history kept on the device */
     int32_t newton_max_iter;  /* 0 -> 20 */
@@ -141,6 +141,17 @@ dclbm_status dclbm_read_populations(const dclbm_sim* sim, int32_t level, double*
 
 /* Density [n] and velocity [D][n] of a level from the post-collision populations, NaN on holes. */
 dclbm_status dclbm_read_macros(const dclbm_sim* sim, int32_t level, double* d_rho, double* d_u);
+
+/* Velocity divergence of a level (Sec. 4.1.1, 4.1.2: the field in which the
+ * reflection of an acoustic pulse at a refinement interface is shown):
+ * centred differences (u_a(x + e_a) - u_a(x - e_a)) / 2 summed over the D
+ * axes, in the level's lattice units.  d_u is the level's velocity [D][n]
+ * as dclbm_read_macros writes it (device memory, caller-owned); d_div [n]
+ * receives the divergence, NaN where a stencil point is a hole or lies
+ * beyond a refined level's extent (level 0 wraps periodically).  Enqueued
+ * on the simulation's stream; DCLBM_ERR_INVALID for a null pointer or a bad
+ * level. */
+dclbm_status dclbm_velocity_divergence(const dclbm_sim* sim, int32_t level, const double* d_u, double* d_div);
 
 /* Shared macroscopic state X = (rho, u) found by Newton at the co-located
  * nodes of a refined level (Sec. 3.2), [4][n] dense, NaN elsewhere. */

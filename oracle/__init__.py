@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
 benchmark's CPU-baseline leg.  The product library never imports it.
 """
 from .oracle import Oracle, build_oracle, build_baseline, lattice_table, feq, newton, residual, sets, \
-    line_stencil, time_interp, load_library
+    line_stencil, time_interp, load_library, oaspl, velocity_divergence
 
 __all__ = ["Oracle", "build_oracle", "build_baseline", "lattice_table", "feq", "newton", "residual", "sets",
-           "line_stencil", "time_interp", "load_library"]
+           "line_stencil", "time_interp", "load_library", "oaspl", "velocity_divergence"]

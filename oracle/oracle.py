@@ -306,3 +306,41 @@ class Oracle:
         if rc != 0:
             raise ValueError("not a co-located fine node")
         return _bits_to_set(kf.value), _bits_to_set(kc.value)
+
+
+def oaspl(series, start: int, stop: int, c0: float = 347.3, cs2: float = 1.0 / 3.0):
+    """Overall sound pressure level in dB re 2e-5 Pa of each column of a probe
+    series of p' = c_s^2 (rho - 1) (lattice units, rho0 = 1 kg/m^3), over rows
+    [start, stop): pressure in pascals c0^2 (rho - 1), its mean over the
+    window removed, root mean square, 20 log10(p_rms / 2e-5)."""
+    p = np.asarray(series, dtype=np.float64)[start:stop] * (c0 * c0 / cs2)
+    p = p - p.mean(axis=0)
+    return 20.0 * np.log10(np.sqrt((p * p).mean(axis=0)) / 2e-5)
+
+
+def velocity_divergence(lattice: str, f, dims, periodic: bool):
+    """Centred-difference velocity divergence of a level's populations
+    f [Q, n] (x fastest over dims = (nx, ny, nz)): u = sum_i xi_i f_i / sum_i f_i,
+    then sum over the D axes of (u_a(x + e_a) - u_a(x - e_a)) / 2.  Periodic
+    levels wrap; otherwise nodes whose stencil leaves the level are NaN, and
+    NaN populations (holes) propagate."""
+    xi, _ = lattice_table(lattice)
+    D = 2 if lattice == "D2Q9" else 3
+    f = np.asarray(f, dtype=np.float64)
+    rho = f.sum(axis=0)
+    shape = (dims[2], dims[1], dims[0])
+    div = np.zeros(shape)
+    for a in range(D):
+        u = ((xi[:, a].astype(np.float64) @ f) / rho).reshape(shape)
+        ax = 2 - a
+        if periodic:
+            div += 0.5 * (np.roll(u, -1, axis=ax) - np.roll(u, 1, axis=ax))
+        else:
+            d = np.full(shape, np.nan)
+            hi = [slice(None)] * 3
+            lo = [slice(None)] * 3
+            mid = [slice(None)] * 3
+            hi[ax], lo[ax], mid[ax] = slice(2, None), slice(None, -2), slice(1, -1)
+            d[tuple(mid)] = 0.5 * (u[tuple(hi)] - u[tuple(lo)])
+            div += d
+    return div.reshape(-1)

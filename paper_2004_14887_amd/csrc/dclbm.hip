@@ -345,7 +345,8 @@ dclbm_status build_geometry(Sim& s)
     if (c.eq_order != 2 && c.eq_order != 3) return fail(DCLBM_ERR_INVALID, "eq_order must be 2 or 3");
     if (c.n_levels < 1 || c.n_levels > DCLBM_MAX_LEVELS) return fail(DCLBM_ERR_INVALID, "n_levels out of range");
     if (!(c.tau0 > 0.5)) return fail(DCLBM_ERR_INVALID, "tau0 must exceed 1/2");
-    if (c.n_probes < 0 || c.n_probes > 32) return fail(DCLBM_ERR_INVALID, "n_probes must be in [0, 32]");
+    if (c.n_probes < 0 || c.n_probes > kMaxProbes)
+        return fail(DCLBM_ERR_INVALID, "n_probes must be in [0, %d]", kMaxProbes);
     if (c.n_probes > 0 && (!c.h_probe_xyz || c.probe_capacity < 1))
         return fail(DCLBM_ERR_INVALID, "probes need coordinates and a capacity");
     if (c.collision != DCLBM_BGK && c.collision != DCLBM_HRR) return fail(DCLBM_ERR_INVALID, "unknown collision model %d", c.collision);
@@ -1096,6 +1097,23 @@ dclbm_status dclbm_read_macros(const dclbm_sim* sim, int32_t level, double* d_rh
     if (st != DCLBM_OK) return st;
     Sim& s = const_cast<Sim&>(sim->s);
     s.eng->read(s, level, nullptr, d_rho, d_u);
+    HIPCHECK(hipGetLastError());
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_velocity_divergence(const dclbm_sim* sim, int32_t level, const double* d_u, double* d_div)
+{
+    dclbm_status st = check_level_impl(sim, level);
+    if (st != DCLBM_OK) return st;
+    if (!d_u || !d_div) return fail(DCLBM_ERR_INVALID, "null field pointer");
+    const Sim& s = sim->s;
+    const HostLevel& L = s.lv[level];
+    const int64_t n = L.n_dense();
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (s.D == 2)
+        hipLaunchKernelGGL((k_divergence<2>), grid, dim3(256), 0, s.stream, L.dev(), d_u, d_div);
+    else
+        hipLaunchKernelGGL((k_divergence<3>), grid, dim3(256), 0, s.stream, L.dev(), d_u, d_div);
     HIPCHECK(hipGetLastError());
     return DCLBM_OK;
 }

@@ -368,12 +368,17 @@ __device__ __forceinline__ int tile_row(const TileMap& tm, int c, int rr)
 // Bulk workgroups of a level with k tiles per workgroup (bulk_k).
 __host__ __device__ constexpr int bulk_groups(int per, int k) { return 8 * ((per + k - 1) / k); }
 
+// Probes of one simulation: at most one per lane of a wave (the probe
+// launch is one wave, the probe workgroup of a level launch samples with its
+// first kMaxProbes threads).
+constexpr int kMaxProbes = 64;
+
 struct ProbeArgs {
     int n;
     int64_t capacity;
-    const void* buf[32];   // storage buffer holding the probe's node
-    int64_t off[32];       // element offset of direction 0 of that node
-    int64_t stride[32];    // element distance between directions (the row-block width, or nz * ny in a face buffer)
+    const void* buf[kMaxProbes];   // storage buffer holding the probe's node
+    int64_t off[kMaxProbes];       // element offset of direction 0 of that node
+    int64_t stride[kMaxProbes];    // element distance between directions (the row-block width, or nz * ny in a face buffer)
 };
 
 struct LevelArgs {
@@ -1606,6 +1611,35 @@ __global__ __launch_bounds__(256) void k_hrr_ring_init(LevelDev g, void* Mring, 
     for (int slot = 0; slot < 3; ++slot)
 #pragma unroll
         for (int c = 0; c < 4; ++c) Rg[(4 * slot + c) * n + d] = v[c];
+}
+
+// Centred-difference velocity divergence of a level's dense FP64 velocity
+// [D][n] (NaN at holes, so a stencil touching a hole gives NaN); stencil
+// points beyond a refined level's extent give NaN, level 0 wraps.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_divergence(LevelDev g, const double* __restrict__ u, double* __restrict__ out)
+{
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= n) return;
+    const int k[3] = {(int)(d % g.nx), (int)((d / g.nx) % g.ny), (int)(d / ((int64_t)g.nx * g.ny))};
+    const int n3[3] = {g.nx, g.ny, g.nz};
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        int qm[3] = {k[0], k[1], k[2]}, qp[3] = {k[0], k[1], k[2]};
+        qm[c] -= 1;
+        qp[c] += 1;
+        if (g.periodic) {
+            qm[c] = qm[c] < 0 ? qm[c] + n3[c] : qm[c];
+            qp[c] = qp[c] >= n3[c] ? qp[c] - n3[c] : qp[c];
+        } else if (qm[c] < 0 || qp[c] >= n3[c]) {
+            s = __builtin_nan("");
+            continue;
+        }
+        s += 0.5 * (u[c * n + dense_index<DIM>(g, qp[0], qp[1], qp[2])] - u[c * n + dense_index<DIM>(g, qm[0], qm[1], qm[2])]);
+    }
+    out[d] = s;
 }
 
 // ---------------------------------------------------------------- history ring init

@@ -170,6 +170,21 @@ class Simulation:
         self.stream.synchronize()
         return rho, u
 
+    def divergence(self, l, u: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Centred-difference velocity divergence [n] of level l (NaN where a
+        stencil point is a hole or beyond the level), from u [D][n] as
+        macros() returns it (read here when not given)."""
+        if u is None:
+            u = self.macros(l)[1]
+        u = u.to(self.device, torch.float64).contiguous()
+        assert u.shape == (self.D, self.n_dense(l))
+        out = self._out((self.n_dense(l),))
+        self._sync_torch()
+        _lib.check(self.lib.dclbm_velocity_divergence(self.h, l, C.c_void_p(u.data_ptr()),
+                                                      C.c_void_p(out.data_ptr())))
+        self.stream.synchronize()
+        return out
+
     def shared(self, l) -> torch.Tensor:
         out = self._out((4, self.n_dense(l)))
         _lib.check(self.lib.dclbm_read_shared(self.h, l, C.c_void_p(out.data_ptr())))

@@ -1,0 +1,85 @@
+"""The paper's two studies of the interface's acoustic behaviour, run on the
+GPU path:
+
+* the reflection of an acoustic pulse at plane refinement interfaces
+  (Sec. 4.1.1): the velocity divergence of the refined run against a
+  uniform-fine reference run, on the fine region, after the pulse has crossed
+  the interfaces;
+* the spurious noise of a vortex convected across a plane interface
+  (Sec. 4.2.1): the overall sound pressure level (OASPL) at 36 far-field
+  probes.
+
+Both compare the couplings DC1 and DC2.  Every step of both runs is the
+library's (through Simulation); what is done here on the host is reading
+back the probe series or the divergence fields and reducing them.
+"""
+from __future__ import annotations
+
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+from . import workloads as W
+from .sim import Simulation
+
+
+def oaspl(series: np.ndarray, start: int, stop: int, c0: float = W.C0) -> np.ndarray:
+    """OASPL in dB re 2e-5 Pa of each probe (columns) of a series of
+    p' = c_s^2 (rho - 1) in lattice units over coarse steps [start, stop):
+    pascals are c0^2 rho0 (rho - 1) with rho0 = 1 kg/m^3; the window's mean
+    is removed before the root mean square."""
+    p = np.asarray(series, dtype=np.float64)[start:stop] * (c0 * c0 / W.CS2)
+    p = p - p.mean(axis=0)
+    prms = np.sqrt((p * p).mean(axis=0))
+    return 20.0 * np.log10(prms / 2e-5)
+
+
+def _run(wl: W.Workload, precision: str, device: str, steps: Optional[int] = None) -> Simulation:
+    sim = Simulation(wl, precision, device=device, probe_capacity=max(1, wl.steps))
+    sim.init_from_workload()
+    sim.step(wl.steps if steps is None else steps)
+    sim.check()
+    return sim
+
+
+def reflection(n0: int = 150, steps: int = 90, coupling: int = 2, collision: str = "bgk", tau0: float = 0.51,
+               precision: str = "fp64", device: str = "cuda:0") -> dict:
+    """Reflected field of the acoustic pulse at the plane interfaces of
+    workloads.pulse_plane after `steps` coarse steps: (div u - div u_ref) on
+    the refined level's nodes, divided by max |div u_ref| over the reference
+    domain.  Returns the field [ny, nx] (NaN on the level's boundary nodes,
+    where the centred difference is undefined), its largest magnitude
+    ("max") and its root mean square over the defined nodes ("l2")."""
+    wl = W.pulse_plane(n0=n0, coupling=coupling, tau0=tau0, steps=steps, collision=collision)
+    ref = W.uniform_fine_reference(wl)
+    a = _run(wl, precision, device)
+    d1 = a.divergence(1)
+    ny, nx = wl.dims(1)[1], wl.dims(1)[0]
+    a.close()
+    b = _run(ref, precision, device)
+    dr = b.divergence(0).reshape(ref.dims(0)[1], ref.dims(0)[0])
+    b.close()
+    lo = wl.boxes[0][0]
+    sub = dr[2 * lo[1]:2 * lo[1] + ny, 2 * lo[0]:2 * lo[0] + nx]
+    scale = dr.abs().max()
+    rel = ((d1.reshape(ny, nx) - sub) / scale).cpu().numpy()
+    m = ~np.isnan(rel)
+    return {"field": rel, "max": float(np.abs(rel[m]).max()), "l2": float(np.sqrt((rel[m] ** 2).mean())),
+            "div_ref_max": float(scale), "workload": wl.name, "steps": steps}
+
+
+def vortex_oaspl(n0: int = 512, steps: int = 650, coupling: int = 2, precision: str = "fp64",
+                 window: Tuple[int, int] = (200, 650), device: str = "cuda:0", boxes=None) -> dict:
+    """OASPL of the spurious noise of workloads.vortex_plane at its 36 probes
+    over the coarse-step window; `boxes=[]` runs the same flow without the
+    refinement (the level of noise the interface adds to)."""
+    wl = W.vortex_plane(n0=n0, coupling=coupling, steps=steps)
+    if boxes is not None:
+        wl.boxes = boxes
+    sim = _run(wl, precision, device)
+    series = sim.probes().cpu().numpy()
+    sim.close()
+    L = oaspl(series, *window)
+    return {"per_probe": L, "max": float(L.max()), "mean": float(L.mean()), "series": series,
+            "workload": wl.name, "window": list(window)}

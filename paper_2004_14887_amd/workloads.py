@@ -337,6 +337,85 @@ def vortex_2level(seed: int = 1, n0: int = 128, steps: int = 200, coupling: int 
                     probes=probes, background=(U0, 0.0, 0.0), vortices=vort, seed=seed)
 
 
+def pulse_plane(n0: int = 150, coupling: int = 2, tau0: float = 0.51, steps: int = 90,
+                lattice: str = "D2Q9", collision: str = "bgk") -> Workload:
+    """The acoustic pulse across plane refinement interfaces (Sec. 4.1.1) at
+    the paper's resolution: a 3 m periodic square of 150 coarse cells
+    (dx^c = 0.02 m), the Gaussian pulse of Eq.(init_Pulse) at its centre
+    (A = 1e-3, R_c = 0.1 m = 5 cells), and a refined band whose x faces lie
+    37 cells (0.74 m) either side of the centre.  The paper's band is periodic
+    in y; a nested box cannot touch the periodic boundary, so the band stops
+    3 cells short of it, and the y faces are first reached by the pulse's
+    front after about 100 coarse steps, after the 90 steps used here."""
+    c = n0 / 2.0
+    half = int(round(0.74 / 3.0 * n0))
+    lo = int(round(c)) - half
+    boxes = [((lo, 3), (lo + 2 * half, n0 - 3))]
+    return Workload(name=f"pulse_plane_{n0}_dc{coupling}", lattice=lattice, n0=(n0, n0), boxes=boxes, tau0=tau0,
+                    steps=steps, coupling=coupling, pulses=[dict(c=(c, c, 0.0), A=1e-3, Rc=0.1 / 3.0 * n0)],
+                    collision=collision)
+
+
+# Physical scales of the convected-vortex study (Sec. 4.2): speed of sound,
+# kinematic viscosity and the coarse spacing, which fix the lattice time step
+# dt = dx / (sqrt(3) c0) and tau0 - 1/2 = 3 nu dt / dx^2.
+C0 = 347.3
+NU = 1.49e-5
+DX_COARSE = 0.02
+
+
+def physical_tau0(dx: float = DX_COARSE) -> float:
+    dt = dx / (math.sqrt(3.0) * C0)
+    return 0.5 + 3.0 * NU * dt / dx ** 2
+
+
+def vortex_plane(n0: int = 512, coupling: int = 2, steps: int = 650, collision: str = "hrr",
+                 tau0: float = None) -> Workload:
+    """The barotropic vortex convected across a plane refinement interface
+    (Sec. 4.2.1, Eq.(init_COVO)) at the paper's resolution: dx^c = 0.02 m
+    (dx^f = 0.01 m), U_x = 0.1 c0, eps = 0.15 U_x, R_c = 0.06 m = 3 coarse
+    cells, the vortex starting 6 R_c upstream of the interface, inside the
+    fine region, with the physical viscosity (tau0 - 1/2 = 3.7e-6) and the
+    H-RR collision the paper uses for it.  36 probes on a circle of 1.2 m
+    (60 coarse cells) around the interface's centre, at the nearest coarse
+    nodes.  The paper bounds its 3 m domain with absorbing layers; here the
+    periodic domain is 512 cells (10.24 m) wide instead, so that neither the
+    start-up transient nor the interface's noise comes back to the probes
+    through the periodic boundary within the 650 steps (the nearest image
+    is more than 430 cells away).  The refined region is a box of 80 x 160
+    coarse cells whose right face is the interface; the vortex crosses only
+    that face."""
+    c = n0 // 2
+    U = 0.1 * CS
+    Rc = 0.06 / DX_COARSE
+    boxes = [((c - 80, c - 80), (c, c + 80))]
+    probes = []
+    for k in range(36):
+        th = 2.0 * math.pi * k / 36.0
+        probes.append((int(round(c + 60.0 * math.cos(th))), int(round(c + 60.0 * math.sin(th)))))
+    vort = [dict(xc=c - 6.0 * Rc, yc=float(c), eps=0.15 * U, Rc=Rc)]
+    return Workload(name=f"vortex_plane_{n0}_dc{coupling}", lattice="D2Q9", n0=(n0, n0), boxes=boxes,
+                    tau0=physical_tau0() if tau0 is None else tau0, steps=steps, coupling=coupling, eq_order=3,
+                    probes=probes, background=(U, 0.0, 0.0), vortices=vort, collision=collision)
+
+
+def uniform_fine_reference(wl: Workload) -> Workload:
+    """The reference of the reflection study (Sec. 4.1.1): the same domain and
+    fields on one periodic level at the resolution of wl's first refined
+    level (twice as many nodes per axis, tau from Eq.(rescTau)), run for
+    twice as many steps.  Its node i (per axis) sits at coarse coordinate
+    i / 2, so wl's level-1 node k matches reference node 2 lo + k."""
+    assert wl.n_levels >= 2
+    scale = lambda v: tuple(2.0 * x for x in v)
+    pulses = [dict(c=scale(p["c"]), A=p["A"], Rc=2.0 * p["Rc"]) for p in wl.pulses]
+    vort = [dict(xc=2.0 * v["xc"], yc=2.0 * v["yc"], eps=v["eps"], Rc=2.0 * v["Rc"]) for v in wl.vortices]
+    assert not wl.rings
+    return Workload(name=wl.name + "_reference", lattice=wl.lattice, n0=tuple(2 * n for n in wl.n0), boxes=[],
+                    tau0=2.0 * wl.tau0 - 0.5, steps=2 * wl.steps, coupling=wl.coupling, eq_order=wl.eq_order,
+                    background=wl.background, vortices=vort, pulses=pulses, collision=wl.collision,
+                    hrr_sigma=wl.hrr_sigma, hrr_psi=wl.hrr_psi)
+
+
 def pulse_vortices_3level(seed: int = 2, n0: int = 2048, steps: int = 1000, coupling: int = 2,
                           tau0: float = 0.55) -> Workload:
     """D2Q9, 3 levels: periodic n0^2, nested x2 patch over 25% and x4 patch over

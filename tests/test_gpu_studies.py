@@ -1,0 +1,132 @@
+"""GPU parity of the two acoustic studies (run with -m gpu).
+
+* dclbm_velocity_divergence against the oracle's divergence of its own
+  populations, on refined 2-D and 3-D meshes (FP64, 1e-13 absolute: the
+  fields peak near 1e-5 and a wrong stencil point is off by about that; NaN
+  exactly on holes and on refined levels' outer nodes);
+* the reflection study (Sec. 4.1.1) at the paper's resolution, DC1 and DC2:
+  the reflected field of the GPU runs against that of oracle runs, 1e-9 of
+  the reference's largest divergence (measured rates: 3.2e-3 DC1, 3.4e-3
+  DC2 after 90 coarse steps); before the pulse reaches the interfaces the
+  field is below 1e-10;
+* the convected vortex (Sec. 4.2.1) with H-RR at the physical viscosity: the
+  probe series on a 192^2 mesh against the oracle (FP64, 1e-13 absolute in
+  p'), and at full size (512^2, 650 steps) the OASPL of every probe against
+  the oracle's values stored in tests/golden/vortex_plane_oaspl.json
+  (FP64 0.01 dB; FP32 0.5 dB)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle as O  # noqa: E402
+from paper_2004_14887_amd import workloads as W  # noqa: E402
+
+requires_gpu = pytest.mark.skipif(not torch.cuda.is_available(), reason="no GPU")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "vortex_plane_oaspl.json")
+
+
+def oracle_run(wl, steps=None, probes=False):
+    o = O.Oracle(wl.lattice, wl.n0, wl.boxes, wl.tau0, wl.coupling, wl.eq_order, wl.probes if probes else [],
+                 max(1, wl.steps))
+    if wl.collision == "hrr":
+        o.set_collision("hrr", wl.hrr_sigma, wl.hrr_psi)
+    for l in range(wl.n_levels):
+        rho, u = W.initial_fields(wl, l)
+        o.init(l, rho, u)
+    o.run(wl.steps if steps is None else steps)
+    return o
+
+
+@requires_gpu
+@pytest.mark.parametrize("wl", [
+    W.Workload("div2", "D2Q9", (72, 40), [((10, 8), (50, 30)), ((12, 6), (60, 36))], 0.56, 4,
+               pulses=[dict(c=(30.0, 19.0, 0.0), A=1e-3, Rc=3.0)], background=(0.03, 0.01, 0.0)),
+    W.Workload("div3", "D3Q19", (32, 28, 24), [((8, 7, 6), (22, 20, 18))], 0.56, 3,
+               pulses=[dict(c=(15.0, 13.0, 12.0), A=1e-3, Rc=2.5)], background=(0.03, 0.01, -0.02)),
+], ids=["2d_3level", "3d_2level"])
+def test_divergence_matches_oracle(wl):
+    from paper_2004_14887_amd.sim import Simulation
+
+    print(f"[gpu] divergence {wl.name}", flush=True)
+    sim = Simulation(wl, "fp64", probe_capacity=wl.steps)
+    sim.init_from_workload()
+    sim.step(wl.steps)
+    o = oracle_run(wl)
+    for l in range(wl.n_levels):
+        g = sim.divergence(l).cpu().numpy()
+        r = O.velocity_divergence(wl.lattice, o.f(l), wl.dims(l), l == 0)
+        assert np.array_equal(np.isnan(g), np.isnan(r)), f"level {l}: NaN pattern differs"
+        m = ~np.isnan(r)
+        e = np.abs(g[m] - r[m]).max()
+        print(f"  level {l}: abs err {e:.2e} (field peak {np.abs(r[m]).max():.2e})", flush=True)
+        assert e < 1e-13
+
+
+def _oracle_reflection(wl):
+    ref = W.uniform_fine_reference(wl)
+    a = oracle_run(wl)
+    b = oracle_run(ref)
+    d1 = O.velocity_divergence(wl.lattice, a.f(1), wl.dims(1), False).reshape(wl.dims(1)[1], wl.dims(1)[0])
+    dr = O.velocity_divergence(ref.lattice, b.f(0), ref.dims(0), True).reshape(ref.dims(0)[1], ref.dims(0)[0])
+    lo = wl.boxes[0][0]
+    ny, nx = d1.shape
+    return (d1 - dr[2 * lo[1]:2 * lo[1] + ny, 2 * lo[0]:2 * lo[0] + nx]) / np.abs(dr).max()
+
+
+@requires_gpu
+@pytest.mark.parametrize("coupling", [1, 2])
+def test_reflection_study_matches_oracle(coupling):
+    from paper_2004_14887_amd import studies
+
+    print(f"[gpu] reflection study DC{coupling}", flush=True)
+    early = studies.reflection(steps=5, coupling=coupling)
+    assert early["max"] < 1e-10
+    res = studies.reflection(steps=90, coupling=coupling)
+    r = _oracle_reflection(W.pulse_plane(coupling=coupling, steps=90))
+    g = res["field"]
+    assert np.array_equal(np.isnan(g), np.isnan(r))
+    m = ~np.isnan(r)
+    e = np.abs(g[m] - r[m]).max()
+    print(f"  rate max {res['max']:.3e} l2 {res['l2']:.3e}; field error {e:.2e}", flush=True)
+    assert e < 1e-9
+    assert 1e-4 < res["max"] < 1e-1
+
+
+@requires_gpu
+def test_vortex_probe_series_matches_oracle():
+    from paper_2004_14887_amd.sim import Simulation
+
+    wl = W.vortex_plane(n0=192, coupling=2, steps=120)
+    print(f"[gpu] {wl.name} H-RR tau0 - 1/2 = {wl.tau0 - 0.5:.2e}, {wl.steps} steps", flush=True)
+    sim = Simulation(wl, "fp64", probe_capacity=wl.steps)
+    sim.init_from_workload()
+    sim.step(wl.steps)
+    sim.check()
+    g = sim.probes().cpu().numpy()
+    r = oracle_run(wl, probes=True).probes()
+    e = np.abs(g - r).max()
+    print(f"  probe error {e:.2e} (signal {np.abs(r).max():.2e})", flush=True)
+    assert g.shape == (120, 36)
+    assert e < 1e-13
+
+
+@requires_gpu
+@pytest.mark.parametrize("precision,tol", [("fp64", 0.01), ("fp32", 0.5)])
+def test_vortex_oaspl_full_size_against_oracle_values(precision, tol):
+    from paper_2004_14887_amd import studies
+
+    gold = json.load(open(GOLDEN))
+    for cp in (1, 2):
+        print(f"[gpu] vortex_plane 512^2 DC{cp} {precision}, 650 steps", flush=True)
+        res = studies.vortex_oaspl(coupling=cp, precision=precision, window=tuple(gold["window"]))
+        ref = np.array(gold["per_probe"][f"DC{cp}"])
+        e = np.abs(res["per_probe"] - ref).max()
+        print(f"  OASPL max {res['max']:.2f} mean {res['mean']:.2f} dB; largest probe difference {e:.3f} dB",
+              flush=True)
+        assert e < tol
