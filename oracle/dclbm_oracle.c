@@ -327,6 +327,9 @@ struct orc_sim {
     int collision;     /* 0: BGK; 1: H-RR */
     double hrr_sigma;  /* weight of the projected part of a_1^(2), Eq.(a12_HRR) */
     int hrr_psi;       /* cubic Mach correction psi_i of App. A on (1) or off (0) */
+    int sponge_w;      /* absorbing layer on level 0: width in cells (0 = none) */
+    double sponge_sigma;
+    double sponge_u[3];/* target velocity of the layer (target density 1) */
     long long newton_calls;
     int newton_max_iters;
     long long newton_iter_hist[8];
@@ -1137,6 +1140,72 @@ static void collide_level(orc_sim* s, int l, int substep)
     }
 }
 
+/* Absorbing layer (the paper only cites one, for its convected-vortex runs,
+ * Sec. 4.2.1; reading): on level 0, at nodes within W cells of the periodic
+ * seam, after the collision
+ *   f_i <- f_i - sigma(x) (f0_i(rho, u) - f0_i(1, u_t)),
+ * (rho, u) the node's moments, u_t the target velocity, with the strength
+ * sigma(x) = sigma_max ((W - e) / W)^2, e = min over the axes of the node's
+ * distance in cells to the nearest outermost node of the domain (0 there).
+ * The moments are driven towards (1, u_t) and the deviation from the target
+ * equilibrium shrinks by 1 - sigma each step; outside the layer nothing
+ * changes. */
+static double sponge_strength(const orc_sim* s, const int k[3])
+{
+    const level_t* v = &s->lv[0];
+    int e = v->n[0];
+    for (int a = 0; a < s->L.D; ++a) {
+        const int ea = k[a] < v->n[a] - 1 - k[a] ? k[a] : v->n[a] - 1 - k[a];
+        if (ea < e) e = ea;
+    }
+    if (e >= s->sponge_w) return 0.0;
+    const double r = (double)(s->sponge_w - e) / (double)s->sponge_w;
+    return s->sponge_sigma * r * r;
+}
+
+static void sponge_level0(orc_sim* s)
+{
+    const lattice_t* L = &s->L;
+    level_t* v = &s->lv[0];
+    double fet[MAXQ];
+    for (int i = 0; i < L->Q; ++i) fet[i] = feq_i(L, s->eq_order, i, 1.0, s->sponge_u);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < v->n[2]; ++z)
+        for (int y = 0; y < v->n[1]; ++y)
+            for (int x = 0; x < v->n[0]; ++x) {
+                const int k[3] = {x, y, z};
+                const long long q = nid(v, x, y, z);
+                if (v->cls[q] == C_HOLE) continue;
+                const double sig = sponge_strength(s, k);
+                if (sig == 0.0) continue;
+                double* f = v->f + q * L->Q;
+                double rho = 0.0, j[3] = {0, 0, 0}, u[3] = {0, 0, 0};
+                for (int i = 0; i < L->Q; ++i) {
+                    rho += f[i];
+                    for (int a = 0; a < L->D; ++a) j[a] += L->xi[i][a] * f[i];
+                }
+                for (int a = 0; a < L->D; ++a) u[a] = j[a] / rho;
+                for (int i = 0; i < L->Q; ++i) f[i] -= sig * (feq_i(L, s->eq_order, i, rho, u) - fet[i]);
+            }
+}
+
+int orc_set_sponge(orc_sim* s, int width, double sigma_max, const double* u_target)
+{
+    if (!s || width < 0 || !(sigma_max >= 0.0 && sigma_max <= 1.0)) return -1;
+    const level_t* v = &s->lv[0];
+    for (int a = 0; a < s->L.D; ++a)
+        if (2 * width >= v->n[a]) return -1;
+    if (s->nlev > 1) {
+        /* the child's closed box must lie outside the layer */
+        for (int a = 0; a < s->L.D; ++a)
+            if (v->clo[a] < width || v->chi[a] > v->n[a] - 1 - width) return -1;
+    }
+    s->sponge_w = width;
+    s->sponge_sigma = sigma_max;
+    for (int a = 0; a < 3; ++a) s->sponge_u[a] = (u_target && a < s->L.D) ? u_target[a] : 0.0;
+    return 0;
+}
+
 /* One step of level l; substep = 1 (asynchronous) or 2 (synchronous) with
  * respect to the parent, 0 on level 0.  Each level advances twice per step of
  * its parent (acoustic scaling, Sec. 3.1), recursively. */
@@ -1155,6 +1224,7 @@ static int advance(orc_sim* s, int l, int substep)
         restrict_tfc(s, l);                   /* 3f */
     }
     collide_level(s, l, substep);             /* 2h / 3g */
+    if (l == 0 && s->sponge_w > 0) sponge_level0(s);
     return 0;
 }
 

@@ -27,6 +27,10 @@ int orc_classes(const orc_sim* s, int l, unsigned char* out);
 void orc_set_newton(orc_sim* s, double tol, int maxit);
 void orc_plant_R(orc_sim* s, double R);
 int orc_set_collision(orc_sim* s, int kind, double sigma, int psi_on);
+/* Absorbing layer on level 0: width in cells, strength 0..1 at the domain's
+ * outermost nodes, target velocity [3] (target density 1).  The child's box
+ * must lie outside the layer.  0 on success, -1 on a bad argument. */
+int orc_set_sponge(orc_sim* s, int width, double sigma_max, const double* u_target);
 /* H-RR gradient tensors of level l from the current state, [N][2][3][3]:
  * d_b u_a, then sum_g d_g Psi_abg (test access) */
 int orc_hrr_gradients(orc_sim* s, int l, int substep, double* out);

@@ -66,6 +66,7 @@ def load_library(path: str = None):
             lib.orc_set_newton.argtypes = [P, C.c_double, C.c_int]
             lib.orc_plant_R.argtypes = [P, C.c_double]
             lib.orc_set_collision.argtypes = [P, C.c_int, C.c_double, C.c_int]
+            lib.orc_set_sponge.argtypes = [P, C.c_int, C.c_double, dp]
             lib.orc_hrr_gradients.argtypes = [P, C.c_int, C.c_int, dp]
             lib.orc_init.argtypes = [P, C.c_int, dp, dp]
             lib.orc_run.argtypes = [P, C.c_longlong]
@@ -235,6 +236,13 @@ class Oracle:
         refined meshes); call before init."""
         if self.lib.orc_set_collision(self.h, {"bgk": 0, "hrr": 1}[kind], float(sigma), int(bool(psi))) != 0:
             raise ValueError("oracle: invalid collision setting (0 <= sigma <= 1)")
+
+    def set_sponge(self, width: int, sigma_max: float, u_target=(0.0, 0.0, 0.0)):
+        """Absorbing layer on level 0 (width cells at the periodic seam)."""
+        u = np.zeros(3)
+        u[:len(u_target)] = u_target
+        if self.lib.orc_set_sponge(self.h, int(width), float(sigma_max), _dp(u)) != 0:
+            raise ValueError("oracle: invalid absorbing layer")
 
     def hrr_gradients(self, l, substep=2):
         """H-RR gradient tensors of level l from the current state:
