@@ -460,15 +460,15 @@ def hrr_block(steps, warmup, bgk_mlups):
     interface gradients of Sec. 3.3: FP32 and FP64, eager launches (four per
     refined level substep, two on level 0).  Minimum HBM traffic per node
     update: the populations read twice (the macroscopic pass and the
-    collision) and written once, and the four macroscopic values written
-    and read once: 3 Q + 8 values."""
+    collision) and written once, and the D + 1 macroscopic values written
+    and read once: 3 Q + 2 (D + 1) values."""
     wl = make_workload("pulse_vortices_3level", steps)
     wl.collision = "hrr"
     forms = {p: run_form(wl, p, steps, warmup, min(steps, 20), 0, True) for p in ("fp32", "fp64")}
     out = {}
     for p, f in forms.items():
         bpv = BYTES[p]
-        gbs = f["mlups"] * 1e6 * (3 * wl.Q + 8) * bpv / 1e9
+        gbs = f["mlups"] * 1e6 * (3 * wl.Q + 2 * (wl.D + 1)) * bpv / 1e9
         out[p] = {"mlups": round(f["mlups"], 1), "ms_per_step": round(f["wall_ms"] / f["steps"], 5),
                   "min_traffic_gbs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
                   "vs_bgk_same_form": round(f["mlups"] / bgk_mlups[p], 3) if bgk_mlups.get(p) else None}
@@ -482,8 +482,9 @@ def studies_block():
     RMS reflected velocity divergence relative to the uniform-fine
     reference's peak, after 90 coarse steps) and the spurious noise of a
     vortex convected across a plane interface (Sec. 4.2.1; OASPL over 36
-    probes, H-RR at the physical viscosity, 512^2 periodic domain, coarse
-    steps 200-650), with the same vortex on the unrefined mesh beside it."""
+    probes, H-RR at the physical viscosity, the paper's 3 m domain of 150^2
+    coarse cells with absorbing layers, coarse steps 200-650), with the same
+    vortex on the unrefined mesh beside it."""
     from paper_2004_14887_amd import studies
 
     refl, noise = {}, {}
@@ -497,10 +498,10 @@ def studies_block():
             f"({time.perf_counter() - t0:.1f} s)")
     v = studies.vortex_oaspl(coupling=2, boxes=[])
     noise["no_refinement"] = {"max_db": round(v["max"], 2), "mean_db": round(v["mean"], 2)}
-    noise["paper_table"] = {"note": "context only: 3 m domain with absorbing layers, window not stated",
+    noise["paper_table"] = {"note": "context only: its absorbing layers and probe window are not given",
                             "STD": {"max_db": 80.7, "mean_db": 77.0}, "DC1": {"max_db": 68.9, "mean_db": 65.6},
                             "DC2": {"max_db": 69.8, "mean_db": 66.5}}
-    return {"reflection_pulse_plane_150": refl, "oaspl_vortex_plane_512": noise}
+    return {"reflection_pulse_plane_150": refl, "oaspl_vortex_plane_150": noise}
 
 
 def main():

@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define DCLBM_ABI_VERSION 3
+#define DCLBM_ABI_VERSION 4
 #define DCLBM_MAX_LEVELS 4
 
 typedef enum {
@@ -100,6 +100,14 @@ typedef struct {
     int32_t collision;        /* dclbm_collision */
     double hrr_sigma;         /* HRR: weight of the projected part, 0..1 (0.98 in the paper's runs) */
     int32_t hrr_psi;          /* HRR: cubic Mach correction of App. A on (1) or off (0) */
+    /* Absorbing layer on level 0 (Sec. 4.2.1 uses one; its form is a reading):
+     * after each coarse step's collision, nodes within sponge_cells cells of
+     * the periodic seam take f_i - s(x) (f0_i(rho, u) - f0_i(1, u_ref)), with
+     * s(x) = sponge_sigma ((W - e) / W)^2, e the node's distance in cells to
+     * the domain's outermost nodes.  0 cells: none.  The level-1 box must lie
+     * outside the layer.  Steps with a layer are launched eagerly. */
+    int32_t sponge_cells;
+    double sponge_sigma;      /* 0..1 */
 } dclbm_config;
 
 typedef struct dclbm_sim dclbm_sim;

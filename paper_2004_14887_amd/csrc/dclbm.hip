@@ -354,6 +354,10 @@ dclbm_status build_geometry(Sim& s)
         if (!(c.hrr_sigma >= 0.0 && c.hrr_sigma <= 1.0)) return fail(DCLBM_ERR_INVALID, "hrr_sigma must be in [0, 1]");
     }
     s.hrr = c.collision == DCLBM_HRR ? 1 : 0;
+    if (c.sponge_cells < 0 || !(c.sponge_sigma >= 0.0 && c.sponge_sigma <= 1.0))
+        return fail(DCLBM_ERR_INVALID, "sponge_cells must be >= 0 and sponge_sigma in [0, 1]");
+    s.sponge_w = c.sponge_sigma > 0.0 ? c.sponge_cells : 0;
+    s.sponge_sigma = c.sponge_sigma;
     s.D = c.lattice == DCLBM_D2Q9 ? 2 : 3;
     s.Q = s.D == 2 ? 9 : 19;
     s.P = c.precision;
@@ -397,6 +401,7 @@ dclbm_status build_geometry(Sim& s)
             for (int a = 0; a < D; ++a) {
                 n[a] = c.n0[a];
                 if (n[a] < 8) return fail(DCLBM_ERR_INVALID, "level-0 extent must be at least 8");
+                if (2 * s.sponge_w >= n[a]) return fail(DCLBM_ERR_INVALID, "absorbing layer wider than half the domain");
                 if (n[a] > (1 << 20)) return fail(DCLBM_ERR_INVALID, "level-0 extent too large");
             }
             L.periodic = 1;
@@ -415,6 +420,10 @@ dclbm_status build_geometry(Sim& s)
             }
             Pn.has_child = 1;
             L.boundary = 1;
+            if (l == 1 && s.sponge_w > 0)
+                for (int a = 0; a < D; ++a)
+                    if (Pn.clo[a] < s.sponge_w || Pn.chi[a] > pn[a] - 1 - s.sponge_w)
+                        return fail(DCLBM_ERR_INVALID, "the level-1 box reaches into the absorbing layer");
         }
         L.nx = n[0];
         L.ny = n[1];
@@ -760,6 +769,7 @@ static dclbm_status launch_status(Sim& s, const char* what)
 static dclbm_status coarse_step_eager(Sim& s)
 {
     one_coarse_step(s);
+    if (s.sponge_w > 0) s.eng->sponge(s);
     HIPCHECK(hipGetLastError());
     return launch_status(s, "level substep launch");
 }
@@ -773,7 +783,7 @@ static bool all_first_steps_done(const Sim& s)
 
 static dclbm_status coarse_step(Sim& s)
 {
-    if (s.timing || s.stream == nullptr || !all_first_steps_done(s) || (s.hrr && s.lv.size() > 1))
+    if (s.timing || s.stream == nullptr || !all_first_steps_done(s) || (s.hrr && s.lv.size() > 1) || s.sponge_w > 0)
         return coarse_step_eager(s);
     const int par = s.lv[0].parity;
     if (!s.gexec[par]) {
@@ -873,6 +883,8 @@ static uint64_t config_fingerprint(const Sim& s)
         f.add(c.hrr_sigma);
         f.add(c.hrr_psi);
     }
+    f.add(s.sponge_w);
+    if (s.sponge_w > 0) f.add(c.sponge_sigma);
     f.add((uint64_t)s.need_bytes);
     f.add((uint64_t)s.probe_xyz.size());
     for (int32_t v : s.probe_xyz) f.add(v);
@@ -980,6 +992,8 @@ dclbm_status dclbm_create(const dclbm_config* cfg, void* d_workspace, size_t byt
         s.off_partial = tmp.off_partial;
         s.off_bal = tmp.off_bal;
         s.hrr = tmp.hrr;
+        s.sponge_w = tmp.sponge_w;
+        s.sponge_sigma = tmp.sponge_sigma;
     }
     dclbm_status st = sim_attach(s, d_workspace, bytes, (hipStream_t)stream);
     if (st != DCLBM_OK) return st;

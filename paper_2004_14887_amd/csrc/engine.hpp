@@ -123,6 +123,8 @@ struct Engine {
     virtual void hrr_close(Sim& s, int l, int substep, int first) = 0;
     // the three slots of level l's macroscopic-field ring from its initial fields
     virtual void hrr_ring_init(Sim& s, int l, const double* rho, const double* u) = 0;
+    // the absorbing layer on level 0's current state
+    virtual void sponge(Sim& s) = 0;
     virtual void probe(Sim& s) = 0;
     virtual void init(Sim& s, int l, const double* rho, const double* u) = 0;
     virtual void ring_init(Sim& s, int l) = 0;
@@ -167,6 +169,8 @@ struct Sim {
     double* d_bal = nullptr;
     int partial_blocks = 1024;
     int hrr = 0;                      // H-RR collision
+    int sponge_w = 0;                 // absorbing layer on level 0: width in cells (0: none)
+    double sponge_sigma = 0.0;
     int device = -1;                  // device current at creation
     double* d_scratch = nullptr;      // that device's static scratch array (dclbm_balance_static)
     std::unique_ptr<Engine> eng;

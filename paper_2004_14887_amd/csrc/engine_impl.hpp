@@ -222,6 +222,14 @@ struct EngineImpl final : Engine {
         const unsigned gtfc = (unsigned)((a.n_cap + kBlock - 1) / kBlock);
         hipLaunchKernelGGL((k_hrr_collide<DIM, EQ, P>), dim3(h.nb_bulk + gtf + gie + gtfc), dim3(kBlock), 0, s.stream, h);
     }
+    void sponge(Sim& s) override
+    {
+        const HostLevel& L = s.lv[0];
+        const int64_t n = L.n_dense();
+        hipLaunchKernelGGL((k_sponge<DIM, EQ, P>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s.stream, L.dev(),
+                           L.f[L.parity], L.parity, s.sponge_w, s.sponge_sigma, s.cfg.u_ref[0], s.cfg.u_ref[1],
+                           s.D == 3 ? s.cfg.u_ref[2] : 0.0);
+    }
     void hrr_ring_init(Sim& s, int l, const double* rho, const double* u) override
     {
         const HostLevel& L = s.lv[l];

@@ -493,15 +493,16 @@ __device__ __forceinline__ int64_t dense_index(const LevelDev& g, int x, int y, 
     return ((int64_t)z * g.ny + y) * g.nx + x;
 }
 
-// (drho, du) of node d into a [4][n] array
-template <typename R>
+// (drho, du) of node d into a [4][n] array (in 2-D the third velocity
+// component is neither written nor read)
+template <int DIM, typename R>
 __device__ __forceinline__ void put_mac(void* Mv, int64_t n, int64_t d, R drho, const R du[3])
 {
     R* M = (R*)Mv;
     M[d] = drho;
     M[n + d] = du[0];
     M[2 * n + d] = du[1];
-    M[3 * n + d] = du[2];
+    if (DIM == 3) M[3 * n + d] = du[2];
 }
 
 // HRR: the H-RR refined-mesh mode (no collision; see LevelArgs::M).
@@ -617,7 +618,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
                     F::store_wb(dp + eoff<DIM>(a.gp, i, pm.x, pm.y, pm.z), HRR ? c : e0 + keepp * (c - e0));
                 }
                 if constexpr (HRR)
-                    put_mac<R>(a.M_parent, (int64_t)a.gp.nx * a.gp.ny * a.gp.nz,
+                    put_mac<DIM, R>(a.M_parent, (int64_t)a.gp.nx * a.gp.ny * a.gp.nz,
                                dense_index<DIM>(a.gp, pm.x, pm.y, pm.z), mx.drho, mx.du);
             }
             const R keep = R(a.keep);
@@ -628,7 +629,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
                             HRR ? R(col[i * TFM]) : e0 + keep * (col[i * TFM] - e0));
             }
             if constexpr (HRR)
-                put_mac<R>(a.M, (int64_t)a.g.nx * a.g.ny * a.g.nz, dense_index<DIM>(a.g, m.x, m.y, m.z), mx.drho,
+                put_mac<DIM, R>(a.M, (int64_t)a.g.nx * a.g.ny * a.g.nz, dense_index<DIM>(a.g, m.x, m.y, m.z), mx.drho,
                            mx.du);
         }
     }
@@ -679,7 +680,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
         flag_unstable((SH ? R(1) : R(0)) + drho, a.flags);
         velocity<DIM, SH, R>(rf, drho, jj, du);
         if constexpr (HRR)
-            put_mac<R>(a.M, (int64_t)a.g.nx * a.g.ny * a.g.nz, dense_index<DIM>(a.g, m.x, m.y, m.z), drho, du);
+            put_mac<DIM, R>(a.M, (int64_t)a.g.nx * a.g.ny * a.g.nz, dense_index<DIM>(a.g, m.x, m.y, m.z), drho, du);
         else
             bgk<DIM, EQ, SH, R>(s, rf, make_mac<DIM, SH, R>(rf, drho, du), R(a.keep));
 #pragma unroll
@@ -1384,12 +1385,12 @@ __global__ __launch_bounds__(kBlock) void k_hrr_macros(HrrArgs h)
     flag_unstable((SH ? R(1) : R(0)) + drho, a.flags);
     velocity<DIM, SH, R>(rf, drho, j, du);
     const int64_t n = (int64_t)g.nx * g.ny * g.nz, d = dense_index<DIM>(g, x, y, z);
-    put_mac<R>(h.M, n, d, drho, du);
+    put_mac<DIM, R>(h.M, n, d, drho, du);
     // a bulk node within one node of the child's box (the box itself holds
     // no bulk nodes)
     if (h.Mring && x >= g.clo[0] - 1 && x <= g.chi[0] + 1 && y >= g.clo[1] - 1 && y <= g.chi[1] + 1 &&
         (DIM == 2 || (z >= g.clo[2] - 1 && z <= g.chi[2] + 1)))
-        put_mac<R>((R*)h.Mring + (int64_t)h.ring_new * 4 * n, n, d, drho, du);
+        put_mac<DIM, R>((R*)h.Mring + (int64_t)h.ring_new * 4 * n, n, d, drho, du);
 }
 
 // Gradients of co-located node t of a refined level on the coarse stencil:
@@ -1449,7 +1450,7 @@ __device__ __forceinline__ void tf_gradients(const HrrArgs& h, int t, const Ref<
 template <int DIM, bool SH, typename R>
 __device__ __forceinline__ Mac<R> mac_at(const R* M, int64_t n, int64_t d, const Ref<R>& rf)
 {
-    R du[3] = {M[n + d], M[2 * n + d], M[3 * n + d]};
+    R du[3] = {M[n + d], M[2 * n + d], DIM == 3 ? M[3 * n + d] : R(0)};
     return make_mac<DIM, SH, R>(rf, M[d], du);
 }
 
@@ -1611,6 +1612,52 @@ __global__ __launch_bounds__(256) void k_hrr_ring_init(LevelDev g, void* Mring, 
     for (int slot = 0; slot < 3; ++slot)
 #pragma unroll
         for (int c = 0; c < 4; ++c) Rg[(4 * slot + c) * n + d] = v[c];
+}
+
+// Absorbing layer on level 0 (one thread per node; nodes outside the layer
+// return at once): f_i <- f_i - s(x) (f0_i(rho, u) - f0_i(1, u_t)) on the
+// state of parity par, with s(x) = sigma ((W - e) / W)^2 and e the node's
+// distance in cells to the domain's outermost nodes.
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(256) void k_sponge(LevelDev g, void* f, int par, int W, double sigma, double tx, double ty,
+                                                double tz)
+{
+    using F = Form<P>;
+    using T = typename F::T;
+    using R = typename F::R;
+    constexpr int Q = Lat<DIM>::Q;
+    constexpr bool SH = F::shifted;
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= n) return;
+    const int k[3] = {(int)(d % g.nx), (int)((d / g.nx) % g.ny), (int)(d / ((int64_t)g.nx * g.ny))};
+    const int n3[3] = {g.nx, g.ny, g.nz};
+    int e = g.nx;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int ea = k[a] < n3[a] - 1 - k[a] ? k[a] : n3[a] - 1 - k[a];
+        e = ea < e ? ea : e;
+    }
+    if (e >= W) return;
+    const double r = (double)(W - e) / (double)W;
+    const R sg = R(sigma * r * r);
+    const Ref<R> rf = ref_of<R>(g);
+    T* base = (T*)f;
+    R s[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) s[i] = F::load(node_elem<DIM>(g, base, par, i, k[0], k[1], k[2]));
+    R drho, j[3], du[3];
+    moments<DIM, R>(s, drho, j);
+    velocity<DIM, SH, R>(rf, drho, j, du);
+    R f0[Q], ft[Q];
+    eq_all<DIM, EQ, SH, R>(g, rf, make_mac<DIM, SH, R>(rf, drho, du), f0);
+    // the target (1, u_t) in the carried variables
+    const R dut[3] = {R(tx) - (SH ? rf.ur[0] : R(0)), R(ty) - (SH ? rf.ur[1] : R(0)),
+                      DIM == 3 ? R(tz) - (SH ? rf.ur[2] : R(0)) : R(0)};
+    eq_all<DIM, EQ, SH, R>(g, rf, make_mac<DIM, SH, R>(rf, SH ? R(0) : R(1), dut), ft);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        F::store(node_elem<DIM>(g, base, par, i, k[0], k[1], k[2]), s[i] - sg * (f0[i] - ft[i]));
 }
 
 // Centred-difference velocity divergence of a level's dense FP64 velocity

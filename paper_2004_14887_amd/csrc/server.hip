@@ -630,6 +630,8 @@ dclbm_status dclbm_server_submit(dclbm_server* h, const dclbm_config* cfg, int64
     if (cfg->n_levels > c.max_levels) return fail(DCLBM_ERR_INVALID, "request has %d levels, server admits %d", cfg->n_levels, c.max_levels);
     if (cfg->n_probes > c.max_probes) return fail(DCLBM_ERR_INVALID, "request has %d probes, server keeps %d", cfg->n_probes, c.max_probes);
     if (cfg->collision != DCLBM_BGK) return fail(DCLBM_ERR_INVALID, "the serving launches run the BGK collision only");
+    if (cfg->sponge_cells > 0 && cfg->sponge_sigma > 0.0)
+        return fail(DCLBM_ERR_INVALID, "the serving launches have no absorbing layer");
     if (steps < 1 || steps > c.max_probe_steps) return fail(DCLBM_ERR_INVALID, "steps must be in [1, %lld]", (long long)c.max_probe_steps);
     std::unique_ptr<Request> r(new Request());
     r->steps = steps;

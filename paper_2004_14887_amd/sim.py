@@ -52,6 +52,8 @@ def make_config(wl: Workload, precision: str = "fp64", probe_capacity: Optional[
     cfg.collision = _lib.COLLISION[wl.collision]
     cfg.hrr_sigma = float(wl.hrr_sigma)
     cfg.hrr_psi = 1 if wl.hrr_psi else 0
+    cfg.sponge_cells = int(wl.sponge_cells)
+    cfg.sponge_sigma = float(wl.sponge_sigma)
     return cfg, probes
 
 

@@ -69,11 +69,12 @@ def reflection(n0: int = 150, steps: int = 90, coupling: int = 2, collision: str
             "div_ref_max": float(scale), "workload": wl.name, "steps": steps}
 
 
-def vortex_oaspl(n0: int = 512, steps: int = 650, coupling: int = 2, precision: str = "fp64",
+def vortex_oaspl(n0: int = 150, steps: int = 650, coupling: int = 2, precision: str = "fp64",
                  window: Tuple[int, int] = (200, 650), device: str = "cuda:0", boxes=None) -> dict:
-    """OASPL of the spurious noise of workloads.vortex_plane at its 36 probes
-    over the coarse-step window; `boxes=[]` runs the same flow without the
-    refinement (the level of noise the interface adds to)."""
+    """OASPL of the spurious noise of workloads.vortex_plane (absorbing
+    layers included) at its 36 probes over the coarse-step window;
+    `boxes=[]` runs the same flow without the refinement (the level of noise
+    the interface adds to)."""
     wl = W.vortex_plane(n0=n0, coupling=coupling, steps=steps)
     if boxes is not None:
         wl.boxes = boxes

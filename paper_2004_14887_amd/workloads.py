@@ -47,6 +47,8 @@ class Workload:
     collision: str = "bgk"            # "bgk" | "hrr" (Sec. 2; Sec. 3.3 and 3.5 on refined meshes)
     hrr_sigma: float = 0.98
     hrr_psi: bool = True
+    sponge_cells: int = 0             # absorbing layer on level 0 (width in cells; 0: none)
+    sponge_sigma: float = 0.0
 
     @property
     def D(self) -> int:
@@ -369,26 +371,26 @@ def physical_tau0(dx: float = DX_COARSE) -> float:
     return 0.5 + 3.0 * NU * dt / dx ** 2
 
 
-def vortex_plane(n0: int = 512, coupling: int = 2, steps: int = 650, collision: str = "hrr",
-                 tau0: float = None) -> Workload:
+def vortex_plane(n0: int = 150, coupling: int = 2, steps: int = 650, collision: str = "hrr",
+                 tau0: float = None, layer: int = 12, layer_sigma: float = 0.3) -> Workload:
     """The barotropic vortex convected across a plane refinement interface
-    (Sec. 4.2.1, Eq.(init_COVO)) at the paper's resolution: dx^c = 0.02 m
-    (dx^f = 0.01 m), U_x = 0.1 c0, eps = 0.15 U_x, R_c = 0.06 m = 3 coarse
-    cells, the vortex starting 6 R_c upstream of the interface, inside the
-    fine region, with the physical viscosity (tau0 - 1/2 = 3.7e-6) and the
-    H-RR collision the paper uses for it.  36 probes on a circle of 1.2 m
-    (60 coarse cells) around the interface's centre, at the nearest coarse
-    nodes.  The paper bounds its 3 m domain with absorbing layers; here the
-    periodic domain is 512 cells (10.24 m) wide instead, so that neither the
-    start-up transient nor the interface's noise comes back to the probes
-    through the periodic boundary within the 650 steps (the nearest image
-    is more than 430 cells away).  The refined region is a box of 80 x 160
-    coarse cells whose right face is the interface; the vortex crosses only
-    that face."""
+    (Sec. 4.2.1, Eq.(init_COVO)) at the paper's resolution and domain: a 3 m
+    square of 150 coarse cells (dx^c = 0.02 m, dx^f = 0.01 m), U_x = 0.1 c0,
+    eps = 0.15 U_x, R_c = 0.06 m = 3 coarse cells, the vortex starting 6 R_c
+    upstream of the interface, inside the fine region, with the physical
+    viscosity (tau0 - 1/2 = 3.7e-6) and the H-RR collision the paper uses for
+    it.  36 probes on a circle of 1.2 m (60 coarse cells) around the
+    interface's centre, at the nearest coarse nodes.  The paper bounds the
+    domain with absorbing layers; here a layer of `layer` cells (0.24 m) at
+    the periodic seam absorbs what would come back.  The refined region is
+    the box left of the interface, from the layer's inner edge (plus the
+    2-cell margin) to the interface, over the height between the layers; the
+    vortex crosses only its right face."""
     c = n0 // 2
     U = 0.1 * CS
     Rc = 0.06 / DX_COARSE
-    boxes = [((c - 80, c - 80), (c, c + 80))]
+    m = layer + 2
+    boxes = [((m, m), (c, n0 - m))]
     probes = []
     for k in range(36):
         th = 2.0 * math.pi * k / 36.0
@@ -396,7 +398,8 @@ def vortex_plane(n0: int = 512, coupling: int = 2, steps: int = 650, collision: 
     vort = [dict(xc=c - 6.0 * Rc, yc=float(c), eps=0.15 * U, Rc=Rc)]
     return Workload(name=f"vortex_plane_{n0}_dc{coupling}", lattice="D2Q9", n0=(n0, n0), boxes=boxes,
                     tau0=physical_tau0() if tau0 is None else tau0, steps=steps, coupling=coupling, eq_order=3,
-                    probes=probes, background=(U, 0.0, 0.0), vortices=vort, collision=collision)
+                    probes=probes, background=(U, 0.0, 0.0), vortices=vort, collision=collision,
+                    sponge_cells=layer, sponge_sigma=layer_sigma if layer else 0.0)
 
 
 def uniform_fine_reference(wl: Workload) -> Workload:

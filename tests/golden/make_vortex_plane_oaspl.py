@@ -1,8 +1,9 @@
 """Writes vortex_plane_oaspl.json: the FP64 oracle's OASPL of the convected
 vortex across a plane refinement interface (Sec. 4.2.1), DC1 and DC2, at
-the full size of workloads.vortex_plane (512^2 coarse, 650 coarse steps, H-RR
-at the physical viscosity), over the probe window [200, 650).  Calls only the
-oracle; takes a few minutes on 8 cores.
+the full size of workloads.vortex_plane (150^2 coarse cells with absorbing
+layers, 650 coarse steps, H-RR at the physical viscosity), over the probe
+window [200, 650).  Calls only the oracle (and the seeded input generators);
+takes about a minute on 8 cores.
 
     python tests/golden/make_vortex_plane_oaspl.py
 """
@@ -22,12 +23,14 @@ WINDOW = (200, 650)
 
 
 def main():
-    out = {"workload": "vortex_plane n0=512 steps=650 H-RR sigma=0.98 psi eq_order=3", "window": list(WINDOW),
+    out = {"workload": "vortex_plane n0=150 layer=12 sigma=0.3 steps=650 H-RR sigma=0.98 psi eq_order=3",
+           "window": list(WINDOW),
            "unit": "dB re 2e-5 Pa", "per_probe": {}, "max": {}, "mean": {}}
     for cp in (1, 2):
-        wl = W.vortex_plane(n0=512, coupling=cp, steps=WINDOW[1])
+        wl = W.vortex_plane(coupling=cp, steps=WINDOW[1])
         o = O.Oracle(wl.lattice, wl.n0, wl.boxes, wl.tau0, wl.coupling, wl.eq_order, wl.probes, wl.steps)
         o.set_collision("hrr", wl.hrr_sigma, wl.hrr_psi)
+        o.set_sponge(wl.sponge_cells, wl.sponge_sigma, wl.background)
         for l in range(wl.n_levels):
             rho, u = W.initial_fields(wl, l)
             o.init(l, rho, u)

@@ -9,11 +9,14 @@
   the reference's largest divergence (measured rates: 3.2e-3 DC1, 3.4e-3
   DC2 after 90 coarse steps); before the pulse reaches the interfaces the
   field is below 1e-10;
-* the convected vortex (Sec. 4.2.1) with H-RR at the physical viscosity: the
-  probe series on a 192^2 mesh against the oracle (FP64, 1e-13 absolute in
-  p'), and at full size (512^2, 650 steps) the OASPL of every probe against
-  the oracle's values stored in tests/golden/vortex_plane_oaspl.json
-  (FP64 0.01 dB; FP32 0.5 dB)."""
+* the convected vortex (Sec. 4.2.1) with H-RR at the physical viscosity and
+  absorbing layers: the probe series of its first 200 coarse steps against
+  the oracle (FP64, 1e-13 absolute in p'), and over all 650 steps the OASPL
+  of every probe against the oracle's values stored in
+  tests/golden/vortex_plane_oaspl.json (FP64 0.01 dB; FP32 0.5 dB);
+* the absorbing layer against the oracle's: every node of a pulse run (BGK,
+  one level and two levels, FP64 1e-12 relative, FP32 1e-7 absolute), a
+  uniform flow at the target exact in every form."""
 import json
 import os
 
@@ -36,6 +39,8 @@ def oracle_run(wl, steps=None, probes=False):
                  max(1, wl.steps))
     if wl.collision == "hrr":
         o.set_collision("hrr", wl.hrr_sigma, wl.hrr_psi)
+    if wl.sponge_cells:
+        o.set_sponge(wl.sponge_cells, wl.sponge_sigma, wl.background)
     for l in range(wl.n_levels):
         rho, u = W.initial_fields(wl, l)
         o.init(l, rho, u)
@@ -102,7 +107,7 @@ def test_reflection_study_matches_oracle(coupling):
 def test_vortex_probe_series_matches_oracle():
     from paper_2004_14887_amd.sim import Simulation
 
-    wl = W.vortex_plane(n0=192, coupling=2, steps=120)
+    wl = W.vortex_plane(coupling=2, steps=200)
     print(f"[gpu] {wl.name} H-RR tau0 - 1/2 = {wl.tau0 - 0.5:.2e}, {wl.steps} steps", flush=True)
     sim = Simulation(wl, "fp64", probe_capacity=wl.steps)
     sim.init_from_workload()
@@ -112,7 +117,7 @@ def test_vortex_probe_series_matches_oracle():
     r = oracle_run(wl, probes=True).probes()
     e = np.abs(g - r).max()
     print(f"  probe error {e:.2e} (signal {np.abs(r).max():.2e})", flush=True)
-    assert g.shape == (120, 36)
+    assert g.shape == (200, 36)
     assert e < 1e-13
 
 
@@ -123,10 +128,54 @@ def test_vortex_oaspl_full_size_against_oracle_values(precision, tol):
 
     gold = json.load(open(GOLDEN))
     for cp in (1, 2):
-        print(f"[gpu] vortex_plane 512^2 DC{cp} {precision}, 650 steps", flush=True)
+        print(f"[gpu] vortex_plane 150^2 DC{cp} {precision}, 650 steps", flush=True)
         res = studies.vortex_oaspl(coupling=cp, precision=precision, window=tuple(gold["window"]))
         ref = np.array(gold["per_probe"][f"DC{cp}"])
         e = np.abs(res["per_probe"] - ref).max()
         print(f"  OASPL max {res['max']:.2f} mean {res['mean']:.2f} dB; largest probe difference {e:.3f} dB",
               flush=True)
         assert e < tol
+
+
+def sponge_workload(boxes, steps=40):
+    return W.Workload("sponge", "D2Q9", (72, 64), boxes, 0.53, steps, background=(0.04, -0.01, 0.0),
+                      pulses=[dict(c=(36.0, 32.0, 0.0), A=1e-3, Rc=3.0)], sponge_cells=14, sponge_sigma=0.3)
+
+
+@requires_gpu
+@pytest.mark.parametrize("boxes", [[], [((24, 20), (48, 44))]], ids=["one_level", "two_levels"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-7)])
+def test_absorbing_layer_matches_oracle(boxes, precision, tol):
+    from paper_2004_14887_amd.sim import Simulation
+
+    wl = sponge_workload(boxes)
+    print(f"[gpu] absorbing layer {len(boxes) + 1} level(s) {precision}", flush=True)
+    sim = Simulation(wl, precision, probe_capacity=wl.steps)
+    sim.init_from_workload()
+    sim.step(wl.steps)
+    sim.check()
+    o = oracle_run(wl)
+    for l in range(wl.n_levels):
+        g, r = sim.populations(l).cpu().numpy(), o.f(l)
+        m = ~np.isnan(r)
+        d = np.abs(g[m] - r[m])
+        e = float(d.max() / np.abs(r[m]).max()) if precision == "fp64" else float(d.max())
+        print(f"  level {l}: err {e:.2e}", flush=True)
+        assert e < tol
+
+
+@requires_gpu
+def test_absorbing_layer_keeps_the_target_flow():
+    from paper_2004_14887_amd.sim import Simulation
+
+    for prec in ("fp64", "fp32", "fp16"):
+        wl = sponge_workload([((24, 20), (48, 44))], steps=6)
+        wl.pulses = []
+        sim = Simulation(wl, prec, probe_capacity=6)
+        sim.init_from_workload()
+        sim.step(6)
+        for l in range(2):
+            rho, u = sim.macros(l)
+            m = ~torch.isnan(rho)
+            assert (rho[m] - 1).abs().max().item() < 1e-14, prec
+            assert (u[0][m] - 0.04).abs().max().item() < 1e-14 and (u[1][m] + 0.01).abs().max().item() < 1e-14
