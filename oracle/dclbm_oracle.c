@@ -327,6 +327,7 @@ struct orc_sim {
     int collision;     /* 0: BGK; 1: H-RR */
     double hrr_sigma;  /* weight of the projected part of a_1^(2), Eq.(a12_HRR) */
     int hrr_psi;       /* cubic Mach correction psi_i of App. A on (1) or off (0) */
+    unsigned char* region; /* refined region of level 1 as a mask of level-0 cells over its box (NULL: the box) */
     int sponge_w;      /* absorbing layer on level 0: width in cells (0 = none) */
     double sponge_sigma;
     double sponge_u[3];/* target velocity of the layer (target density 1) */
@@ -376,6 +377,47 @@ static void classify_level(const lattice_t* L, level_t* v, int l)
             }
 }
 
+/* Co-located interface node at fine position (x, y) of level v? */
+static int is_tff(const level_t* v, int x, int y)
+{
+    return x >= 0 && y >= 0 && x < v->n[0] && y < v->n[1] && v->cls[nid(v, x, y, 0)] == C_TFF;
+}
+
+/* 4-point stencil of hanging node k on a refined region's boundary (2-D,
+ * one odd coordinate): along its odd axis, the centred points k-3..k+3 when
+ * all four are co-located interface nodes, else the one-sided points
+ * k-1..k+5 or k+1..k-5, else the linear pair k-1, k+1 (a boundary run of one
+ * parent cell between two steps).  The weights are those of R6; on a box
+ * boundary the rule gives the box line's stencils.  Returns the number of
+ * points used, -1 if none fits. */
+static int region_stencil(const level_t* v, const int k[3], int pos[4], double w[4])
+{
+    const int a = (k[0] & 1) ? 0 : 1;
+    int p[3] = {k[0], k[1], 0};
+#define TFF_AT(o) (p[a] = k[a] + (o), is_tff(v, p[0], p[1]))
+    if (TFF_AT(-3) && TFF_AT(-1) && TFF_AT(1) && TFF_AT(3)) {
+        const int o[4] = {-3, -1, 1, 3};
+        const double ww[4] = {-1.0 / 16, 9.0 / 16, 9.0 / 16, -1.0 / 16};
+        for (int j = 0; j < 4; ++j) pos[j] = k[a] + o[j], w[j] = ww[j];
+        return 4;
+    }
+    for (int sg = 1; sg >= -1; sg -= 2) {
+        if (TFF_AT(-sg) && TFF_AT(sg) && TFF_AT(3 * sg) && TFF_AT(5 * sg)) {
+            const int o[4] = {-sg, sg, 3 * sg, 5 * sg};
+            const double ww[4] = {5.0 / 16, 15.0 / 16, -5.0 / 16, 1.0 / 16};
+            for (int j = 0; j < 4; ++j) pos[j] = k[a] + o[j], w[j] = ww[j];
+            return 4;
+        }
+    }
+    if (TFF_AT(-1) && TFF_AT(1)) {
+        pos[0] = k[a] - 1, pos[1] = k[a] + 1, pos[2] = pos[3] = k[a] - 1;
+        w[0] = w[1] = 0.5, w[2] = w[3] = 0.0;
+        return 2;
+    }
+#undef TFF_AT
+    return -1;
+}
+
 /* Node k of level v, displaced by d; returns its id, or -1 if it is not an
  * active node of that level. */
 static long long active_at(const lattice_t* L, const level_t* v, const int k[3], const int d[3])
@@ -418,6 +460,7 @@ static void known_masks(const orc_sim* s, int l, const int k[3], unsigned* Kf, u
 static void free_sim(orc_sim* s)
 {
     if (!s) return;
+    free(s->region);
     for (int l = 0; l < MAXL; ++l) {
         level_t* v = &s->lv[l];
         free(v->cls);
@@ -547,6 +590,88 @@ orc_sim* orc_create(int lattice, int eq_order, int coupling, const int n0[3], in
 
 void orc_destroy(orc_sim* s) { free_sim(s); }
 
+/* A refined level-1 region made of level-0 cells (Sec. 3.4 closing paragraph
+ * and App. B: the interface is the boundary of the region, whatever its
+ * shape, and the node sets follow from which neighbours exist).  mask covers
+ * the cells of level 1's box, x fastest; 1 = refined.  Reading of the node
+ * classes: a level-0 node is a hole when all its incident cells are refined,
+ * a co-located (TF^c) node when some are; a level-1 node is active when any
+ * of its incident parent cells is refined and on the interface when not all
+ * are (cells outside the box count as not refined); interface nodes with all
+ * coordinates even are co-located (TF^f), the others hanging (IE).  Inactive
+ * level-1 nodes are holes of that level.  Only for two levels in 2-D with
+ * BGK, before any initialisation; 0 on success, -1 on a bad argument, -2 if a
+ * co-located node admits no valid couples or a hanging node has no
+ * co-located neighbours on its line. */
+static int region_refined(const orc_sim* s, int cx, int cy)
+{
+    const level_t* v0 = &s->lv[0];
+    const int nx = v0->chi[0] - v0->clo[0], ny = v0->chi[1] - v0->clo[1];
+    if (cx < 0 || cy < 0 || cx >= nx || cy >= ny) return 0;
+    return s->region[(long long)cy * nx + cx] != 0;
+}
+
+int orc_set_region(orc_sim* s, const unsigned char* mask)
+{
+    if (!s || !mask || s->nlev != 2 || s->L.D != 2 || s->collision != 0 || s->lv[0].captures != 0) return -1;
+    const lattice_t* L = &s->L;
+    level_t* v0 = &s->lv[0];
+    level_t* v1 = &s->lv[1];
+    const int nx = v0->chi[0] - v0->clo[0], ny = v0->chi[1] - v0->clo[1];
+    free(s->region);
+    s->region = (unsigned char*)malloc((size_t)nx * ny);
+    if (!s->region) return -1;
+    memcpy(s->region, mask, (size_t)nx * ny);
+    /* level 0: count the refined cells incident to each node of the closed box */
+    for (int y = 0; y < v0->n[1]; ++y)
+        for (int x = 0; x < v0->n[0]; ++x) {
+            int c = C_BULK;
+            if (x >= v0->clo[0] && x <= v0->chi[0] && y >= v0->clo[1] && y <= v0->chi[1]) {
+                int r = 0;
+                for (int dy = -1; dy <= 0; ++dy)
+                    for (int dx = -1; dx <= 0; ++dx) r += region_refined(s, x - v0->clo[0] + dx, y - v0->clo[1] + dy);
+                c = r == 4 ? C_HOLE : (r > 0 ? C_TFC : C_BULK);
+            }
+            v0->cls[nid(v0, x, y, 0)] = (unsigned char)c;
+        }
+    /* level 1: incident parent cells of fine node k: both neighbours of an
+     * even coordinate, the one cell of an odd coordinate */
+    for (int y = 0; y < v1->n[1]; ++y)
+        for (int x = 0; x < v1->n[0]; ++x) {
+            int tot = 0, r = 0;
+            for (int cy = (y - 1) >> 1; cy <= y >> 1; ++cy)
+                for (int cx = (x - 1) >> 1; cx <= x >> 1; ++cx) {
+                    ++tot;
+                    r += region_refined(s, cx, cy);
+                }
+            int c = C_HOLE;
+            if (r > 0) c = r < tot ? ((x % 2 == 0 && y % 2 == 0) ? C_TFF : C_IE) : C_BULK;
+            v1->cls[nid(v1, x, y, 0)] = (unsigned char)c;
+        }
+    /* the coarse co-located list and its history ring */
+    v0->n_tfc = 0;
+    for (long long q = 0; q < v0->N; ++q) v0->tfc_id[q] = v0->cls[q] == C_TFC ? v0->n_tfc++ : -1;
+    free(v0->H);
+    v0->H = (double*)malloc(sizeof(double) * (v0->n_tfc > 0 ? v0->n_tfc : 1) * 3 * L->Q);
+    if (!v0->H) return -1;
+    for (long long q = 0; q < v0->n_tfc * 3 * L->Q; ++q) v0->H[q] = NAN;
+    for (int y = 0; y < v1->n[1]; ++y)
+        for (int x = 0; x < v1->n[0]; ++x) {
+            const unsigned char c = v1->cls[nid(v1, x, y, 0)];
+            int k[3] = {x, y, 0};
+            if (c == C_TFF) {
+                unsigned Kf, Kc, P, Qf, Qc, Mf, Mc, gR;
+                known_masks(s, 1, k, &Kf, &Kc);
+                if (sets_from_known(L, Kf, Kc, s->coupling, &P, &Qf, &Qc, &Mf, &Mc, &gR) != 0) return -2;
+            } else if (c == C_IE) {
+                int pos[4];
+                double w[4];
+                if (region_stencil(v1, k, pos, w) < 0) return -2;
+            }
+        }
+    return 0;
+}
+
 int orc_level_dims(const orc_sim* s, int l, int dims[3])
 {
     if (l < 0 || l >= s->nlev) return -1;
@@ -582,6 +707,7 @@ void orc_plant_R(orc_sim* s, double R) { s->R_override = R; }
 int orc_set_collision(orc_sim* s, int kind, double sigma, int psi_on)
 {
     if (kind != 0 && kind != 1) return -1;
+    if (kind == 1 && s->region) return -1;   /* H-RR gradients need box interfaces */
     if (!(sigma >= 0.0 && sigma <= 1.0)) return -1;
     s->collision = kind;
     s->hrr_sigma = sigma;
@@ -803,7 +929,10 @@ static void interpolate_ie(orc_sim* s, int l)
                 for (int a = 0; a < 3; ++a) {
                     if (a < L->D && (k[a] % 2)) {
                         npts[a] = 4;
-                        line_stencil(k[a], v->n[a] - 1, pos[a], w[a]);
+                        if (s->region)
+                            region_stencil(v, k, pos[a], w[a]);
+                        else
+                            line_stencil(k[a], v->n[a] - 1, pos[a], w[a]);
                     } else {
                         npts[a] = 1;
                         pos[a][0] = k[a];

@@ -31,6 +31,11 @@ int orc_set_collision(orc_sim* s, int kind, double sigma, int psi_on);
  * outermost nodes, target velocity [3] (target density 1).  The child's box
  * must lie outside the layer.  0 on success, -1 on a bad argument. */
 int orc_set_sponge(orc_sim* s, int width, double sigma_max, const double* u_target);
+/* Refined region of level 1 as a mask of level-0 cells over its box (x
+ * fastest, 1 = refined); two levels, 2-D, BGK, before initialisation.
+ * 0 on success, -1 on a bad argument, -2 on a region the coupling cannot
+ * handle. */
+int orc_set_region(orc_sim* s, const unsigned char* mask);
 /* H-RR gradient tensors of level l from the current state, [N][2][3][3]:
  * d_b u_a, then sum_g d_g Psi_abg (test access) */
 int orc_hrr_gradients(orc_sim* s, int l, int substep, double* out);

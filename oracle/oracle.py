@@ -67,6 +67,7 @@ def load_library(path: str = None):
             lib.orc_plant_R.argtypes = [P, C.c_double]
             lib.orc_set_collision.argtypes = [P, C.c_int, C.c_double, C.c_int]
             lib.orc_set_sponge.argtypes = [P, C.c_int, C.c_double, dp]
+            lib.orc_set_region.argtypes = [P, C.POINTER(C.c_ubyte)]
             lib.orc_hrr_gradients.argtypes = [P, C.c_int, C.c_int, dp]
             lib.orc_init.argtypes = [P, C.c_int, dp, dp]
             lib.orc_run.argtypes = [P, C.c_longlong]
@@ -243,6 +244,14 @@ class Oracle:
         u[:len(u_target)] = u_target
         if self.lib.orc_set_sponge(self.h, int(width), float(sigma_max), _dp(u)) != 0:
             raise ValueError("oracle: invalid absorbing layer")
+
+    def set_region(self, mask):
+        """Refined region of level 1 as a [ny, nx] mask of level-0 cells over
+        its box (1 = refined)."""
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        r = self.lib.orc_set_region(self.h, m.ctypes.data_as(C.POINTER(C.c_ubyte)))
+        if r != 0:
+            raise ValueError("oracle: invalid refined region" + (" (interface sets)" if r == -2 else ""))
 
     def hrr_gradients(self, l, substep=2):
         """H-RR gradient tensors of level l from the current state:

@@ -20,7 +20,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -49,6 +49,7 @@ class Workload:
     hrr_psi: bool = True
     sponge_cells: int = 0             # absorbing layer on level 0 (width in cells; 0: none)
     sponge_sigma: float = 0.0
+    region: Optional[np.ndarray] = None   # level 1 as a [ny, nx] mask of level-0 cells over its box (None: the box)
 
     @property
     def D(self) -> int:
@@ -400,6 +401,31 @@ def vortex_plane(n0: int = 150, coupling: int = 2, steps: int = 650, collision: 
                     tau0=physical_tau0() if tau0 is None else tau0, steps=steps, coupling=coupling, eq_order=3,
                     probes=probes, background=(U, 0.0, 0.0), vortices=vort, collision=collision,
                     sponge_cells=layer, sponge_sigma=layer_sigma if layer else 0.0)
+
+
+def circle_region(box, centre, radius: float) -> np.ndarray:
+    """[ny, nx] mask of the level-0 cells of box = ((lo), (hi)) whose centres
+    lie within `radius` cells of `centre`: a stair-stepped circular refined
+    region (Sec. 4.1.2, Fig. PulseCir_mesh)."""
+    (lx, ly), (hx, hy) = box[0][:2], box[1][:2]
+    cy, cx = np.mgrid[0:hy - ly, 0:hx - lx]
+    px, py = lx + cx + 0.5, ly + cy + 0.5
+    return ((px - centre[0]) ** 2 + (py - centre[1]) ** 2 <= radius * radius).astype(np.uint8)
+
+
+def pulse_circle(n0: int = 150, coupling: int = 2, tau0: float = 0.51, steps: int = 90) -> Workload:
+    """The acoustic pulse across a circular refinement interface (Sec. 4.1.2)
+    at the paper's resolution: the domain and pulse of pulse_plane, the
+    refined region the level-0 cells within 1 m (50 cells) of the pulse's
+    centre, stair-stepped as in Fig. PulseCir_mesh."""
+    c = n0 / 2.0
+    R = 1.0 / 3.0 * n0
+    lo, hi = int(math.floor(c - R)) - 1, int(math.ceil(c + R)) + 1
+    box = ((lo, lo), (hi, hi))
+    wl = Workload(name=f"pulse_circle_{n0}_dc{coupling}", lattice="D2Q9", n0=(n0, n0), boxes=[box], tau0=tau0,
+                  steps=steps, coupling=coupling, pulses=[dict(c=(c, c, 0.0), A=1e-3, Rc=0.1 / 3.0 * n0)])
+    wl.region = circle_region(box, (c, c), R)
+    return wl
 
 
 def uniform_fine_reference(wl: Workload) -> Workload:

@@ -1,0 +1,131 @@
+"""Pins of the oracle's refined regions of any shape made of level-0 cells
+(Sec. 3.4 closing paragraph, App. B; the node classes and the hanging-node
+stencil rule are readings R30, R31).
+
+* A mask covering the whole box gives the box path bit for bit, and a mask
+  covering a rectangle inside a larger box gives the path of that smaller box
+  bit for bit (level 0 everywhere, level 1 on the shared nodes): the classes
+  derived from the mask and the stencil rule reduce to the box's.
+* A stair-stepped circle (Sec. 4.1.2) and an L-shaped region (a concave
+  corner) admit valid couples at every co-located node under DC1 and DC2,
+  keep a uniform flow, and, with a centred pulse in a centred circle, keep
+  the square's symmetry (transposition and mirror images) to rounding.
+* Every level-0 co-located node has its level-1 partner, and holes are
+  exactly the nodes whose four cells are refined."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2004_14887_amd import workloads as W
+
+N = 64
+BOX = ((12, 12), (52, 52))
+HOLE, BULK, TFC, TFF, IE = 0, 1, 2, 3, 4
+
+
+def run(wl, region=None, steps=10, coupling=2):
+    o = O.Oracle("D2Q9", wl.n0, wl.boxes, wl.tau0, coupling, wl.eq_order, [], 1)
+    if region is not None:
+        o.set_region(region)
+    for l in range(wl.n_levels):
+        rho, u = W.initial_fields(wl, l)
+        o.init(l, rho, u)
+    o.run(steps)
+    return o
+
+
+def pulse(boxes, c=(30.0, 33.0)):
+    return W.Workload("p", "D2Q9", (N, N), boxes, 0.55, 10, pulses=[dict(c=(c[0], c[1], 0.0), A=1e-3, Rc=3.0)],
+                      background=(0.03, 0.01, 0.0))
+
+
+def same(a, b):
+    return np.array_equal(np.nan_to_num(a, nan=7.0), np.nan_to_num(b, nan=7.0))
+
+
+@pytest.mark.parametrize("coupling", [1, 2])
+def test_full_mask_is_the_box(coupling):
+    a = run(pulse([BOX]), np.ones((40, 40), np.uint8), coupling=coupling)
+    b = run(pulse([BOX]), None, coupling=coupling)
+    for l in range(2):
+        assert same(a.f(l), b.f(l))
+
+
+@pytest.mark.parametrize("coupling", [1, 2])
+def test_rectangle_in_a_larger_box_is_the_smaller_box(coupling):
+    big, small = ((10, 11), (54, 53)), ((14, 16), (47, 49))
+    m = np.zeros((53 - 11, 54 - 10), np.uint8)
+    m[16 - 11:49 - 11, 14 - 10:47 - 10] = 1
+    a = run(pulse([big]), m, coupling=coupling)
+    b = run(pulse([small]), None, coupling=coupling)
+    assert same(a.f(0), b.f(0))
+    fa = a.f(1).reshape(9, 2 * (53 - 11) + 1, 2 * (54 - 10) + 1)
+    fb = b.f(1).reshape(9, 2 * (49 - 16) + 1, 2 * (47 - 14) + 1)
+    oy, ox = 2 * (16 - 11), 2 * (14 - 10)
+    sub = fa[:, oy:oy + fb.shape[1], ox:ox + fb.shape[2]]
+    assert same(sub, fb)
+    assert np.isnan(np.delete(fa, np.s_[ox:ox + fb.shape[2]], axis=2)).all()
+
+
+def circle():
+    return W.circle_region(BOX, (32.0, 32.0), 16.0)
+
+
+def l_shape():
+    m = np.ones((40, 40), np.uint8)
+    m[20:, 20:] = 0
+    return m
+
+
+@pytest.mark.parametrize("region", [circle, l_shape])
+@pytest.mark.parametrize("coupling", [1, 2])
+def test_uniform_flow_is_kept(region, coupling):
+    wl = W.Workload("u", "D2Q9", (N, N), [BOX], 0.55, 10, background=(0.04, -0.02, 0.0))
+    o = run(wl, region(), coupling=coupling)
+    fe = O.feq("D2Q9", 1.0, np.array([0.04, -0.02, 0.0]))
+    for l in range(2):
+        f = o.f(l)
+        m = ~np.isnan(f[0])
+        assert m.sum() > 1000
+        assert np.abs(f[:, m] - fe[:, None]).max() < 1e-14
+
+
+@pytest.mark.parametrize("coupling", [1, 2])
+def test_centred_pulse_in_a_circle_keeps_the_square_symmetry(coupling):
+    wl = pulse([BOX], c=(32.0, 32.0))
+    wl.background = (0.0, 0.0, 0.0)
+    o = run(wl, circle(), steps=40, coupling=coupling)
+    r0 = o.f(0).sum(0).reshape(N, N)
+    r1 = o.f(1).sum(0).reshape(81, 81)
+    assert np.nanmax(np.abs(r1 - 1)) > 1e-5
+    assert np.nanmax(np.abs(r0 - r0.T)) < 1e-13
+    assert np.nanmax(np.abs(r0 - np.roll(r0[:, ::-1], 1, axis=1))) < 1e-13
+    assert np.nanmax(np.abs(r1 - r1.T)) < 1e-13
+    assert np.nanmax(np.abs(r1 - r1[:, ::-1])) < 1e-13
+
+
+def test_classes_pair_up():
+    o = O.Oracle("D2Q9", (N, N), [BOX], 0.55, 2, 2, [], 1)
+    m = circle()
+    o.set_region(m)
+    c0 = o.classes(0).reshape(N, N)
+    c1 = o.classes(1).reshape(81, 81)
+    ys, xs = np.nonzero(c0 == TFC)
+    assert len(xs) > 50
+    assert (c1[2 * (ys - 12), 2 * (xs - 12)] == TFF).all()
+    assert (c1 == TFF).sum() == len(xs)
+    # holes: all four incident cells refined
+    pad = np.zeros((42, 42), np.uint8)
+    pad[1:41, 1:41] = m
+    four = pad[:-1, :-1] & pad[:-1, 1:] & pad[1:, :-1] & pad[1:, 1:]
+    assert np.array_equal(c0[12:53, 12:53] == HOLE, four.astype(bool))
+
+
+def test_region_validation():
+    o = O.Oracle("D2Q9", (N, N), [BOX], 0.55, 2, 2, [], 1)
+    o.set_region(circle())
+    with pytest.raises(ValueError):
+        o.set_collision("hrr")
+    o3 = O.Oracle("D2Q9", (N, N), [BOX, ((10, 10), (30, 30))], 0.55, 2, 2, [], 1)
+    with pytest.raises(ValueError):
+        o3.set_region(circle())
