@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define DCLBM_ABI_VERSION 4
+#define DCLBM_ABI_VERSION 5
 #define DCLBM_MAX_LEVELS 4
 
 typedef enum {
@@ -108,6 +108,19 @@ typedef struct {
      * outside the layer.  Steps with a layer are launched eagerly. */
     int32_t sponge_cells;
     double sponge_sigma;      /* 0..1 */
+    /* Refined region of level 1 made of level-0 cells (Sec. 3.4 closing
+     * paragraph, App. B: the interface may have any stair-stepped shape; the
+     * node sets follow from which neighbours exist).  NULL: the whole box.
+     * Otherwise a host mask over the cells of level 1's box, x fastest,
+     * (hi - lo) per axis, 1 = refined, read during dclbm_workspace_bytes and
+     * dclbm_create only.  A level-0 node is a hole when its four cells are
+     * refined and co-located when some are; a level-1 node exists when any of
+     * its parent cells is refined and is on the interface when not all are.
+     * Hanging nodes interpolate along their boundary run: centred 4-point,
+     * else one-sided 4-point, else linear on a one-cell run.  D2Q9, two
+     * levels and BGK only (DCLBM_ERR_INVALID otherwise, or when a co-located
+     * node admits no valid couples). */
+    const uint8_t* h_region;
 } dclbm_config;
 
 typedef struct dclbm_sim dclbm_sim;

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdclbm.so")
 
 MAX_LEVELS = 4
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 LATTICE = {"D2Q9": 0, "D3Q19": 1}
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2}
@@ -52,6 +52,7 @@ class Config(C.Structure):
         ("hrr_psi", C.c_int32),
         ("sponge_cells", C.c_int32),
         ("sponge_sigma", C.c_double),
+        ("h_region", C.POINTER(C.c_uint8)),
     ]
 
 

@@ -218,6 +218,37 @@ static void stencil_positions(int k, int N, int pos[4])
     }
 }
 
+// Points and weight type of hanging node k on a refined region's boundary
+// (2-D, one odd coordinate), along its odd axis, from the co-located nodes
+// present on that line: k-3, k-1, k+1, k+3 if all are (type 1), else k-1,
+// k+1, k+3, k+5 or k+1, k-1, k-3, k-5 (type 2), else k-1, k+1 (type 3, the
+// last two points repeat k-1 with zero weight).  On a box face this gives
+// the box line's stencils.  Returns the type, 0 if none fits.
+static int region_stencil(const HostLevel& L, const int k[3], int pos[4])
+{
+    const int a = (k[0] & 1) ? 0 : 1;
+    auto tf = [&](int o) {
+        int q[2] = {k[0], k[1]};
+        q[a] += o;
+        return q[0] >= 0 && q[1] >= 0 && q[0] < L.nx && q[1] < L.ny &&
+               L.cls[(size_t)q[1] * L.nx + q[0]] == kClsTf;
+    };
+    if (tf(-3) && tf(-1) && tf(1) && tf(3)) {
+        pos[0] = k[a] - 3; pos[1] = k[a] - 1; pos[2] = k[a] + 1; pos[3] = k[a] + 3;
+        return 1;
+    }
+    for (int sg = 1; sg >= -1; sg -= 2)
+        if (tf(-sg) && tf(sg) && tf(3 * sg) && tf(5 * sg)) {
+            pos[0] = k[a] - sg; pos[1] = k[a] + sg; pos[2] = k[a] + 3 * sg; pos[3] = k[a] + 5 * sg;
+            return 2;
+        }
+    if (tf(-1) && tf(1)) {
+        pos[0] = k[a] - 1; pos[1] = k[a] + 1; pos[2] = k[a] - 1; pos[3] = k[a] - 1;
+        return 3;
+    }
+    return 0;
+}
+
 // Segment of a boundary node: the face it is assigned to (the first axis on
 // which it sits on the box boundary, and the side) and its tile within that
 // face: 256 positions along the line in 2-D, 16 x 16 in 3-D.
@@ -247,17 +278,22 @@ static dclbm_status build_segments(Sim& s, int l)
     const int D = s.D;
     HostLevel& L = s.lv[l];
     const int n[3] = {L.nx, L.ny, L.nz};
+    const bool region = !L.cls.empty();
+    // a region's interface is grouped by 64 x 8 tiles of the level
+    auto key = [&](const int k[3]) {
+        return region ? std::make_tuple(7, k[1] / 8, k[0] / 64) : segment_key(D, k, n);
+    };
     struct Seg {
         std::vector<int> own, ie;
     };
     std::map<std::tuple<int, int, int>, Seg> segs;
     for (size_t t = 0; t < L.tf_meta.size(); ++t) {
         const int k[3] = {L.tf_meta[t].x, L.tf_meta[t].y, L.tf_meta[t].z};
-        segs[segment_key(D, k, n)].own.push_back((int)t);
+        segs[key(k)].own.push_back((int)t);
     }
     for (size_t e = 0; e < L.ie_meta.size(); ++e) {
         const int k[3] = {L.ie_meta[e].x, L.ie_meta[e].y, L.ie_meta[e].z};
-        segs[segment_key(D, k, n)].ie.push_back((int)e);
+        segs[key(k)].ie.push_back((int)e);
     }
     const size_t nie = L.ie_meta.size();
     L.seg_info.clear();
@@ -282,8 +318,15 @@ static dclbm_status build_segments(Sim& s, int l)
             for (int a = 0; a < 3; ++a) {
                 pos[a][0] = pos[a][1] = pos[a][2] = pos[a][3] = k[a];
                 if (a < D && (k[a] & 1)) {
-                    if (n[a] - 1 < 6) return fail(DCLBM_ERR_INVALID, "level %d box too small for the 4-point stencil", l);
-                    stencil_positions(k[a], n[a] - 1, pos[a]);
+                    if (region) {
+                        if (!region_stencil(L, k, pos[a]))
+                            return fail(DCLBM_ERR_INVALID, "level %d hanging node (%d,%d): no co-located nodes on its line",
+                                        l, k[0], k[1]);
+                    } else {
+                        if (n[a] - 1 < 6)
+                            return fail(DCLBM_ERR_INVALID, "level %d box too small for the 4-point stencil", l);
+                        stencil_positions(k[a], n[a] - 1, pos[a]);
+                    }
                     odd[no++] = a;
                 }
             }
@@ -431,6 +474,45 @@ dclbm_status build_geometry(Sim& s)
         L.tau = tau;
         tau = 2.0 * tau - 0.5;
     }
+    // a refined region of level-0 cells: node classes of level 0 and level 1
+    // (a level-0 node is a hole when its four cells are refined, co-located
+    // when some are; a level-1 node is active when any of its parent cells is
+    // refined, on the interface when not all are; cells outside the box are
+    // not refined)
+    if (c.h_region) {
+        if (D != 2 || c.n_levels != 2 || s.hrr)
+            return fail(DCLBM_ERR_INVALID, "refined regions need D2Q9, two levels and BGK");
+        HostLevel& L0 = s.lv[0];
+        HostLevel& L1 = s.lv[1];
+        const int cw = L0.chi[0] - L0.clo[0], ch = L0.chi[1] - L0.clo[1];
+        auto refined = [&](int cx, int cy) {
+            return cx >= 0 && cy >= 0 && cx < cw && cy < ch && c.h_region[(size_t)cy * cw + cx] != 0;
+        };
+        L0.cls.assign((size_t)L0.nx * L0.ny, kClsBulk);
+        for (int y = L0.clo[1]; y <= L0.chi[1]; ++y)
+            for (int x = L0.clo[0]; x <= L0.chi[0]; ++x) {
+                int r = 0;
+                for (int dy = -1; dy <= 0; ++dy)
+                    for (int dx = -1; dx <= 0; ++dx) r += refined(x - L0.clo[0] + dx, y - L0.clo[1] + dy) ? 1 : 0;
+                L0.cls[(size_t)y * L0.nx + x] = r == 4 ? kClsHole : (r > 0 ? kClsTfc : kClsBulk);
+            }
+        L1.cls.assign((size_t)L1.nx * L1.ny, kClsHole);
+        int64_t active = 0;
+        for (int y = 0; y < L1.ny; ++y)
+            for (int x = 0; x < L1.nx; ++x) {
+                int tot = 0, r = 0;
+                for (int cy = (y - 1) >> 1; cy <= (y >> 1); ++cy)
+                    for (int cx = (x - 1) >> 1; cx <= (x >> 1); ++cx) {
+                        ++tot;
+                        r += refined(cx, cy) ? 1 : 0;
+                    }
+                uint8_t k = kClsHole;
+                if (r > 0) k = r < tot ? ((x & 1) || (y & 1) ? kClsIe : kClsTf) : kClsBulk;
+                L1.cls[(size_t)y * L1.nx + x] = k;
+                active += k != kClsHole;
+            }
+        if (active == 0) return fail(DCLBM_ERR_INVALID, "the refined region is empty");
+    }
     // storage layout per level: row blocks of 2^xsh nodes, Q directions per block
     for (int l = 0; l < c.n_levels; ++l) {
         HostLevel& L = s.lv[l];
@@ -444,7 +526,9 @@ dclbm_status build_geometry(Sim& s)
         L.nxb = (stored + (1 << L.xsh) - 1) >> L.xsh;
         L.elems = ((int64_t)L.nz * L.ny * L.nxb * Q) << L.xsh;
         int64_t hole = 0;
-        if (L.has_child) {
+        if (!L.cls.empty()) {
+            for (uint8_t k : L.cls) hole += k == kClsHole;
+        } else if (L.has_child) {
             hole = 1;
             for (int a = 0; a < D; ++a) hole *= (L.chi[a] - L.clo[a] - 1);
         }
@@ -464,10 +548,15 @@ dclbm_status build_geometry(Sim& s)
             for (int y = 0; y < L.ny; ++y)
                 for (int x = 0; x < L.nx; ++x) {
                     const int k[3] = {x, y, z};
+                    const bool region = !L.cls.empty();
                     bool bnd = false, even = true;
                     for (int a = 0; a < D; ++a) {
                         if (k[a] == 0 || k[a] == n[a] - 1) bnd = true;
                         if (k[a] & 1) even = false;
+                    }
+                    if (region) {
+                        const uint8_t cl = L.cls[(size_t)y * L.nx + x];
+                        bnd = cl == kClsTf || cl == kClsIe;
                     }
                     if (!bnd) continue;
                     uint32_t Kf = 0, Kc = 0;
@@ -475,13 +564,22 @@ dclbm_status build_geometry(Sim& s)
                         int cv[3];
                         dirs(D, i, cv);
                         bool fin = true, hole = true;
+                        int sf3[3] = {0, 0, 0}, sc3[3] = {0, 0, 0};
                         for (int a = 0; a < D; ++a) {
                             const int sf = k[a] - cv[a];
+                            sf3[a] = sf;
                             if (sf < 0 || sf > n[a] - 1) fin = false;
                             if (even) {
                                 const int sc = L.plo[a] + k[a] / 2 - cv[a];
+                                sc3[a] = sc;
                                 if (!(sc > Pn.clo[a] && sc < Pn.chi[a])) hole = false;
                             }
+                        }
+                        if (region) {
+                            // present sources from the classes: a fine source exists when it is
+                            // an active node; a coarse one when it is not a hole
+                            if (fin) fin = L.cls[(size_t)sf3[1] * L.nx + sf3[0]] != kClsHole;
+                            if (even) hole = Pn.cls[(size_t)sc3[1] * Pn.nx + sc3[0]] == kClsHole;
                         }
                         if (fin) Kf |= 1u << i;
                         if (even && !hole) Kc |= 1u << i;
@@ -498,7 +596,15 @@ dclbm_status build_geometry(Sim& s)
                         for (int a = 0; a < D; ++a) p[a] = L.plo[a] + k[a] / 2;
                         Pn.tfc_meta.push_back(make_int4(p[0], p[1], p[2], (int)Kc));
                     } else {
-                        L.ie_meta.push_back(make_int4(x, y, z, (int)(all & ~Kf)));
+                        int wtype = 0;
+                        if (region) {
+                            int pos[4];
+                            wtype = region_stencil(L, k, pos);
+                            if (!wtype)
+                                return fail(DCLBM_ERR_INVALID, "level %d hanging node (%d,%d): no co-located nodes on its line",
+                                            l, x, y);
+                        }
+                        L.ie_meta.push_back(make_int4(x, y, z, (int)((all & ~Kf) | ((uint32_t)wtype << 24))));
                     }
                 }
         // Renumber co-located and hanging nodes in segment order, so that one
@@ -564,6 +670,9 @@ dclbm_status build_geometry(Sim& s)
                 if (d < 0 || (d >> sh) > n[a] - 1 || (d & ((1LL << sh) - 1))) inside = false;
                 else k[a] = (int)(d >> sh);
             }
+            // a refined region holds the point only where it has a node
+            if (inside && !s.lv[l].cls.empty() && s.lv[l].cls[((size_t)k[2] * n[1] + k[1]) * n[0] + k[0]] == kClsHole)
+                inside = false;
             if (inside) best = ProbeLoc{l, s.lv[l].elem0(Q, k[0], k[1], k[2]), k[0], k[1], k[2]};
         }
         s.probes.push_back(best);
@@ -612,6 +721,8 @@ dclbm_status build_geometry(Sim& s)
             if (L.has_child) L.off_Mring = take(3 * 4 * L.n_dense() * (int64_t)s.rsize);
             if (!L.ie_meta.empty()) L.off_ie_tf = take((int64_t)L.ie_tf.size() * 4);
         }
+    for (auto& L : s.lv)
+        if (!L.cls.empty()) L.off_cls = take((int64_t)L.cls.size());
     s.need_bytes = (size_t)off;
     return DCLBM_OK;
 }
@@ -672,6 +783,11 @@ dclbm_status sim_attach(Sim& s, void* d_workspace, size_t bytes, hipStream_t str
             L.d_Mring = L.has_child ? (void*)(s.ws + L.off_Mring) : nullptr;
             L.d_ie_tf = L.ie_meta.empty() ? nullptr : s.at<int>(L.off_ie_tf);
             if (L.d_ie_tf) HIPCHECK(upload(s, L.d_ie_tf, L.ie_tf));
+        }
+    for (auto& L : s.lv)
+        if (!L.cls.empty()) {
+            L.d_cls = (uint8_t*)(s.ws + L.off_cls);
+            HIPCHECK(upload(s, L.d_cls, L.cls));
         }
     s.d_partial = s.at<double>(s.off_partial);
     s.d_bal = s.at<double>(s.off_bal);
@@ -885,6 +1001,8 @@ static uint64_t config_fingerprint(const Sim& s)
     }
     f.add(s.sponge_w);
     if (s.sponge_w > 0) f.add(c.sponge_sigma);
+    for (const auto& L : s.lv)
+        for (uint8_t k : L.cls) f.add((int32_t)k);
     f.add((uint64_t)s.need_bytes);
     f.add((uint64_t)s.probe_xyz.size());
     for (int32_t v : s.probe_xyz) f.add(v);

@@ -51,6 +51,10 @@ struct HostLevel {
     int64_t off_f[2] = {0, 0}, off_xf[2] = {0, 0}, off_tf = 0, off_ie = 0, off_X = 0, off_tfc = 0, off_H = 0, off_seg_info = 0,
             off_seg_tf = 0, off_seg_ie = 0, off_seg_sten = 0;
     int64_t off_M = 0, off_Mring = 0, off_ie_tf = 0;   // H-RR
+    // refined region of level-0 cells (level 1 and its parent): node classes
+    std::vector<uint8_t> cls;
+    int64_t off_cls = 0;
+    uint8_t* d_cls = nullptr;
     // device pointers
     void* f[2] = {nullptr, nullptr};
     void* xf[2] = {nullptr, nullptr};
@@ -88,6 +92,7 @@ struct HostLevel {
         g.xface = xface;
         g.xf[0] = xf[0];
         g.xf[1] = xf[1];
+        g.cls = d_cls;
         return g;
     }
     int64_t n_dense() const { return (int64_t)nx * ny * nz; }

@@ -117,7 +117,14 @@ struct LevelDev {
     // that the interface tiles of those faces read and write whole lines
     int xface;
     void* xf[2];
+    // a level shaped by a refined region of level-0 cells (and its parent):
+    // one class byte per node, x fastest (kClsBulk, kClsHole for holes and for
+    // refined-level nodes outside the region, kClsTfc, kClsTf, kClsIe); null
+    // for box levels, whose classes follow from the box
+    const uint8_t* cls;
 };
+
+constexpr uint8_t kClsBulk = 0, kClsHole = 1, kClsTfc = 2, kClsTf = 3, kClsIe = 4;
 
 template <typename R>
 __device__ __forceinline__ Ref<R> ref_of(const LevelDev& g)
@@ -306,6 +313,7 @@ __device__ __forceinline__ const T* pull_elem(const LevelDev& g, const T* src, i
 template <int DIM>
 __device__ __forceinline__ bool is_interface_or_hole(const LevelDev& g, int x, int y, int z)
 {
+    if (g.cls) return g.cls[((int64_t)z * g.ny + y) * g.nx + x] != kClsBulk;
     if (g.boundary &&
         (x == 0 || x == g.nx - 1 || y == 0 || y == g.ny - 1 || (DIM == 3 && (z == 0 || z == g.nz - 1))))
         return true;
@@ -318,8 +326,24 @@ __device__ __forceinline__ bool is_interface_or_hole(const LevelDev& g, int x, i
 template <int DIM>
 __device__ __forceinline__ bool is_hole(const LevelDev& g, int x, int y, int z)
 {
+    if (g.cls) return g.cls[((int64_t)z * g.ny + y) * g.nx + x] == kClsHole;
     return g.has_child && x > g.clo[0] && x < g.chi[0] && y > g.clo[1] && y < g.chi[1] &&
            (DIM == 2 || (z > g.clo[2] && z < g.chi[2]));
+}
+
+// Weights of a hanging node's stencil on a refined region's boundary, by the
+// type the host stored in bits 24-26 of its metadata: 1 centred (-1, 9, 9,
+// -1)/16, 2 one-sided (5, 15, -5, 1)/16 (the host orders the points away
+// from the step), 3 linear (1/2, 1/2) on a run of one parent cell.
+__device__ __forceinline__ void typed_weights(int type, float w[4])
+{
+    if (type == 1) {
+        w[0] = -1.f / 16; w[1] = 9.f / 16; w[2] = 9.f / 16; w[3] = -1.f / 16;
+    } else if (type == 2) {
+        w[0] = 5.f / 16; w[1] = 15.f / 16; w[2] = -5.f / 16; w[3] = 1.f / 16;
+    } else {
+        w[0] = 0.5f; w[1] = 0.5f; w[2] = 0.f; w[3] = 0.f;
+    }
 }
 
 // 4-point stencil along one axis for odd position k on a line 0..N:
@@ -657,10 +681,14 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
             }
         }
         float w0[4], w1[4] = {1.f, 0.f, 0.f, 0.f};
-        line_weights(ka, Na, w0);
+        const int wtype = (m.w >> 24) & 7;
+        if (wtype)
+            typed_weights(wtype, w0);
+        else
+            line_weights(ka, Na, w0);
         if (no == 2) line_weights(kb, Nb, w1);
         const int ns = no == 2 ? 16 : 4;
-        const uint32_t miss = (uint32_t)m.w;
+        const uint32_t miss = (uint32_t)m.w & 0xffffffu;
         R s[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i)
@@ -1961,9 +1989,13 @@ __global__ __launch_bounds__(256) void k_balance(LevelDev g, const typename Form
         const int64_t yz = d / g.nx;
         const int y = (int)(yz % g.ny);
         const int z = (int)(yz / g.ny);
-        if (g.has_child && x >= g.clo[0] && x <= g.chi[0] && y >= g.clo[1] && y <= g.chi[1] &&
-            (DIM == 2 || (z >= g.clo[2] && z <= g.chi[2])))
+        if (g.cls) {
+            const uint8_t c = g.cls[d];
+            if (c == kClsHole || c == kClsTfc) continue;   // no node, or owned by the finer level
+        } else if (g.has_child && x >= g.clo[0] && x <= g.chi[0] && y >= g.clo[1] && y <= g.chi[1] &&
+                   (DIM == 2 || (z >= g.clo[2] && z <= g.chi[2]))) {
             continue;   // hole or owned by the finer level
+        }
         double r = 0.0, j[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < Q; ++i) {
             const double f =

@@ -13,6 +13,7 @@ from __future__ import annotations
 import ctypes as C
 from typing import Optional
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -54,7 +55,14 @@ def make_config(wl: Workload, precision: str = "fp64", probe_capacity: Optional[
     cfg.hrr_psi = 1 if wl.hrr_psi else 0
     cfg.sponge_cells = int(wl.sponge_cells)
     cfg.sponge_sigma = float(wl.sponge_sigma)
-    return cfg, probes
+    keep = [probes]
+    if wl.region is not None:
+        region = np.ascontiguousarray(np.asarray(wl.region, dtype=np.uint8))
+        lo, hi = wl.boxes[0]
+        assert region.shape == (hi[1] - lo[1], hi[0] - lo[0]), "region mask must cover level 1's box cells"
+        cfg.h_region = region.ctypes.data_as(C.POINTER(C.c_uint8))
+        keep.append(region)
+    return cfg, keep
 
 
 def workspace_bytes(wl: Workload, precision: str = "fp64", **kw) -> int:

@@ -44,14 +44,20 @@ def _run(wl: W.Workload, precision: str, device: str, steps: Optional[int] = Non
 
 
 def reflection(n0: int = 150, steps: int = 90, coupling: int = 2, collision: str = "bgk", tau0: float = 0.51,
-               precision: str = "fp64", device: str = "cuda:0") -> dict:
-    """Reflected field of the acoustic pulse at the plane interfaces of
-    workloads.pulse_plane after `steps` coarse steps: (div u - div u_ref) on
+               precision: str = "fp64", device: str = "cuda:0", shape: str = "plane") -> dict:
+    """Reflected field of the acoustic pulse at the refinement interface of
+    workloads.pulse_plane (shape "plane", Sec. 4.1.1) or pulse_circle
+    ("circle", Sec. 4.1.2) after `steps` coarse steps: (div u - div u_ref) on
     the refined level's nodes, divided by max |div u_ref| over the reference
-    domain.  Returns the field [ny, nx] (NaN on the level's boundary nodes,
-    where the centred difference is undefined), its largest magnitude
-    ("max") and its root mean square over the defined nodes ("l2")."""
-    wl = W.pulse_plane(n0=n0, coupling=coupling, tau0=tau0, steps=steps, collision=collision)
+    domain.  Returns the field [ny, nx] (NaN where the centred difference is
+    undefined: the level's outermost nodes, and nodes next to a region's
+    missing nodes), its largest magnitude ("max") and its root mean square
+    over the defined nodes ("l2")."""
+    if shape == "circle":
+        wl = W.pulse_circle(n0=n0, coupling=coupling, tau0=tau0, steps=steps)
+        wl.collision = collision
+    else:
+        wl = W.pulse_plane(n0=n0, coupling=coupling, tau0=tau0, steps=steps, collision=collision)
     ref = W.uniform_fine_reference(wl)
     a = _run(wl, precision, device)
     d1 = a.divergence(1)
