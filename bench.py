@@ -477,21 +477,24 @@ def hrr_block(steps, warmup, bgk_mlups):
 
 
 def studies_block():
-    """The paper's two acoustic studies on the GPU path, DC1 against DC2
-    (FP64): the pulse reflected by plane interfaces (Sec. 4.1.1; largest and
-    RMS reflected velocity divergence relative to the uniform-fine
-    reference's peak, after 90 coarse steps) and the spurious noise of a
+    """The paper's acoustic studies on the GPU path, DC1 against DC2 (FP64):
+    the pulse reflected by plane interfaces (Sec. 4.1.1) and by a
+    stair-stepped circular interface (Sec. 4.1.2; largest and RMS reflected
+    velocity divergence relative to the uniform-fine reference's peak, after
+    90 coarse steps) and the spurious noise of a
     vortex convected across a plane interface (Sec. 4.2.1; OASPL over 36
     probes, H-RR at the physical viscosity, the paper's 3 m domain of 150^2
     coarse cells with absorbing layers, coarse steps 200-650), with the same
     vortex on the unrefined mesh beside it."""
     from paper_2004_14887_amd import studies
 
-    refl, noise = {}, {}
+    refl, refl_c, noise = {}, {}, {}
     for cp in (1, 2):
         t0 = time.perf_counter()
         r = studies.reflection(steps=90, coupling=cp)
         refl[f"DC{cp}"] = {"max": float(f"{r['max']:.4g}"), "l2": float(f"{r['l2']:.4g}")}
+        r = studies.reflection(steps=90, coupling=cp, shape="circle")
+        refl_c[f"DC{cp}"] = {"max": float(f"{r['max']:.4g}"), "l2": float(f"{r['l2']:.4g}")}
         v = studies.vortex_oaspl(coupling=cp)
         noise[f"DC{cp}"] = {"max_db": round(v["max"], 2), "mean_db": round(v["mean"], 2)}
         log(f"studies DC{cp}: reflection {r['max']:.3e}, OASPL max {v['max']:.2f} dB "
@@ -501,7 +504,7 @@ def studies_block():
     noise["paper_table"] = {"note": "context only: its absorbing layers and probe window are not given",
                             "STD": {"max_db": 80.7, "mean_db": 77.0}, "DC1": {"max_db": 68.9, "mean_db": 65.6},
                             "DC2": {"max_db": 69.8, "mean_db": 66.5}}
-    return {"reflection_pulse_plane_150": refl, "oaspl_vortex_plane_150": noise}
+    return {"reflection_pulse_plane_150": refl, "reflection_pulse_circle_150": refl_c, "oaspl_vortex_plane_150": noise}
 
 
 def main():
