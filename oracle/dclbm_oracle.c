@@ -599,8 +599,8 @@ void orc_destroy(orc_sim* s) { free_sim(s); }
  * of its incident parent cells is refined and on the interface when not all
  * are (cells outside the box count as not refined); interface nodes with all
  * coordinates even are co-located (TF^f), the others hanging (IE).  Inactive
- * level-1 nodes are holes of that level.  Only for two levels in 2-D with
- * BGK, before any initialisation; 0 on success, -1 on a bad argument, -2 if a
+ * level-1 nodes are holes of that level.  Only for two levels in 2-D, before
+ * any initialisation; 0 on success, -1 on a bad argument, -2 if a
  * co-located node admits no valid couples or a hanging node has no
  * co-located neighbours on its line. */
 static int region_refined(const orc_sim* s, int cx, int cy)
@@ -613,7 +613,7 @@ static int region_refined(const orc_sim* s, int cx, int cy)
 
 int orc_set_region(orc_sim* s, const unsigned char* mask)
 {
-    if (!s || !mask || s->nlev != 2 || s->L.D != 2 || s->collision != 0 || s->lv[0].captures != 0) return -1;
+    if (!s || !mask || s->nlev != 2 || s->L.D != 2 || s->lv[0].captures != 0) return -1;
     const lattice_t* L = &s->L;
     level_t* v0 = &s->lv[0];
     level_t* v1 = &s->lv[1];
@@ -707,7 +707,6 @@ void orc_plant_R(orc_sim* s, double R) { s->R_override = R; }
 int orc_set_collision(orc_sim* s, int kind, double sigma, int psi_on)
 {
     if (kind != 0 && kind != 1) return -1;
-    if (kind == 1 && s->region) return -1;   /* H-RR gradients need box interfaces */
     if (!(sigma >= 0.0 && sigma <= 1.0)) return -1;
     s->collision = kind;
     s->hrr_sigma = sigma;
@@ -1115,7 +1114,11 @@ static void hrr_gradients(orc_sim* s, int l, int substep)
                         int d[3] = {0, 0, 0};
                         d[b] = sgn * h;
                         int kk[3] = {k[0] + d[0], k[1] + d[1], k[2] + d[2]};
-                        if (c == C_TFF && (kk[b] < 0 || kk[b] > v->n[b] - 1)) {
+                        /* a point of a fine co-located node's stencil outside the level,
+                         * or (refined regions) on a missing node of it, is a parent node:
+                         * its fine partner would exist if it were co-located or a hole,
+                         * so it is a bulk node of the parent */
+                        if (c == C_TFF && (kk[b] < 0 || kk[b] > v->n[b] - 1 || active_at(L, v, k, d) < 0)) {
                             int P[3] = {0, 0, 0};
                             for (int a = 0; a < L->D; ++a) P[a] = v->plo[a] + k[a] / 2;
                             P[b] += sgn;
@@ -1151,7 +1154,10 @@ static void hrr_gradients(orc_sim* s, int l, int substep)
                 for (int a = 0; a < 3; ++a) {
                     if (a < L->D && (k[a] % 2)) {
                         npts[a] = 4;
-                        line_stencil(k[a], v->n[a] - 1, pos[a], w[a]);
+                        if (s->region)
+                            region_stencil(v, k, pos[a], w[a]);
+                        else
+                            line_stencil(k[a], v->n[a] - 1, pos[a], w[a]);
                     } else {
                         npts[a] = 1;
                         pos[a][0] = k[a];

@@ -1,6 +1,6 @@
 """Pins of the oracle's refined regions of any shape made of level-0 cells
-(Sec. 3.4 closing paragraph, App. B; the node classes and the hanging-node
-stencil rule are readings R30, R31).
+(Sec. 3.4 closing paragraph, App. B; the node classes, the hanging-node
+stencil rule and the H-RR gradients on them are readings R30-R32).
 
 * A mask covering the whole box gives the box path bit for bit, and a mask
   covering a rectangle inside a larger box gives the path of that smaller box
@@ -122,10 +122,80 @@ def test_classes_pair_up():
 
 
 def test_region_validation():
-    o = O.Oracle("D2Q9", (N, N), [BOX], 0.55, 2, 2, [], 1)
-    o.set_region(circle())
-    with pytest.raises(ValueError):
-        o.set_collision("hrr")
     o3 = O.Oracle("D2Q9", (N, N), [BOX, ((10, 10), (30, 30))], 0.55, 2, 2, [], 1)
     with pytest.raises(ValueError):
         o3.set_region(circle())
+    o = O.Oracle("D2Q9", (N, N), [BOX], 0.55, 2, 2, [], 1)
+    o.set_region(circle())
+    o.set_collision("hrr", 0.98, True)
+
+
+# ---------------------------------------------------------------- H-RR on regions
+# The gradients of Sec. 3.3 on a stair-stepped interface (reading R32): a
+# point of a fine co-located node's coarse stencil that is not a node of the
+# fine level is a parent node, and that parent node is then a bulk node (its
+# fine partner would exist if it were co-located or a hole), so the parent's
+# ring of complete macroscopic fields serves it as on a box.
+
+def hrr_run(wl, region, steps, coupling=2):
+    o = O.Oracle("D2Q9", wl.n0, wl.boxes, wl.tau0, coupling, 3, [], 1)
+    if region is not None:
+        o.set_region(region)
+    o.set_collision("hrr", 0.98, True)
+    for l in range(wl.n_levels):
+        rho, u = W.initial_fields(wl, l)
+        o.init(l, rho, u)
+    o.run(steps)
+    return o
+
+
+@pytest.mark.parametrize("coupling", [1, 2])
+def test_hrr_full_mask_is_the_box(coupling):
+    a = hrr_run(pulse([BOX]), np.ones((40, 40), np.uint8), 6, coupling)
+    b = hrr_run(pulse([BOX]), None, 6, coupling)
+    for l in range(2):
+        assert same(a.f(l), b.f(l))
+
+
+@pytest.mark.parametrize("region", [circle, l_shape])
+def test_hrr_uniform_flow_and_symmetry(region):
+    wl = W.Workload("u", "D2Q9", (N, N), [BOX], 0.55, 6, background=(0.04, -0.02, 0.0))
+    o = hrr_run(wl, region(), 6)
+    fe = O.feq("D2Q9", 1.0, np.array([0.04, -0.02, 0.0]), 3)
+    for l in range(2):
+        assert np.nanmax(np.abs(o.f(l) - fe[:, None])) < 1e-14
+    if region is circle:
+        wl = pulse([BOX], c=(32.0, 32.0))
+        wl.background = (0.0, 0.0, 0.0)
+        o = hrr_run(wl, circle(), 30)
+        r0, r1 = o.f(0).sum(0).reshape(N, N), o.f(1).sum(0).reshape(81, 81)
+        assert np.nanmax(np.abs(r0 - r0.T)) < 1e-13
+        assert np.nanmax(np.abs(r1 - r1.T)) < 1e-13 and np.nanmax(np.abs(r1 - r1[:, ::-1])) < 1e-13
+
+
+@pytest.mark.parametrize("region", [circle, l_shape])
+@pytest.mark.parametrize("substep", [1, 2])
+def test_hrr_linear_field_gradients_on_a_region(region, substep):
+    """A linear velocity field's gradient is A / 2^l at every node class of a
+    stair-stepped interface: bulk, TF^c (hole neighbours from the child),
+    TF^f (coarse stencil, missing fine points from the parent) and IE
+    (interpolated with weights summing to one)."""
+    wl = W.Workload("lin", "D2Q9", (N, N), [BOX], 0.55, 1)
+    rng = np.random.default_rng(3)
+    A = 1e-3 * (2 * rng.random((2, 2)) - 1)
+    c = np.array([32.0, 32.0])
+    o = O.Oracle("D2Q9", wl.n0, wl.boxes, 0.55, 2, 3, [], 1)
+    o.set_region(region())
+    o.set_collision("hrr", 0.98, True)
+    for l in range(2):
+        pos = W.node_positions(wl, l)
+        o.init(l, np.ones(pos.shape[1]), A @ (pos[:2] - c[:, None]))
+    for l in range(2):
+        G = o.hrr_gradients(l, substep)[0][:2, :2]
+        cls = o.classes(l)
+        idx = np.indices((wl.dims(l)[1], wl.dims(l)[0])).reshape(2, -1)
+        m = (cls != HOLE) & (idx[0] >= 2) & (idx[0] <= wl.dims(l)[1] - 3) & (idx[1] >= 2) & \
+            (idx[1] <= wl.dims(l)[0] - 3) if l == 0 else (cls != HOLE)
+        assert {TFF, IE} <= set(np.unique(cls[m])) if l == 1 else TFC in set(np.unique(cls[m]))
+        err = np.abs(G[:, :, m] - (A / 2.0 ** l)[:, :, None]).max() / np.abs(A).max()
+        assert err < 1e-10, (l, err)
