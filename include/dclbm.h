@@ -117,9 +117,10 @@ typedef struct {
      * refined and co-located when some are; a level-1 node exists when any of
      * its parent cells is refined and is on the interface when not all are.
      * Hanging nodes interpolate along their boundary run: centred 4-point,
-     * else one-sided 4-point, else linear on a one-cell run.  D2Q9, two
-     * levels and BGK only (DCLBM_ERR_INVALID otherwise, or when a co-located
-     * node admits no valid couples). */
+     * else one-sided 4-point, else linear on a one-cell run.  With H-RR, a
+     * point of a co-located node's coarse stencil missing from the region is
+     * the parent node there.  D2Q9 and two levels only (DCLBM_ERR_INVALID
+     * otherwise, or when a co-located node admits no valid couples). */
     const uint8_t* h_region;
 } dclbm_config;
 

@@ -480,8 +480,7 @@ dclbm_status build_geometry(Sim& s)
     // refined, on the interface when not all are; cells outside the box are
     // not refined)
     if (c.h_region) {
-        if (D != 2 || c.n_levels != 2 || s.hrr)
-            return fail(DCLBM_ERR_INVALID, "refined regions need D2Q9, two levels and BGK");
+        if (D != 2 || c.n_levels != 2) return fail(DCLBM_ERR_INVALID, "refined regions need D2Q9 and two levels");
         HostLevel& L0 = s.lv[0];
         HostLevel& L1 = s.lv[1];
         const int cw = L0.chi[0] - L0.clo[0], ch = L0.chi[1] - L0.clo[1];

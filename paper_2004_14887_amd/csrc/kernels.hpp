@@ -1449,7 +1449,9 @@ __device__ __forceinline__ void tf_gradients(const HrrArgs& h, int t, const Ref<
         for (int sg = 0; sg < 2; ++sg) {
             int q3[3] = {k[0], k[1], k[2]};
             q3[c] += sg ? 2 : -2;
-            if (q3[c] >= 0 && q3[c] < n3[c]) {
+            // a point that is not a node of this level (beyond it, or missing
+            // from a refined region) is a bulk node of the parent
+            if (q3[c] >= 0 && q3[c] < n3[c] && !is_hole<DIM>(g, q3[0], q3[1], q3[2])) {
                 rho_u_at<DIM, SH, R>(M, n, dense_index<DIM>(g, q3[0], q3[1], q3[2]), rf, rn[sg], un[sg]);
             } else {
                 int P3[3] = {0, 0, 0};
@@ -1567,7 +1569,11 @@ __global__ __launch_bounds__(kBlock) void k_hrr_collide(HrrArgs h)
             }
         }
         float w0[4], w1[4] = {1.f, 0.f, 0.f, 0.f};
-        line_weights(ka, Na, w0);
+        const int wtype = (m.w >> 24) & 7;
+        if (wtype)
+            typed_weights(wtype, w0);
+        else
+            line_weights(ka, Na, w0);
         if (no == 2) line_weights(kb, Nb, w1);
         const int ns = no == 2 ? 16 : 4;
         for (int qq = 0; qq < ns; ++qq) {

@@ -1,13 +1,13 @@
-"""The paper's two studies of the interface's acoustic behaviour, run on the
-GPU path:
+"""The paper's studies of the interface's acoustic behaviour, run on the GPU
+path:
 
-* the reflection of an acoustic pulse at plane refinement interfaces
-  (Sec. 4.1.1): the velocity divergence of the refined run against a
-  uniform-fine reference run, on the fine region, after the pulse has crossed
-  the interfaces;
-* the spurious noise of a vortex convected across a plane interface
-  (Sec. 4.2.1): the overall sound pressure level (OASPL) at 36 far-field
-  probes.
+* the reflection of an acoustic pulse at plane (Sec. 4.1.1) and circular
+  (Sec. 4.1.2) refinement interfaces: the velocity divergence of the refined
+  run against a uniform-fine reference run, on the fine region, after the
+  pulse has crossed the interface;
+* the spurious noise of a vortex convected across a plane (Sec. 4.2.1) or a
+  30-degree-inclined (Sec. 4.2.2) interface: the overall sound pressure level
+  (OASPL) at 36 far-field probes.
 
 Both compare the couplings DC1 and DC2.  Every step of both runs is the
 library's (through Simulation); what is done here on the host is reading
@@ -76,14 +76,18 @@ def reflection(n0: int = 150, steps: int = 90, coupling: int = 2, collision: str
 
 
 def vortex_oaspl(n0: int = 150, steps: int = 650, coupling: int = 2, precision: str = "fp64",
-                 window: Tuple[int, int] = (200, 650), device: str = "cuda:0", boxes=None) -> dict:
-    """OASPL of the spurious noise of workloads.vortex_plane (absorbing
-    layers included) at its 36 probes over the coarse-step window;
-    `boxes=[]` runs the same flow without the refinement (the level of noise
-    the interface adds to)."""
-    wl = W.vortex_plane(n0=n0, coupling=coupling, steps=steps)
+                 window: Tuple[int, int] = (200, 650), device: str = "cuda:0", boxes=None,
+                 shape: str = "plane") -> dict:
+    """OASPL of the spurious noise of workloads.vortex_plane (shape "plane",
+    Sec. 4.2.1) or vortex_inclined ("inclined", Sec. 4.2.2), absorbing layers
+    included, at its 36 probes over the coarse-step window; `boxes=[]` runs
+    the same flow without the refinement (the level of noise the interface
+    adds to)."""
+    make = W.vortex_inclined if shape == "inclined" else W.vortex_plane
+    wl = make(n0=n0, coupling=coupling, steps=steps)
     if boxes is not None:
         wl.boxes = boxes
+        wl.region = None
     sim = _run(wl, precision, device)
     series = sim.probes().cpu().numpy()
     sim.close()

@@ -428,6 +428,29 @@ def pulse_circle(n0: int = 150, coupling: int = 2, tau0: float = 0.51, steps: in
     return wl
 
 
+def vortex_inclined(n0: int = 150, coupling: int = 2, steps: int = 650, collision: str = "hrr",
+                    tau0: float = None, layer: int = 12, layer_sigma: float = 0.3) -> Workload:
+    """The convected vortex of vortex_plane across a 30-degree-inclined
+    interface (Sec. 4.2.2, Fig. COVO_inclined_mesh): the refined region is the
+    stair-stepped set of level-0 cells left of the line through the domain's
+    centre leaning 30 degrees from the vertical (x = c + tan(30) (y - c)),
+    within the layers; the vortex crosses it at the centre.  Same flow,
+    collision, probes, layers and steps as the plane case."""
+    wl = vortex_plane(n0=n0, coupling=coupling, steps=steps, collision=collision, tau0=tau0, layer=layer,
+                      layer_sigma=layer_sigma)
+    c = n0 // 2
+    m = layer + 2
+    t = math.tan(math.radians(30.0))
+    hi_x = int(math.ceil(c + t * (n0 - m - c))) + 2
+    box = ((m, m), (min(hi_x, n0 - m), n0 - m))
+    wl.boxes = [box]
+    cy, cx = np.mgrid[0:box[1][1] - box[0][1], 0:box[1][0] - box[0][0]]
+    px, py = box[0][0] + cx + 0.5, box[0][1] + cy + 0.5
+    wl.region = (px < c + t * (py - c)).astype(np.uint8)
+    wl.name = f"vortex_inclined_{n0}_dc{coupling}"
+    return wl
+
+
 def uniform_fine_reference(wl: Workload) -> Workload:
     """The reference of the reflection study (Sec. 4.1.1): the same domain and
     fields on one periodic level at the resolution of wl's first refined

@@ -174,3 +174,28 @@ def test_circular_interface_reflection_matches_oracle(coupling):
     e = np.abs(g[m] - r[m]).max()
     print(f"  rate max {res['max']:.3e} l2 {res['l2']:.3e}; field error {e:.2e}", flush=True)
     assert e < 1e-9
+
+
+@requires_gpu
+@pytest.mark.parametrize("region", [circle, l_shape])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-7)])
+def test_region_hrr_random_fields(region, precision, tol):
+    """H-RR on a refined region (R32): every node against the oracle."""
+    wl = workload(region(), 2, steps=3)
+    wl.collision, wl.eq_order = "hrr", 3
+    from paper_2004_14887_amd.sim import Simulation
+
+    fields = random_fields(wl, 23)
+    print(f"[gpu] region H-RR {precision}", flush=True)
+    sim = Simulation(wl, precision, probe_capacity=3)
+    o = O.Oracle(wl.lattice, wl.n0, wl.boxes, wl.tau0, wl.coupling, wl.eq_order, [], 1)
+    o.set_region(wl.region)
+    o.set_collision("hrr", wl.hrr_sigma, wl.hrr_psi)
+    for l in range(2):
+        rho, u = fields[l]
+        sim.init(l, torch.from_numpy(rho), torch.from_numpy(u))
+        o.init(l, rho, u)
+    sim.step(3)
+    sim.check()
+    o.run(3)
+    assert errors(sim, o, wl, precision == "fp64") < tol

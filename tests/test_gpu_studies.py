@@ -9,10 +9,11 @@
   the reference's largest divergence (measured rates: 3.2e-3 DC1, 3.4e-3
   DC2 after 90 coarse steps); before the pulse reaches the interfaces the
   field is below 1e-10;
-* the convected vortex (Sec. 4.2.1) with H-RR at the physical viscosity and
-  absorbing layers: the probe series of its first 200 coarse steps against
-  the oracle (FP64, 1e-13 absolute in p'), and over all 650 steps the OASPL
-  of every probe against the oracle's values stored in
+* the convected vortex across a plane (Sec. 4.2.1) and a 30-degree-inclined
+  stair-stepped (Sec. 4.2.2) interface, with H-RR at the physical viscosity
+  and absorbing layers: the probe series of the first 200 coarse steps
+  against the oracle (FP64, 1e-13 absolute in p'), and over all 650 steps the
+  OASPL of every probe against the oracle's values stored in
   tests/golden/vortex_plane_oaspl.json (FP64 0.01 dB; FP32 0.5 dB);
 * the absorbing layer against the oracle's: every node of a pulse run (BGK,
   one level and two levels, FP64 1e-12 relative, FP32 1e-7 absolute), a
@@ -37,6 +38,8 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "vor
 def oracle_run(wl, steps=None, probes=False):
     o = O.Oracle(wl.lattice, wl.n0, wl.boxes, wl.tau0, wl.coupling, wl.eq_order, wl.probes if probes else [],
                  max(1, wl.steps))
+    if wl.region is not None:
+        o.set_region(wl.region)
     if wl.collision == "hrr":
         o.set_collision("hrr", wl.hrr_sigma, wl.hrr_psi)
     if wl.sponge_cells:
@@ -104,10 +107,11 @@ def test_reflection_study_matches_oracle(coupling):
 
 
 @requires_gpu
-def test_vortex_probe_series_matches_oracle():
+@pytest.mark.parametrize("make", [W.vortex_plane, W.vortex_inclined], ids=["plane", "inclined"])
+def test_vortex_probe_series_matches_oracle(make):
     from paper_2004_14887_amd.sim import Simulation
 
-    wl = W.vortex_plane(coupling=2, steps=200)
+    wl = make(coupling=2, steps=200)
     print(f"[gpu] {wl.name} H-RR tau0 - 1/2 = {wl.tau0 - 0.5:.2e}, {wl.steps} steps", flush=True)
     sim = Simulation(wl, "fp64", probe_capacity=wl.steps)
     sim.init_from_workload()
@@ -122,15 +126,16 @@ def test_vortex_probe_series_matches_oracle():
 
 
 @requires_gpu
+@pytest.mark.parametrize("shape", ["plane", "inclined"])
 @pytest.mark.parametrize("precision,tol", [("fp64", 0.01), ("fp32", 0.5)])
-def test_vortex_oaspl_full_size_against_oracle_values(precision, tol):
+def test_vortex_oaspl_full_size_against_oracle_values(shape, precision, tol):
     from paper_2004_14887_amd import studies
 
     gold = json.load(open(GOLDEN))
     for cp in (1, 2):
-        print(f"[gpu] vortex_plane 150^2 DC{cp} {precision}, 650 steps", flush=True)
-        res = studies.vortex_oaspl(coupling=cp, precision=precision, window=tuple(gold["window"]))
-        ref = np.array(gold["per_probe"][f"DC{cp}"])
+        print(f"[gpu] vortex {shape} 150^2 DC{cp} {precision}, 650 steps", flush=True)
+        res = studies.vortex_oaspl(coupling=cp, precision=precision, window=tuple(gold["window"]), shape=shape)
+        ref = np.array(gold["cases"][shape]["per_probe"][f"DC{cp}"])
         e = np.abs(res["per_probe"] - ref).max()
         print(f"  OASPL max {res['max']:.2f} mean {res['mean']:.2f} dB; largest probe difference {e:.3f} dB",
               flush=True)
