@@ -199,3 +199,32 @@ def test_hrr_linear_field_gradients_on_a_region(region, substep):
         assert {TFF, IE} <= set(np.unique(cls[m])) if l == 1 else TFC in set(np.unique(cls[m]))
         err = np.abs(G[:, :, m] - (A / 2.0 ** l)[:, :, None]).max() / np.abs(A).max()
         assert err < 1e-10, (l, err)
+
+
+def test_l_shape_inner_corner_is_the_convex_corner_of_appendix_b():
+    """App. B prints the sets of a convex corner (fine grid on three
+    quadrants, coarse grid on the upper-right one): an L-shaped region
+    missing its upper-right block has that corner, and the sets its
+    co-located node gets from the region's occupancy are the printed ones."""
+    rows = {}
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "index_sets.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                p = line.split()
+                rows.setdefault(p[0], {})[p[1]] = {int(v) for v in p[2:]}
+    m = np.ones((40, 40), np.uint8)
+    m[20:, 20:] = 0                       # the block above-right of cell corner (20, 20) is coarse
+    for coupling in (1, 2):
+        o = O.Oracle("D2Q9", (N, N), [BOX], 0.55, coupling, 2, [], 1)
+        o.set_region(m)
+        assert o.classes(1).reshape(81, 81)[40, 40] == TFF
+        Kf, Kc = o.node_masks(1, (40, 40))
+        rc, s = O.sets("D2Q9", Kf, Kc, coupling)
+        assert rc == 0
+        for key in ("P", "Qf", "Mf"):
+            assert s[key] == rows["convex"][key], (coupling, key)
+        # and the outer corners of the same region are the concave corner, rotated
+        Kf, Kc = o.node_masks(1, (80, 0))
+        rc, s = O.sets("D2Q9", Kf, Kc, coupling)
+        assert rc == 0 and len(s["Mf"]) == len(rows["concave"]["Mf"])
