@@ -632,6 +632,7 @@ dclbm_status dclbm_server_submit(dclbm_server* h, const dclbm_config* cfg, int64
     if (cfg->collision != DCLBM_BGK) return fail(DCLBM_ERR_INVALID, "the serving launches run the BGK collision only");
     if (cfg->sponge_cells > 0 && cfg->sponge_sigma > 0.0)
         return fail(DCLBM_ERR_INVALID, "the serving launches have no absorbing layer");
+    if (cfg->h_region) return fail(DCLBM_ERR_INVALID, "the serving launches take box-shaped refined levels only");
     if (steps < 1 || steps > c.max_probe_steps) return fail(DCLBM_ERR_INVALID, "steps must be in [1, %lld]", (long long)c.max_probe_steps);
     std::unique_ptr<Request> r(new Request());
     r->steps = steps;

@@ -139,3 +139,29 @@ def test_hrr_configuration_validation():
     wl.hrr_sigma = 1.5
     with pytest.raises(DclbmError):
         workspace_bytes(wl)
+
+
+def test_region_and_layer_validation():
+    """Refined regions: D2Q9, two levels, non-empty; absorbing layers: within
+    half the domain, strength in [0, 1], outside the level-1 box."""
+    _lib()
+    import numpy as np
+    from paper_2004_14887_amd._lib import DclbmError
+    from paper_2004_14887_amd.sim import workspace_bytes
+
+    wl = W.Workload("r", "D2Q9", (64, 64), [((12, 12), (52, 52))], 0.55, 1)
+    wl.region = W.circle_region(wl.boxes[0], (32.0, 32.0), 16.0)
+    assert workspace_bytes(wl, "fp32") > 0
+    empty = W.Workload("r", "D2Q9", (64, 64), [((12, 12), (52, 52))], 0.55, 1)
+    empty.region = np.zeros((40, 40), np.uint8)
+    three = W.Workload("r", "D2Q9", (64, 64), [((12, 12), (52, 52)), ((10, 10), (30, 30))], 0.55, 1)
+    three.region = wl.region
+    for bad in (empty, three):
+        with pytest.raises(DclbmError):
+            workspace_bytes(bad, "fp32")
+    lay = W.Workload("s", "D2Q9", (64, 64), [((16, 16), (48, 48))], 0.55, 1, sponge_cells=12, sponge_sigma=0.3)
+    assert workspace_bytes(lay, "fp32") > 0
+    for cells, sigma in ((17, 0.3), (33, 0.3), (12, 1.5)):
+        lay.sponge_cells, lay.sponge_sigma = cells, sigma
+        with pytest.raises(DclbmError):
+            workspace_bytes(lay, "fp32")
