@@ -82,10 +82,9 @@ struct EngineImpl final : Engine {
                 return;
             }
         }
-        // level 0 (no segments) of a 2-D FP16 mesh: the kernel without the
-        // segment role, 38 VGPRs and 8 waves/SIMD instead of 78 and 6
-        // (measured 11% faster on that launch; FP32 and FP64 gain nothing)
-        const bool top = DIM == 2 && P == 2 && a.nb_seg == 0;
+        const void* f = level_kernel(s, l, a);
+        LevelArgs arg = a;
+        void* params[1] = {&arg};
         if (s.timing) {
             // start/stop events travel in the dispatch packet of the kernel
             // itself; without the system-scope fence the stop stamp is not
@@ -93,16 +92,26 @@ struct EngineImpl final : Engine {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             s.note(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
             s.note(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
-            if (top)
-                hipExtLaunchKernelGGL((k_level_top<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, e0, e1, 0, a);
-            else
-                hipExtLaunchKernelGGL((k_level<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, e0, e1, 0, a);
+            s.note(hipExtLaunchKernel(f, dim3(grid), dim3(kBlock), params, 0, s.stream, e0, e1, 0));
             s.tev[l].push_back({e0, e1});
-        } else if (top) {
-            hipLaunchKernelGGL((k_level_top<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, a);
         } else {
-            hipLaunchKernelGGL((k_level<DIM, EQ, P>), dim3(grid), dim3(kBlock), 0, s.stream, a);
+            s.note(hipLaunchKernel(f, dim3(grid), dim3(kBlock), params, 0, s.stream));
         }
+    }
+    // The level-substep kernel of level l: without the segment role on
+    // level 0 of a 2-D FP16 mesh (38 VGPRs and 8 waves/SIMD instead of 78
+    // and 6, measured 11% faster on that launch; FP32 and FP64 gain
+    // nothing), and reading node classes on the levels of a refined region.
+    static const void* level_kernel(const Sim& s, int l, const LevelArgs& a)
+    {
+        const bool top = DIM == 2 && P == 2 && a.nb_seg == 0;
+        if constexpr (DIM == 2) {
+            if (s.lv[l].d_cls)
+                return top ? reinterpret_cast<const void*>(&k_level_top<DIM, EQ, P, true>)
+                           : reinterpret_cast<const void*>(&k_level<DIM, EQ, P, true>);
+        }
+        return top ? reinterpret_cast<const void*>(&k_level_top<DIM, EQ, P>)
+                   : reinterpret_cast<const void*>(&k_level<DIM, EQ, P>);
     }
     // The same launches as level_step, as graph nodes with explicit
     // dependencies (no stream capture, so no events or side stream take part
@@ -155,10 +164,7 @@ struct EngineImpl final : Engine {
                 return hipSuccess;
             }
         }
-        const bool top = DIM == 2 && P == 2 && a.nb_seg == 0;
-        const void* f = top ? reinterpret_cast<const void*>(&k_level_top<DIM, EQ, P>)
-                            : reinterpret_cast<const void*>(&k_level<DIM, EQ, P>);
-        e = kernel_node(g, f, r.grid, &a, deps, &n0);
+        e = kernel_node(g, level_kernel(s, r.level, a), r.grid, &a, deps, &n0);
         deps.assign(1, n0);
         return e;
     }
@@ -207,7 +213,9 @@ struct EngineImpl final : Engine {
         const LevelArgs a = level_args(s, l, substep, first, &grid);
         const HrrArgs h = hrr_args(s, a, l);
         const dim3 grid_m(a.nb_probe + a.nb_seg + a.nb_cap + h.nb_bulk);
-        if (a.nb_seg > 0)
+        if (a.nb_seg > 0 && s.lv[l].d_cls)
+            hipLaunchKernelGGL((k_hrr_macros<DIM, EQ, P, true, true>), grid_m, dim3(kBlock), 0, s.stream, h);
+        else if (a.nb_seg > 0)
             hipLaunchKernelGGL((k_hrr_macros<DIM, EQ, P, true>), grid_m, dim3(kBlock), 0, s.stream, h);
         else
             hipLaunchKernelGGL((k_hrr_macros<DIM, EQ, P, false>), grid_m, dim3(kBlock), 0, s.stream, h);

@@ -310,10 +310,10 @@ __device__ __forceinline__ const T* pull_elem(const LevelDev& g, const T* src, i
     return node_elem<DIM>(g, const_cast<T*>(src), par, i, sx, sy, sz);
 }
 
+// A box level's interface nodes and holes (from its box and its child's).
 template <int DIM>
-__device__ __forceinline__ bool is_interface_or_hole(const LevelDev& g, int x, int y, int z)
+__device__ __forceinline__ bool is_interface_or_hole_box(const LevelDev& g, int x, int y, int z)
 {
-    if (g.cls) return g.cls[((int64_t)z * g.ny + y) * g.nx + x] != kClsBulk;
     if (g.boundary &&
         (x == 0 || x == g.nx - 1 || y == 0 || y == g.ny - 1 || (DIM == 3 && (z == 0 || z == g.nz - 1))))
         return true;
@@ -321,6 +321,14 @@ __device__ __forceinline__ bool is_interface_or_hole(const LevelDev& g, int x, i
         (DIM == 2 || (z >= g.clo[2] && z <= g.chi[2])))
         return true;
     return false;
+}
+
+// Any level: a refined region's class bytes, else the box.
+template <int DIM>
+__device__ __forceinline__ bool is_interface_or_hole(const LevelDev& g, int x, int y, int z)
+{
+    if (g.cls) return g.cls[((int64_t)z * g.ny + y) * g.nx + x] != kClsBulk;
+    return is_interface_or_hole_box<DIM>(g, x, y, z);
 }
 
 template <int DIM>
@@ -530,7 +538,7 @@ __device__ __forceinline__ void put_mac(void* Mv, int64_t n, int64_t d, R drho, 
 }
 
 // HRR: the H-RR refined-mesh mode (no collision; see LevelArgs::M).
-template <int DIM, int EQ, int P, bool ROLLED, bool HRR = false>
+template <int DIM, int EQ, int P, bool ROLLED, bool HRR = false, bool RG = false>
 __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typename Form<P>::R* lds,
                                              std::bool_constant<ROLLED> = {})
 {
@@ -681,8 +689,11 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
             }
         }
         float w0[4], w1[4] = {1.f, 0.f, 0.f, 0.f};
-        const int wtype = (m.w >> 24) & 7;
-        if (wtype)
+        // a refined region's hanging nodes carry their stencil's weight type
+        // (compiled only into the region kernels: in the box kernels the
+        // extra branch spilled registers)
+        const int wtype = RG ? (m.w >> 24) & 7 : 0;
+        if (RG && wtype)
             typed_weights(wtype, w0);
         else
             line_weights(ka, Na, w0);
@@ -907,7 +918,11 @@ struct BulkTile {
 
 // Where tile bb's wave reads and writes; tile_ok false makes it a tile
 // without nodes.
-template <int DIM, int P>
+// RG: the level (or its child) is a refined region, whose node classes are
+// read from its class bytes.  Box levels keep the box test: the class read
+// in the tile's locate step raised the 2-D kernels' register demand enough
+// to spill part of the tile state to scratch.
+template <int DIM, int P, bool RG = false>
 __device__ __forceinline__ void bulk_locate(const LevelArgs& a, int bb, BulkTile<DIM, P>& t, bool tile_ok = true)
 {
     using T = typename Form<P>::T;
@@ -924,7 +939,10 @@ __device__ __forceinline__ void bulk_locate(const LevelArgs& a, int bb, BulkTile
     t.x = x;
     t.y = y;
     t.z = z;
-    t.v = in && y < g.ny && x < g.nx && !is_interface_or_hole<DIM>(g, x, y, z);
+    if constexpr (RG)
+        t.v = in && y < g.ny && x < g.nx && !is_interface_or_hole<DIM>(g, x, y, z);
+    else
+        t.v = in && y < g.ny && x < g.nx && !is_interface_or_hole_box<DIM>(g, x, y, z);
     t.any = __ballot(t.v) != 0ull;
     // 64-node row blocks (the level's xsh): a compile-time width, so that
     // each direction's offset is an immediate of the access
@@ -1019,11 +1037,11 @@ __device__ __forceinline__ void bulk_finish(const LevelArgs& a, BulkTile<DIM, P>
         B::st_nt(t.rd, (uint32_t)(t.ox[1] + i * ((int)sizeof(T) << kRowShift)), to_bits<P>(t.s[i]));
 }
 
-template <int DIM, int EQ, int P>
+template <int DIM, int EQ, int P, bool RG = false>
 __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
 {
     BulkTile<DIM, P> t;
-    bulk_locate<DIM, P>(a, bb, t);
+    bulk_locate<DIM, P, RG>(a, bb, t);
     if (!t.any) return;                                       // whole wave
     bulk_pull<DIM, P>(a, t);
     bulk_finish<DIM, EQ, P>(a, t);
@@ -1037,12 +1055,12 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
 // walks whole tile rows.
 __host__ __device__ constexpr int bulk_k(int dim, int p) { return dim == 2 && p == 2 ? 2 : 1; }
 
-template <int DIM, int EQ, int P>
+template <int DIM, int EQ, int P, bool RG = false>
 __device__ __forceinline__ void role_bulk_group(const LevelArgs& a, int b)
 {
     constexpr int K = bulk_k(DIM, P);
     if constexpr (K == 1) {
-        role_bulk<DIM, EQ, P>(a, b);
+        role_bulk<DIM, EQ, P, RG>(a, b);
     } else {
         const int c = b & 7, q = b >> 3;
         BulkTile<DIM, P> t[K];
@@ -1050,7 +1068,7 @@ __device__ __forceinline__ void role_bulk_group(const LevelArgs& a, int b)
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int m = q * K + j;   // past the level's tiles: a tile without nodes
-            bulk_locate<DIM, P>(a, 8 * m + c, t[j], m < a.tm.per);
+            bulk_locate<DIM, P, RG>(a, 8 * m + c, t[j], m < a.tm.per);
             any = any || t[j].any;
         }
         if (!any) return;                                     // whole wave
@@ -1102,7 +1120,7 @@ __device__ __forceinline__ void probe_pending(const ProbeArgs& pa, double* serie
 // register demand the segment role imposes on the whole kernel: 3-D 110
 // VGPRs, 4 waves/SIMD; 2-D FP16 78 VGPRs, 6 waves/SIMD instead of 91 and 5,
 // measured 2.4% faster.  2-D FP32/FP64 keep the unrolled loop.
-template <int DIM, int EQ, int P, bool ROLLED = (DIM == 3 || P == 2), bool SEG = true>
+template <int DIM, int EQ, int P, bool ROLLED = (DIM == 3 || P == 2), bool SEG = true, bool RG = false>
 __device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename Form<P>::R* lds)
 {
     if (b < a.nb_probe) {
@@ -1123,22 +1141,22 @@ __device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename 
     if (b2 < nseg) {
         if constexpr (SEG) {
             if (b2 < a.nb_seg) {
-                role_segment<DIM, EQ, P, ROLLED>(a, b2, lds);
+                role_segment<DIM, EQ, P, ROLLED, false, RG>(a, b2, lds);
                 return true;
             }
         }
         return false;
     }
-    role_bulk_group<DIM, EQ, P>(a, b2 - nseg);
+    role_bulk_group<DIM, EQ, P, RG>(a, b2 - nseg);
     return false;
 }
 
-template <int DIM, int EQ, int P>
+template <int DIM, int EQ, int P, bool RG = false>
 __global__ __launch_bounds__(kBlock) void k_level(LevelArgs a)
 {
     using R = typename Form<P>::R;
     __shared__ R lds[Lat<DIM>::Q * SegLimits<DIM>::TF];
-    level_block<DIM, EQ, P>(a, blockIdx.x, lds);
+    level_block<DIM, EQ, P, (DIM == 3 || P == 2), true, RG>(a, blockIdx.x, lds);
 }
 
 // The same level substep as two kernels that run side by side (3-D, FP16
@@ -1163,10 +1181,10 @@ __global__ __launch_bounds__(kBlock) void k_iface(LevelArgs a)
 // Level 0 has no parent interface, so its launch has no segment workgroups:
 // compiled without the segment role, the kernel needs only the bulk's
 // registers and runs at a higher occupancy (used for 2-D FP16 storage).
-template <int DIM, int EQ, int P>
+template <int DIM, int EQ, int P, bool RG = false>
 __global__ __launch_bounds__(kBlock) void k_level_top(LevelArgs a)
 {
-    level_block<DIM, EQ, P, true, false>(a, blockIdx.x, nullptr);
+    level_block<DIM, EQ, P, true, false, RG>(a, blockIdx.x, nullptr);
 }
 
 // ---------------------------------------------------------------- H-RR collision
@@ -1369,8 +1387,8 @@ __device__ __forceinline__ void hrr_collide_node(const LevelDev& g, const Ref<ty
 // work overlaps the bulk (one launch measured 13% faster per coarse step
 // than the segments in a launch of their own beside it on a second stream).
 // SEG: the level has segments (without them the kernel holds no LDS and
-// needs fewer registers).
-template <int DIM, int EQ, int P, bool SEG>
+// needs fewer registers); RG: they lie on a refined region's boundary.
+template <int DIM, int EQ, int P, bool SEG, bool RG = false>
 __global__ __launch_bounds__(kBlock) void k_hrr_macros(HrrArgs h)
 {
     using F = Form<P>;
@@ -1390,7 +1408,7 @@ __global__ __launch_bounds__(kBlock) void k_hrr_macros(HrrArgs h)
     b -= a.nb_probe;
     if constexpr (SEG) {
         if (b < a.nb_seg) {
-            role_segment<DIM, EQ, P, true, true>(a, b, lds);
+            role_segment<DIM, EQ, P, true, true, RG>(a, b, lds);
             return;
         }
         b -= a.nb_seg;
