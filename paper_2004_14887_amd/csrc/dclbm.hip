@@ -112,6 +112,7 @@ LevelArgs level_args(const Sim& s, int l, int substep, int first, unsigned* grid
         a.nb_seg = (int)L.seg_info.size();
         a.seg_info = L.d_seg_info;
         a.seg_tf = L.d_seg_tf;
+        a.seg_tfm = L.d_seg_tfm;
         a.seg_ie = L.d_seg_ie;
         a.seg_sten = L.d_seg_sten;
         a.n_ie = (int)L.ie_meta.size();
@@ -298,6 +299,7 @@ static dclbm_status build_segments(Sim& s, int l)
     const size_t nie = L.ie_meta.size();
     L.seg_info.clear();
     L.seg_tf.clear();
+    L.seg_tfm.clear();
     L.seg_ie.clear();
     L.seg_sten.assign(16 * nie, 0);
     L.ie_tf.assign(16 * nie, 0);
@@ -362,6 +364,7 @@ static dclbm_status build_segments(Sim& s, int l)
                         list.size(), sg.ie.size());
         L.seg_info.push_back(make_int4((int)L.seg_tf.size(), (int)list.size(), ie_off, (int)sg.ie.size()));
         L.seg_tf.insert(L.seg_tf.end(), list.begin(), list.end());
+        for (int e : list) L.seg_tfm.push_back(L.tf_meta[e & 0x3fffffff]);
     }
     // the stencil table is indexed by position in seg_ie, which is the IE order of the segments
     return DCLBM_OK;
@@ -640,6 +643,11 @@ dclbm_status build_geometry(Sim& s)
             }
             st = build_segments(s, l);
             if (st != DCLBM_OK) return st;
+            // the segment role reads hanging node q0 of its segment list as
+            // ie_meta[q0] (one dependent load fewer): the renumbering makes
+            // that list the identity
+            for (size_t q = 0; q < L.seg_ie.size(); ++q)
+                if (L.seg_ie[q] != (int)q) return fail(DCLBM_ERR_INVALID, "level %d: hanging nodes out of segment order", l);
         }
     }
     // probes: finest level whose closed box contains the point
@@ -696,6 +704,7 @@ dclbm_status build_geometry(Sim& s)
             L.off_X = take((int64_t)L.tf_meta.size() * 4 * (int64_t)s.rsize);
             L.off_seg_info = take((int64_t)L.seg_info.size() * 16);
             L.off_seg_tf = take((int64_t)L.seg_tf.size() * 4);
+            L.off_seg_tfm = take((int64_t)L.seg_tfm.size() * 16);
         }
         if (!L.ie_meta.empty()) {
             L.off_ie = take((int64_t)L.ie_meta.size() * 16);
@@ -742,9 +751,11 @@ dclbm_status sim_attach(Sim& s, void* d_workspace, size_t bytes, hipStream_t str
             L.X = s.ws + L.off_X;
             L.d_seg_info = s.at<int4>(L.off_seg_info);
             L.d_seg_tf = s.at<int>(L.off_seg_tf);
+            L.d_seg_tfm = s.at<int4>(L.off_seg_tfm);
             HIPCHECK(upload(s, L.d_tf, L.tf_meta));
             HIPCHECK(upload(s, L.d_seg_info, L.seg_info));
             HIPCHECK(upload(s, L.d_seg_tf, L.seg_tf));
+            HIPCHECK(upload(s, L.d_seg_tfm, L.seg_tfm));
         }
         if (!L.ie_meta.empty()) {
             L.d_ie = s.at<int4>(L.off_ie);

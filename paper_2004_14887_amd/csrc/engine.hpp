@@ -44,12 +44,13 @@ struct HostLevel {
     int mx = 1, my = 1, mz = 1;
     std::vector<int4> seg_info;           // (tf_off, tf_cnt, ie_off, ie_cnt)
     std::vector<int> seg_tf, seg_ie, seg_sten;
+    std::vector<int4> seg_tfm;   // tf_meta of each seg_tf entry (segment order)
     std::vector<int> ie_tf;               // [16][n_ie] co-located indices of each hanging node's stencil
     // interface with the child (coarse co-located nodes, child's order)
     std::vector<int4> tfc_meta;
     // workspace offsets
     int64_t off_f[2] = {0, 0}, off_xf[2] = {0, 0}, off_tf = 0, off_ie = 0, off_X = 0, off_tfc = 0, off_H = 0, off_seg_info = 0,
-            off_seg_tf = 0, off_seg_ie = 0, off_seg_sten = 0;
+            off_seg_tf = 0, off_seg_ie = 0, off_seg_sten = 0, off_seg_tfm = 0;
     int64_t off_M = 0, off_Mring = 0, off_ie_tf = 0;   // H-RR
     // refined region of level-0 cells (level 1 and its parent): node classes
     std::vector<uint8_t> cls;
@@ -60,6 +61,7 @@ struct HostLevel {
     void* xf[2] = {nullptr, nullptr};
     int4 *d_tf = nullptr, *d_ie = nullptr, *d_tfc = nullptr, *d_seg_info = nullptr;
     int *d_seg_tf = nullptr, *d_seg_ie = nullptr, *d_seg_sten = nullptr;
+    int4* d_seg_tfm = nullptr;
     void *X = nullptr, *H = nullptr;
     // H-RR: (drho, du) of every node [4][n]; its post-streaming values at the
     // coarse times t-dt, t, t+dt [3][4][n] (level with a child); gradients of

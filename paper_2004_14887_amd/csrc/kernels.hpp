@@ -429,7 +429,8 @@ struct LevelArgs {
     // segments (level has a parent)
     const int4* seg_info; // (tf_off, tf_cnt, ie_off, ie_cnt)
     const int* seg_tf;    // co-located index | owned << 30
-    const int* seg_ie;    // hanging-node index
+    const int4* seg_tfm;  // the co-located node's metadata, per seg_tf entry
+    const int* seg_ie;    // hanging-node index (the identity: hanging nodes are numbered in segment order)
     const int* seg_sten;  // [16][n_ie] local stencil indices into the segment's co-located list
     int n_ie;
     const int4* tf_meta;  // (x, y, z, Gamma=R mask)
@@ -557,10 +558,11 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
     // tile holds the node's h (fine value where Gamma = 1, time-interpolated
     // coarse value where Gamma = R), then its completed populations.
     if (j < info.y) {
+        // index and metadata in one round trip (not index, then metadata)
         const int e = a.seg_tf[info.x + j];
+        const int4 m = a.seg_tfm[info.x + j];
         const int t = e & 0x3fffffff;
         const bool owned = (e >> 30) & 1;
-        const int4 m = a.tf_meta[t];
         const uint32_t gR = (uint32_t)m.w;
         const R* H = (const R*)a.H_parent;
         const int64_t n = a.n_tf, slot = (int64_t)Q * n;
@@ -669,7 +671,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
     // ---- phase 2: hanging nodes
     for (int je = j; je < info.w; je += kBlock) {
         const int q0 = info.z + je;
-        const int4 m = a.ie_meta[a.seg_ie[q0]];
+        const int4 m = a.ie_meta[q0];   // hanging nodes are numbered in segment order
         const int k[3] = {m.x, m.y, m.z};
         const int N[3] = {a.g.nx - 1, a.g.ny - 1, a.g.nz - 1};
         // odd axes in increasing order carry the stencil; the first one is fastest
