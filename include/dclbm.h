@@ -189,6 +189,26 @@ dclbm_status dclbm_read_shared(const dclbm_sim* sim, int32_t level, double* d_ou
  * probe_capacity).  Synchronises. */
 dclbm_status dclbm_read_probes(const dclbm_sim* sim, double* d_out, int64_t* n_steps);
 
+/* Running sums of the probes over a window of coarse steps, from which the
+ * OASPL of Sec. 4.2 follows without keeping the series: every coarse step s
+ * with start <= s < stop (numbered as the rows of the series, from 0) that
+ * the probes sample adds to FP64 sums on the device, whatever
+ * probe_capacity is.  The sums are kept about K, each probe's first sample
+ * in the window, so that a mean far above the fluctuations does not cancel
+ * them: sum (p' - K) and sum (p' - K)^2 (each product rounded on its own).
+ * dclbm_set_probe_window sets the window and clears the sums; it is
+ * enqueued on the simulation's stream, so it applies to the steps enqueued
+ * after it (a simulation starts with the empty window [0, 0)).  Errors:
+ * DCLBM_ERR_INVALID unless 0 <= start <= stop.  The sums are part of a
+ * checkpoint. */
+dclbm_status dclbm_set_probe_window(dclbm_sim* sim, int64_t start, int64_t stop);
+
+/* The running sums [3][n_probes] FP64 into d_out (device memory, may be
+ * NULL to query): sum (p' - K), sum (p' - K)^2, then K (NaN before the first
+ * sample); *n_summed receives the number of coarse steps summed.  Samples
+ * the last step's probes if they are pending.  Synchronises. */
+dclbm_status dclbm_read_probe_sums(const dclbm_sim* sim, double* d_out, int64_t* n_summed);
+
 /* FP64 balances of the moments of Eq.(moment_rho) and Eq.(moment_rhoU):
  * mass sum rho, momentum sum rho u and kinetic energy sum rho |u|^2 / 2
  * over the nodes each level owns (the finest level containing a point owns

@@ -121,6 +121,8 @@ _SIGS = {
     "dclbm_read_shared": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "dclbm_velocity_divergence": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "dclbm_read_probes": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]),
+    "dclbm_set_probe_window": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64]),
+    "dclbm_read_probe_sums": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]),
     "dclbm_balance": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "dclbm_balance_static": (C.c_int, [C.c_void_p, C.c_void_p]),
     "dclbm_interface_bytes": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),

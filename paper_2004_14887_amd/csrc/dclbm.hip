@@ -140,6 +140,7 @@ LevelArgs level_args(const Sim& s, int l, int substep, int first, unsigned* grid
         a.probe = s.d_probe_args + L.parity;
         a.series = s.d_series;
         a.counter = s.d_counter;
+        a.psums = s.d_psum;
     }
     *grid = (unsigned)(a.nb_probe + a.nb_cap + 8 * a.seg_groups + bulk_groups(a.tm.per, bulk_k(s.D, s.P)));
     return a;
@@ -717,7 +718,8 @@ dclbm_status build_geometry(Sim& s)
         }
     }
     s.off_series = take(std::max<int64_t>(1, c.probe_capacity) * std::max(1, c.n_probes) * 8);
-    s.off_counter = take(16);
+    s.off_counter = take(40);
+    s.off_psum = take(3 * (int64_t)std::max(1, c.n_probes) * 8);
     s.off_probe_args = take(2 * (int64_t)sizeof(ProbeArgs));
     s.off_flags = take(8);
     s.off_partial = take((int64_t)DCLBM_MAX_LEVELS * s.partial_blocks * 5 * 8);
@@ -733,6 +735,14 @@ dclbm_status build_geometry(Sim& s)
         if (!L.cls.empty()) L.off_cls = take((int64_t)L.cls.size());
     s.need_bytes = (size_t)off;
     return DCLBM_OK;
+}
+
+// The running probe sums restart: zero sums, no shift yet (NaN).
+static void clear_probe_sums(Sim& s)
+{
+    const int64_t n = std::max(1, s.cfg.n_probes);
+    hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(64), 0, s.stream, s.d_psum, 2 * n, 0.0);
+    hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(64), 0, s.stream, s.d_psum + 2 * n, n, __builtin_nan(""));
 }
 
 dclbm_status sim_attach(Sim& s, void* d_workspace, size_t bytes, hipStream_t stream)
@@ -773,6 +783,7 @@ dclbm_status sim_attach(Sim& s, void* d_workspace, size_t bytes, hipStream_t str
     }
     s.d_series = s.at<double>(s.off_series);
     s.d_counter = s.at<int64_t>(s.off_counter);
+    s.d_psum = s.at<double>(s.off_psum);
     s.d_probe_args = s.at<ProbeArgs>(s.off_probe_args);
     {
         // probe buffers for either parity of level 0 (finer levels start every
@@ -803,7 +814,8 @@ dclbm_status sim_attach(Sim& s, void* d_workspace, size_t bytes, hipStream_t str
     s.d_bal = s.at<double>(s.off_bal);
     s.eng.reset(make_engine(s.D, s.EQ, s.P));
     s.eng->fill_nan(s);
-    hipLaunchKernelGGL((k_fill<int64_t>), dim3(1), dim3(64), 0, s.stream, s.d_counter, (int64_t)2, (int64_t)0);
+    hipLaunchKernelGGL((k_fill<int64_t>), dim3(1), dim3(64), 0, s.stream, s.d_counter, (int64_t)5, (int64_t)0);
+    clear_probe_sums(s);
     hipLaunchKernelGGL((k_fill<int>), dim3(1), dim3(64), 0, s.stream, s.d_flags, (int64_t)2, 0);
     HIPCHECK(hipGetLastError());
     return DCLBM_OK;
@@ -957,7 +969,7 @@ static dclbm_status check_level_impl(const dclbm_sim* sim, int32_t level)
 // A checkpoint is a 256-byte header followed by the state regions, each at a
 // 256-byte aligned offset, in the order state_regions lists them.
 // "DCLPKT02": the row pitch of 3-D refined levels changed from "01"
-static constexpr uint64_t kCkptMagic = 0x3230544b504c4344ull;   // "DCLPKT02"
+static constexpr uint64_t kCkptMagic = 0x3330544b504c4344ull;   // "DCLPKT03"
 static constexpr int64_t kCkptHeader = 256;
 
 struct CkptHeader {
@@ -1032,7 +1044,8 @@ static void state_regions(const Sim& s, Fn&& fn)
         if (L.d_Mring) fn(L.d_Mring, 3 * 4 * L.n_dense() * (int64_t)s.rsize);
     }
     fn((void*)s.d_series, std::max<int64_t>(1, s.cfg.probe_capacity) * std::max(1, s.cfg.n_probes) * 8);
-    fn((void*)s.d_counter, (int64_t)16);
+    fn((void*)s.d_counter, (int64_t)40);
+    fn((void*)s.d_psum, 3 * (int64_t)std::max(1, s.cfg.n_probes) * 8);
     fn((void*)s.d_flags, (int64_t)8);
 }
 
@@ -1115,6 +1128,7 @@ dclbm_status dclbm_create(const dclbm_config* cfg, void* d_workspace, size_t byt
         s.need_bytes = tmp.need_bytes;
         s.off_series = tmp.off_series;
         s.off_counter = tmp.off_counter;
+        s.off_psum = tmp.off_psum;
         s.off_probe_args = tmp.off_probe_args;
         s.off_flags = tmp.off_flags;
         s.off_partial = tmp.off_partial;
@@ -1284,6 +1298,37 @@ dclbm_status dclbm_read_probes(const dclbm_sim* sim, double* d_out, int64_t* n_s
     if (d_out && stored > 0 && !s.probes.empty())
         HIPCHECK(hipMemcpyAsync(d_out, s.d_series, (size_t)stored * s.probes.size() * 8, hipMemcpyDeviceToDevice,
                                 s.stream));
+    HIPCHECK(hipStreamSynchronize(s.stream));
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_set_probe_window(dclbm_sim* sim, int64_t start, int64_t stop)
+{
+    if (!sim) return fail(DCLBM_ERR_INVALID, "null argument");
+    if (start < 0 || stop < start) return fail(DCLBM_ERR_INVALID, "probe window needs 0 <= start <= stop");
+    Sim& s = sim->s;
+    // stream-ordered, so the window applies from the steps enqueued after
+    // this call; the sums restart from zero
+    hipLaunchKernelGGL((k_fill<int64_t>), dim3(1), dim3(64), 0, s.stream, s.d_counter + 2, (int64_t)1, start);
+    hipLaunchKernelGGL((k_fill<int64_t>), dim3(1), dim3(64), 0, s.stream, s.d_counter + 3, (int64_t)1, stop);
+    hipLaunchKernelGGL((k_fill<int64_t>), dim3(1), dim3(64), 0, s.stream, s.d_counter + 4, (int64_t)1, (int64_t)0);
+    clear_probe_sums(s);
+    HIPCHECK(hipGetLastError());
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_read_probe_sums(const dclbm_sim* sim, double* d_out, int64_t* n_summed)
+{
+    if (!sim || !n_summed) return fail(DCLBM_ERR_INVALID, "null argument");
+    Sim& s = const_cast<Sim&>(sim->s);
+    s.eng->probe(s);
+    HIPCHECK(hipGetLastError());
+    int64_t c = 0;
+    HIPCHECK(hipMemcpyAsync(&c, s.d_counter + 4, 8, hipMemcpyDeviceToHost, s.stream));
+    HIPCHECK(hipStreamSynchronize(s.stream));
+    *n_summed = c;
+    if (d_out && !s.probes.empty())
+        HIPCHECK(hipMemcpyAsync(d_out, s.d_psum, 3 * s.probes.size() * 8, hipMemcpyDeviceToDevice, s.stream));
     HIPCHECK(hipStreamSynchronize(s.stream));
     return DCLBM_OK;
 }

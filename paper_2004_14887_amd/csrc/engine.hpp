@@ -167,8 +167,11 @@ struct Sim {
     char* ws = nullptr;
     size_t ws_bytes = 0, need_bytes = 0;
     int64_t off_series = 0, off_counter = 0, off_flags = 0, off_partial = 0, off_bal = 0, off_probe_args = 0;
+    int64_t off_psum = 0;
     double* d_series = nullptr;
-    int64_t* d_counter = nullptr;     // [0] steps sampled by the probes, [1] coarse steps started
+    int64_t* d_counter = nullptr;     // [0] steps sampled by the probes, [1] coarse steps started,
+                                      // [2, 3] the window of the running sums, [4] steps summed
+    double* d_psum = nullptr;         // running sums of the probes [3][n_probes]
     ProbeArgs* d_probe_args = nullptr; // [2] by level-0 parity
     std::vector<ProbeArgs> h_probe_args;
     int* d_flags = nullptr;

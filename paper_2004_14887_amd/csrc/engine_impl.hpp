@@ -249,7 +249,7 @@ struct EngineImpl final : Engine {
     {
         // the pending sample of the last coarse step (a no-op if none)
         const ProbeArgs a = probe_args(s);
-        hipLaunchKernelGGL((k_probe<DIM, P>), dim3(1), dim3(64), 0, s.stream, a, s.d_series, s.d_counter);
+        hipLaunchKernelGGL((k_probe<DIM, P>), dim3(1), dim3(64), 0, s.stream, a, s.d_series, s.d_counter, s.d_psum);
     }
     void init(Sim& s, int l, const double* rho, const double* u) override
     {

@@ -455,7 +455,8 @@ struct LevelArgs {
     int nb_probe;           // 0 or 1
     const ProbeArgs* probe; // the probe buffers of the state this launch starts from
     double* series;
-    int64_t* counter;       // [0] steps sampled, [1] coarse steps started
+    int64_t* counter;       // [0] steps sampled, [1] coarse steps started, [2, 3] the sums' window, [4] steps summed
+    double* psums;          // running sums of the probes, [3][n]
     // H-RR on refined meshes: the interface role stores completed
     // pre-collision populations and their macroscopic state instead of
     // colliding (the level collides after its child's substeps)
@@ -1082,30 +1083,55 @@ __device__ __forceinline__ void role_bulk_group(const LevelArgs& a, int b)
 }
 
 // p' = (rho - 1)/3 in FP64 of every probe (thread p), appended to the series
-// at row *counter; thread 0 then advances the counter.  One workgroup.
+// at row *counter while the series has room; thread 0 then advances the
+// counter.  One workgroup.
+// sums (null: none kept): when the step lies in the window [counter[2],
+// counter[3]), the running sums of the probes take it, whatever the
+// series' capacity: the FP64 sums from which the sound pressure level of
+// Sec. 4.2 follows for runs of any length.  They are kept about the
+// window's first sample K (shifted data, so that a mean far above the
+// fluctuations does not cancel them): sums[2n + p] = K (NaN until the first
+// sample), sums[p] += d and sums[n + p] += d^2 (the product rounded on its
+// own) with d = p' - K; counter[4] counts the steps taken.
 template <int DIM, int P>
-__device__ __forceinline__ void probe_sample(const ProbeArgs& a, double* series, int64_t* counter)
+__device__ __forceinline__ void probe_sample(const ProbeArgs& a, double* series, int64_t* counter, double* sums)
 {
     using F = Form<P>;
     constexpr int Q = Lat<DIM>::Q;
     const int64_t step = *counter;
     const int p = threadIdx.x;
-    if (p < a.n && step < a.capacity) {
+    const bool keep = step < a.capacity;
+    const bool add = sums && step >= counter[2] && step < counter[3];
+    if (p < a.n && (keep || add)) {
         const typename F::T* b = reinterpret_cast<const typename F::T*>(a.buf[p]) + a.off[p];
         double r = F::rho0;
         for (int i = 0; i < Q; ++i) r += (double)F::load(b + i * a.stride[p]);
-        series[step * a.n + p] = (r - 1.0) / 3.0;
+        const double pp = (r - 1.0) / 3.0;
+        if (keep) series[step * a.n + p] = pp;
+        if (add) {
+            // the square is rounded before the add (no fused multiply-add),
+            // so the sums are those of a plain sequential loop
+#pragma clang fp contract(off)
+            double K = sums[2 * a.n + p];
+            if (K != K) sums[2 * a.n + p] = K = pp;
+            const double d = pp - K;
+            sums[p] += d;
+            sums[a.n + p] += d * d;
+        }
     }
     __syncthreads();
-    if (threadIdx.x == 0) *counter = step + 1;
+    if (threadIdx.x == 0) {
+        *counter = step + 1;
+        if (add) counter[4] += 1;
+    }
 }
 
 // Probes of a finished coarse step not sampled yet (counter[0] < counter[1]).
 template <int DIM, int P>
-__device__ __forceinline__ void probe_pending(const ProbeArgs& pa, double* series, int64_t* counter)
+__device__ __forceinline__ void probe_pending(const ProbeArgs& pa, double* series, int64_t* counter, double* sums)
 {
     const int64_t done = counter[0], started = counter[1];
-    if (done < started) probe_sample<DIM, P>(pa, series, counter);
+    if (done < started) probe_sample<DIM, P>(pa, series, counter, sums);
 }
 
 // Workgroup b of a level substep.  Grid order: the probe workgroup (level 0
@@ -1128,7 +1154,7 @@ __device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename 
     if (b < a.nb_probe) {
         // sample the previous step, then count this one as started
         const int64_t started = a.counter[1];
-        probe_pending<DIM, P>(*a.probe, a.series, a.counter);
+        probe_pending<DIM, P>(*a.probe, a.series, a.counter, a.psums);
         __syncthreads();
         if (threadIdx.x == 0) a.counter[1] = started + 1;
         return false;
@@ -1402,7 +1428,7 @@ __global__ __launch_bounds__(kBlock) void k_hrr_macros(HrrArgs h)
     if (b < a.nb_probe) {
         // the previous coarse step's probes, from the state this step reads
         const int64_t started = a.counter[1];
-        probe_pending<DIM, P>(*a.probe, a.series, a.counter);
+        probe_pending<DIM, P>(*a.probe, a.series, a.counter, a.psums);
         __syncthreads();
         if (threadIdx.x == 0) a.counter[1] = started + 1;
         return;
@@ -1865,9 +1891,9 @@ static __global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__
 // are read).
 template <int DIM, int P>
 __global__ __launch_bounds__(64) void k_probe(ProbeArgs a, double* __restrict__ series,
-                                              int64_t* __restrict__ counter)
+                                              int64_t* __restrict__ counter, double* __restrict__ sums)
 {
-    probe_pending<DIM, P>(a, series, counter);
+    probe_pending<DIM, P>(a, series, counter, sums);
 }
 
 // ---------------------------------------------------------------- serving
@@ -1982,7 +2008,7 @@ __global__ __launch_bounds__(64) void k_server_tail(MultiArgs m)
         SlotDev* sd = const_cast<SlotDev*>(m.slots) + pt[1 + k];
         const int64_t step = sd->step;
         if (step < sd->target) {
-            probe_sample<DIM, P>(sd->probe[step & 1], sd->series, sd->counter);
+            probe_sample<DIM, P>(sd->probe[step & 1], sd->series, sd->counter, nullptr);
             if (threadIdx.x == 0) sd->step = step + 1;
         }
         __syncthreads();

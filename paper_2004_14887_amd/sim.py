@@ -209,6 +209,19 @@ class Simulation:
         _lib.check(self.lib.dclbm_read_probes(self.h, C.c_void_p(out.data_ptr()), C.byref(n)))
         return out[:n.value, :np_]
 
+    def set_probe_window(self, start: int, stop: int) -> None:
+        """Running FP64 sums of p' and p'^2 over coarse steps [start, stop)
+        from the steps enqueued after this call (dclbm_set_probe_window)."""
+        _lib.check(self.lib.dclbm_set_probe_window(self.h, int(start), int(stop)))
+
+    def probe_sums(self):
+        """(sums [3][n_probes] FP64: sum (p' - K), sum (p' - K)^2, K the
+        window's first sample; steps summed)."""
+        n = C.c_int64()
+        out = self._out((3, max(1, len(self.wl.probes))))
+        _lib.check(self.lib.dclbm_read_probe_sums(self.h, C.c_void_p(out.data_ptr()), C.byref(n)))
+        return out[:, :len(self.wl.probes)], n.value
+
     def balance(self):
         out = (C.c_double * 5)()
         _lib.check(self.lib.dclbm_balance(self.h, out))

@@ -7,7 +7,8 @@ path:
   pulse has crossed the interface;
 * the spurious noise of a vortex convected across a plane (Sec. 4.2.1) or a
   30-degree-inclined (Sec. 4.2.2) interface: the overall sound pressure level
-  (OASPL) at 36 far-field probes.
+  (OASPL) at 36 far-field probes, from the FP64 running sums of the
+  probes that the device keeps over the window.
 
 Both compare the couplings DC1 and DC2.  Every step of both runs is the
 library's (through Simulation); what is done here on the host is reading
@@ -35,9 +36,23 @@ def oaspl(series: np.ndarray, start: int, stop: int, c0: float = W.C0) -> np.nda
     return 20.0 * np.log10(prms / 2e-5)
 
 
-def _run(wl: W.Workload, precision: str, device: str, steps: Optional[int] = None) -> Simulation:
+def oaspl_from_sums(sums: np.ndarray, n: int, c0: float = W.C0) -> np.ndarray:
+    """The OASPL of `oaspl` from the running sums of n coarse steps about a
+    shift K per probe (rows: sum (p' - K), sum (p' - K)^2, and K, which
+    the mean square does not depend on): the mean square about the
+    window's mean is sum d^2 / n - (sum d / n)^2."""
+    s1, s2 = np.asarray(sums, dtype=np.float64)[:2]
+    mean = s1 / n
+    prms = np.sqrt(np.maximum(s2 / n - mean * mean, 0.0)) * (c0 * c0 / W.CS2)
+    return 20.0 * np.log10(prms / 2e-5)
+
+
+def _run(wl: W.Workload, precision: str, device: str, steps: Optional[int] = None,
+         window: Optional[Tuple[int, int]] = None) -> Simulation:
     sim = Simulation(wl, precision, device=device, probe_capacity=max(1, wl.steps))
     sim.init_from_workload()
+    if window is not None:
+        sim.set_probe_window(*window)
     sim.step(wl.steps if steps is None else steps)
     sim.check()
     return sim
@@ -80,17 +95,21 @@ def vortex_oaspl(n0: int = 150, steps: int = 650, coupling: int = 2, precision: 
                  shape: str = "plane") -> dict:
     """OASPL of the spurious noise of workloads.vortex_plane (shape "plane",
     Sec. 4.2.1) or vortex_inclined ("inclined", Sec. 4.2.2), absorbing layers
-    included, at its 36 probes over the coarse-step window; `boxes=[]` runs
-    the same flow without the refinement (the level of noise the interface
-    adds to)."""
+    included, at its 36 probes over the coarse-step window, from the device's
+    running sums ("per_probe"; "per_probe_series" is the same from the
+    series); `boxes=[]` runs the same flow without the refinement (the level
+    of noise the interface adds to)."""
     make = W.vortex_inclined if shape == "inclined" else W.vortex_plane
     wl = make(n0=n0, coupling=coupling, steps=steps)
     if boxes is not None:
         wl.boxes = boxes
         wl.region = None
-    sim = _run(wl, precision, device)
+    sim = _run(wl, precision, device, window=window)
     series = sim.probes().cpu().numpy()
+    sums, n = sim.probe_sums()
+    sums = sums.cpu().numpy()
     sim.close()
-    L = oaspl(series, *window)
+    L = oaspl_from_sums(sums, n)
     return {"per_probe": L, "max": float(L.max()), "mean": float(L.mean()), "series": series,
+            "per_probe_series": oaspl(series, *window), "sums": sums, "n_summed": n,
             "workload": wl.name, "window": list(window)}

@@ -1,7 +1,7 @@
 """Checkpoint and resume through the C ABI (run with -m gpu).
 
-Stepping on from a restored checkpoint gives the same populations and
-probe series, bit for bit, as stepping on from the state that was saved.
+Stepping on from a restored checkpoint gives the same populations, probe
+series and running probe sums, bit for bit, as stepping on from the state that was saved.
 This holds when the checkpoint goes back into the simulation that wrote it,
 and when it goes into a fresh simulation of the same configuration.  It is
 checked for every storage form, in 2-D and 3-D, and for a checkpoint taken
@@ -37,13 +37,16 @@ def workload(name, steps):
 
 def state(sim):
     pops = [sim.populations(l).cpu() for l in range(sim.wl.n_levels)]
-    return pops, sim.probes().cpu()
+    sums, n = sim.probe_sums()
+    return pops, sim.probes().cpu(), sums.cpu(), n
 
 
 def same(a, b):
-    pa, sa = a
-    pb, sb = b
+    pa, sa, ua, na = a
+    pb, sb, ub, nb = b
     assert sa.shape == sb.shape and torch.equal(sa, sb), "probe series differ"
+    assert na == nb and torch.equal(torch.nan_to_num(ua, nan=-7.0), torch.nan_to_num(ub, nan=-7.0)), \
+        "probe sums differ"
     for l, (x, y) in enumerate(zip(pa, pb)):
         assert torch.equal(torch.nan_to_num(x, nan=-7.0), torch.nan_to_num(y, nan=-7.0)), f"level {l} differs"
 
@@ -58,13 +61,14 @@ def test_resume_is_bitwise(name, precision, at):
     print(f"[gpu] checkpoint {name} {precision} at step {at}", flush=True)
     a = Simulation(wl, precision, probe_capacity=at + more)
     a.init_from_workload()
+    a.set_probe_window(at - 1, at + more - 1)   # spans the checkpoint
     a.step(at)
     blob = a.save()
     assert blob.numel() == a.checkpoint_bytes()
     a.step(more)
     a.check()
     ref = state(a)
-    assert ref[1].shape[0] == at + more
+    assert ref[1].shape[0] == at + more and ref[3] == more
     # into a fresh simulation of the same configuration
     b = Simulation(wl, precision, probe_capacity=at + more)
     b.load(blob)

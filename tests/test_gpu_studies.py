@@ -184,3 +184,91 @@ def test_absorbing_layer_keeps_the_target_flow():
             m = ~torch.isnan(rho)
             assert (rho[m] - 1).abs().max().item() < 1e-14, prec
             assert (u[0][m] - 0.04).abs().max().item() < 1e-14 and (u[1][m] + 0.01).abs().max().item() < 1e-14
+
+
+def _sequential_sums(series, start, stop):
+    """Sum d = p' - K and d^2 over rows [start, stop) in row order, K the
+    first row, each product rounded on its own: the device's order of
+    operations."""
+    K = series[start]
+    s1 = np.zeros(series.shape[1])
+    s2 = np.zeros(series.shape[1])
+    for k in range(start, stop):
+        d = series[k] - K
+        s1 = s1 + d
+        s2 = s2 + d * d
+    return np.stack([s1, s2, K])
+
+
+@requires_gpu
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+def test_probe_sums_equal_the_sums_of_the_series(precision):
+    from paper_2004_14887_amd.sim import Simulation
+
+    wl = W.pulse_vortices_3level(seed=2, n0=128, steps=40)
+    print(f"[gpu] probe sums {precision}", flush=True)
+    sim = Simulation(wl, precision, probe_capacity=40)
+    sim.init_from_workload()
+    sums, n = sim.probe_sums()
+    assert n == 0 and sums[:2].abs().max().item() == 0 and sums[2].isnan().all()   # the empty window [0, 0)
+    sim.set_probe_window(7, 31)
+    sim.step(20)                                          # partway through the window
+    sums, n = sim.probe_sums()
+    assert n == 13
+    series = sim.probes().cpu().numpy()
+    assert np.array_equal(sums.cpu().numpy(), _sequential_sums(series, 7, 20))
+    sim.step(20)                                          # past its end
+    sums, n = sim.probe_sums()
+    series = sim.probes().cpu().numpy()
+    assert n == 24 and series.shape == (40, 16)
+    assert np.array_equal(sums.cpu().numpy(), _sequential_sums(series, 7, 31))
+    # a new window restarts the sums from the steps enqueued after it
+    sim.set_probe_window(45, 50)
+    sim.step(4)
+    assert sim.probe_sums()[1] == 0
+    sim.step(4)
+    sums, n = sim.probe_sums()
+    assert n == 3
+    assert sim.probes().shape[0] == 40                    # the series is full; the sums go on
+    sim.close()
+
+
+@requires_gpu
+def test_probe_sums_match_the_oracle_beyond_the_series_capacity():
+    from paper_2004_14887_amd.sim import Simulation
+
+    wl = W.pulse_vortices_3level(seed=2, n0=128, steps=40)
+    print("[gpu] probe sums against the oracle, capacity 8 of 40 steps", flush=True)
+    sim = Simulation(wl, "fp64", probe_capacity=8)
+    sim.init_from_workload()
+    sim.set_probe_window(5, 40)
+    sim.step(40)
+    sums, n = sim.probe_sums()
+    assert n == 35 and sim.probes().shape[0] == 8
+    ref = oracle_run(wl, probes=True).probes()
+    got = sums.cpu().numpy()
+    # the shift is the window's first sample; the sums, taken back to sums
+    # of p' and p'^2, are those of the oracle's series
+    assert np.abs(got[2] - ref[5]).max() < 1e-13
+    K = got[2]
+    s1 = got[0] + n * K
+    s2 = got[1] + 2 * K * got[0] + n * K * K
+    want = np.stack([ref[5:40].sum(axis=0), (ref[5:40] ** 2).sum(axis=0)])
+    e = np.abs(np.stack([s1, s2]) - want) / np.abs(want).max(axis=1, keepdims=True)
+    print(f"  relative error {e.max():.2e}", flush=True)
+    assert e.max() < 1e-12
+    from paper_2004_14887_amd import studies
+    assert np.abs(studies.oaspl_from_sums(got, n) - O.oaspl(ref, 5, 40)).max() < 1e-6
+
+
+@requires_gpu
+def test_probe_window_rejects_bad_bounds():
+    from paper_2004_14887_amd._lib import DclbmError
+    from paper_2004_14887_amd.sim import Simulation
+
+    wl = W.pulse_vortices_3level(seed=2, n0=128, steps=2)
+    sim = Simulation(wl, "fp32", probe_capacity=2)
+    for a, b in ((-1, 3), (5, 4)):
+        with pytest.raises(DclbmError):
+            sim.set_probe_window(a, b)
+    sim.close()

@@ -2,7 +2,9 @@
 reduction and the uniform-fine reference of the reflection study.
 
 * OASPL of a sinusoid of amplitude a (Pa) is 20 log10(a / sqrt(2) / 2e-5) dB,
-  whatever its mean; both the oracle's reduction and the product's.
+  whatever its mean; both the oracle's reduction and the product's, the
+  latter also from running sums of p' and p'^2 about the first sample (over
+  whole periods).
 * The reflection study's reference (one periodic level at the fine spacing,
   tau from Eq.(rescTau), twice the steps) must equal the refined run on the
   fine region until the pulse reaches the interfaces: with the oracle, after
@@ -28,6 +30,11 @@ def test_oaspl_of_a_sinusoid(mean):
     assert np.abs(O.oaspl(series, 0, 400) - expect).max() < 1e-9
     studies = pytest.importorskip("paper_2004_14887_amd.studies")
     assert np.abs(studies.oaspl(series, 0, 400) - expect).max() < 1e-9
+    # from the running sums the device keeps: the same level
+    d = series[100:380] - series[100]
+    sums = np.stack([d.sum(axis=0), (d * d).sum(axis=0), series[100]])
+    assert np.abs(studies.oaspl_from_sums(sums, 280) - expect).max() < 1e-6
+    assert np.abs(studies.oaspl_from_sums(sums, 280) - O.oaspl(series, 100, 380)).max() < 1e-9
 
 
 def _divergence_run(wl, steps):
