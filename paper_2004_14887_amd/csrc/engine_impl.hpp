@@ -53,8 +53,8 @@ struct EngineImpl final : Engine {
                 // 3-D FP16 storage, eager launches (graphs get the same two
                 // kernels as independent nodes, see add_nodes): the bulk on
                 // the simulation's stream, the interface workgroups beside it
-                // on the side stream (fork, launch both, join).  Alone, the bulk kernel needs 46 VGPRs
-                // instead of 110 and runs at 8 waves per SIMD instead of 4,
+                // on the side stream (fork, launch both, join).  Alone, the bulk kernel needs 49 VGPRs
+                // instead of 108 and runs at 8 waves per SIMD instead of 4,
                 // which the 2-byte loads need to keep enough bytes in flight
                 // (measured 4% faster).  The FP32/FP64 bulk and every 2-D
                 // form measured slower split, so they stay one launch.
@@ -99,9 +99,9 @@ struct EngineImpl final : Engine {
         }
     }
     // The level-substep kernel of level l: without the segment role on
-    // level 0 of a 2-D FP16 mesh (38 VGPRs and 8 waves/SIMD instead of 78
-    // and 6, measured 11% faster on that launch; FP32 and FP64 gain
-    // nothing), and reading node classes on the levels of a refined region.
+    // level 0 of a 2-D FP16 mesh (38 VGPRs and 8 waves/SIMD instead of 70
+    // and 7; 11% faster on that launch when the full kernel ran at 6 waves;
+    // FP32 and FP64 gain nothing), and reading node classes on the levels of a refined region.
     static const void* level_kernel(const Sim& s, int l, const LevelArgs& a)
     {
         const bool top = DIM == 2 && P == 2 && a.nb_seg == 0;

@@ -557,7 +557,10 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
     const int j = threadIdx.x;
     // ---- phase 1: co-located nodes (own and halo).  Column j of the LDS
     // tile holds the node's h (fine value where Gamma = 1, time-interpolated
-    // coarse value where Gamma = R), then its completed populations.
+    // coarse value where Gamma = R), then its completed populations.  Only
+    // thread j touches column j before the barrier, so the column is plain
+    // LDS: a volatile column went through flat accesses, each waited for,
+    // which serialised the Q loads of the node behind one another.
     if (j < info.y) {
         // index and metadata in one round trip (not index, then metadata)
         const int e = a.seg_tf[info.x + j];
@@ -567,7 +570,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
         const uint32_t gR = (uint32_t)m.w;
         const R* H = (const R*)a.H_parent;
         const int64_t n = a.n_tf, slot = (int64_t)Q * n;
-        volatile R* col = lds + j;
+        R* col = lds + j;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             R v;
@@ -1145,9 +1148,9 @@ __device__ __forceinline__ void probe_pending(const ProbeArgs& pa, double* serie
 // of the workgroup calls this with the same arguments (the segment role
 // synchronises).  Returns true when the workgroup used the LDS (segment role).
 // ROLLED keeps the Newton loop over directions rolled.  That caps the
-// register demand the segment role imposes on the whole kernel: 3-D 110
-// VGPRs, 4 waves/SIMD; 2-D FP16 78 VGPRs, 6 waves/SIMD instead of 91 and 5,
-// measured 2.4% faster.  2-D FP32/FP64 keep the unrolled loop.
+// register demand the segment role imposes on the whole kernel: 3-D FP32
+// 108 VGPRs, 4 waves/SIMD; 2-D FP16 70 VGPRs, 7 waves/SIMD (unrolled, 91
+// and 5).  2-D FP32/FP64 keep the unrolled loop.
 template <int DIM, int EQ, int P, bool ROLLED = (DIM == 3 || P == 2), bool SEG = true, bool RG = false>
 __device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename Form<P>::R* lds)
 {
