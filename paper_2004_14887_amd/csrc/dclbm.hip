@@ -89,6 +89,11 @@ static __global__ __launch_bounds__(64) void k_balance_levels(const double* __re
 }
 
 // ------------------------------------------------------------------ launch arguments
+// 3-D: one group of 8 segment workgroups after every kSegEvery3D groups of
+// bulk workgroups (fewer where the bulk is small), so that the segments of a
+// refined level's faces spread over the front third of its launch.
+static constexpr int kSegEvery3D = 32;
+
 LevelArgs level_args(const Sim& s, int l, int substep, int first, unsigned* grid)
 {
     const HostLevel& L = s.lv[l];
@@ -142,7 +147,9 @@ LevelArgs level_args(const Sim& s, int l, int substep, int first, unsigned* grid
         a.counter = s.d_counter;
         a.psums = s.d_psum;
     }
-    *grid = (unsigned)(a.nb_probe + a.nb_cap + 8 * a.seg_groups + bulk_groups(a.tm.per, bulk_k(s.D, s.P)));
+    const int nbg = bulk_groups(a.tm.per, bulk_k(s.D, s.P)) / 8;
+    if (s.D == 3 && a.seg_groups > 0) a.seg_every = std::min(kSegEvery3D, nbg / a.seg_groups);
+    *grid = (unsigned)(a.nb_probe + a.nb_cap + 8 * a.seg_groups + 8 * nbg);
     return a;
 }
 
@@ -1142,12 +1149,6 @@ dclbm_status dclbm_create(const dclbm_config* cfg, void* d_workspace, size_t byt
     HIPCHECK(hipGetDevice(&s.device));
     st = scratch_address(s.device, &s.d_scratch);
     if (st != DCLBM_OK) return st;
-    if (s.D == 3 && s.P == 2) {
-        // side stream (default priority) for the interface half of the split substeps
-        HIPCHECK(hipStreamCreateWithFlags(&s.side, hipStreamNonBlocking));
-        HIPCHECK(hipEventCreateWithFlags(&s.ev_fork, hipEventDisableTiming));
-        HIPCHECK(hipEventCreateWithFlags(&s.ev_join, hipEventDisableTiming));
-    }
     HIPCHECK(hipStreamSynchronize(s.stream));
     *out = h.release();
     return DCLBM_OK;
@@ -1168,7 +1169,7 @@ dclbm_status dclbm_destroy(dclbm_sim* sim)
             (void)hipEventDestroy(e.second);
         }
     }
-    delete sim;   // releases the side stream and its events
+    delete sim;
     return DCLBM_OK;
 }
 

@@ -161,9 +161,6 @@ struct Sim {
     std::vector<ProbeLoc> probes;
     std::vector<int32_t> probe_xyz;
     hipStream_t stream = nullptr;
-    // second stream and fork/join events of the split (3-D) level substeps
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     char* ws = nullptr;
     size_t ws_bytes = 0, need_bytes = 0;
     int64_t off_series = 0, off_counter = 0, off_flags = 0, off_partial = 0, off_bal = 0, off_probe_args = 0;
@@ -206,16 +203,6 @@ struct Sim {
     T* at(int64_t off) const
     {
         return reinterpret_cast<T*>(ws + off);
-    }
-
-    ~Sim()
-    {
-        if (side) {
-            (void)hipStreamSynchronize(side);
-            (void)hipStreamDestroy(side);
-        }
-        if (ev_fork) (void)hipEventDestroy(ev_fork);
-        if (ev_join) (void)hipEventDestroy(ev_join);
     }
 };
 

@@ -48,40 +48,6 @@ struct EngineImpl final : Engine {
             }
             return;
         }
-        if constexpr (DIM == 3 && P == 2) {
-            if (s.side) {
-                // 3-D FP16 storage, eager launches (graphs get the same two
-                // kernels as independent nodes, see add_nodes): the bulk on
-                // the simulation's stream, the interface workgroups beside it
-                // on the side stream (fork, launch both, join).  Alone, the bulk kernel needs 49 VGPRs
-                // instead of 108 and runs at 8 waves per SIMD instead of 4,
-                // which the 2-byte loads need to keep enough bytes in flight
-                // (measured 4% faster).  The FP32/FP64 bulk and every 2-D
-                // form measured slower split, so they stay one launch.
-                const unsigned g_bulk = (unsigned)bulk_groups(a.tm.per, bulk_k(DIM, P)), g_if = grid - g_bulk;
-                hipEvent_t e0 = nullptr, e1 = nullptr;
-                if (s.timing) {
-                    s.note(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
-                    s.note(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
-                    s.note(hipEventRecord(e0, s.stream));
-                }
-                if (g_if > 0) {
-                    s.note(hipEventRecord(s.ev_fork, s.stream));
-                    s.note(hipStreamWaitEvent(s.side, s.ev_fork, 0));
-                    hipLaunchKernelGGL((k_iface<DIM, EQ, P>), dim3(g_if), dim3(kBlock), 0, s.side, a);
-                }
-                if (g_bulk > 0) hipLaunchKernelGGL((k_bulk<DIM, EQ, P>), dim3(g_bulk), dim3(kBlock), 0, s.stream, a);
-                if (g_if > 0) {
-                    s.note(hipEventRecord(s.ev_join, s.side));
-                    s.note(hipStreamWaitEvent(s.stream, s.ev_join, 0));
-                }
-                if (s.timing) {
-                    s.note(hipEventRecord(e1, s.stream));
-                    s.tev[l].push_back({e0, e1});
-                }
-                return;
-            }
-        }
         const void* f = level_kernel(s, l, a);
         LevelArgs arg = a;
         void* params[1] = {&arg};
@@ -99,12 +65,13 @@ struct EngineImpl final : Engine {
         }
     }
     // The level-substep kernel of level l: without the segment role on
-    // level 0 of a 2-D FP16 mesh (38 VGPRs and 8 waves/SIMD instead of 70
-    // and 7; 11% faster on that launch when the full kernel ran at 6 waves;
-    // FP32 and FP64 gain nothing), and reading node classes on the levels of a refined region.
+    // level 0 with FP16 storage (2-D: 38 VGPRs and 8 waves/SIMD instead of
+    // 70 and 7; 3-D: 50 and 8 instead of 108 and 4, 239 -> 221 us on the
+    // 256^3 level 0; FP32 and FP64 gain nothing, 3-D FP32 lost), and reading
+    // node classes on the levels of a refined region.
     static const void* level_kernel(const Sim& s, int l, const LevelArgs& a)
     {
-        const bool top = DIM == 2 && P == 2 && a.nb_seg == 0;
+        const bool top = P == 2 && a.nb_seg == 0;
         if constexpr (DIM == 2) {
             if (s.lv[l].d_cls)
                 return top ? reinterpret_cast<const void*>(&k_level_top<DIM, EQ, P, true>)
@@ -114,10 +81,8 @@ struct EngineImpl final : Engine {
                    : reinterpret_cast<const void*>(&k_level<DIM, EQ, P>);
     }
     // The same launches as level_step, as graph nodes with explicit
-    // dependencies (no stream capture, so no events or side stream take part
-    // in building a graph): one node per launch in a chain, except the two
-    // kernels of a split 3-D FP16 substep, which both depend on the previous
-    // node(s) and not on each other.
+    // dependencies (no stream capture, so no events take part in building a
+    // graph): one node per launch, in a chain.
     static hipError_t kernel_node(hipGraph_t g, const void* func, unsigned grid, void* args,
                                   const std::vector<hipGraphNode_t>& deps, hipGraphNode_t* out)
     {
@@ -145,24 +110,6 @@ struct EngineImpl final : Engine {
             e = kernel_node(g, reinterpret_cast<const void*>(&k_hrr_collide<DIM, EQ, P>), g_bulk, &h, {n0}, &n1);
             deps.assign(1, n1);
             return e;
-        }
-        if constexpr (DIM == 3 && P == 2) {
-            if (s.side) {
-                const unsigned g_bulk = (unsigned)bulk_groups(a.tm.per, bulk_k(DIM, P)), g_if = r.grid - g_bulk;
-                std::vector<hipGraphNode_t> out;
-                if (g_if > 0) {
-                    e = kernel_node(g, reinterpret_cast<const void*>(&k_iface<DIM, EQ, P>), g_if, &a, deps, &n0);
-                    if (e != hipSuccess) return e;
-                    out.push_back(n0);
-                }
-                if (g_bulk > 0) {
-                    e = kernel_node(g, reinterpret_cast<const void*>(&k_bulk<DIM, EQ, P>), g_bulk, &a, deps, &n1);
-                    if (e != hipSuccess) return e;
-                    out.push_back(n1);
-                }
-                deps = out;
-                return hipSuccess;
-            }
         }
         e = kernel_node(g, level_kernel(s, r.level, a), r.grid, &a, deps, &n0);
         deps.assign(1, n0);

@@ -422,6 +422,8 @@ struct LevelArgs {
     TileMap tm;
     int nb_cap, nb_seg;   // workgroups of the capture and segment roles
     int seg_groups;       // ceil(nb_seg / 8): segment workgroups are padded to a multiple of 8
+    int seg_every;        // 0: the segment groups precede the bulk; else one segment group follows
+                          // every seg_every bulk groups (seg_groups * seg_every <= bulk groups)
     // capture (level has a child): coarse co-located nodes of this level
     const int4* cap_meta; // (x, y, z, K^c mask)
     int n_cap;
@@ -1140,13 +1142,17 @@ __device__ __forceinline__ void probe_pending(const ProbeArgs& pa, double* serie
 // Workgroup b of a level substep.  Grid order: the probe workgroup (level 0
 // of a single simulation), the capture workgroups, the interface segments
 // (padded to a multiple of 8), then the bulk tiles.  Segment work is
-// latency-bound (Newton, gathers) and bulk work bandwidth-bound: placed first,
-// the segments overlap the bulk tiles that start behind them and stay out of
-// the launch's tail (spreading them over the grid, or placing them after the
-// bulk rows they touch, measured slower).  The padding keeps bulk workgroup
-// b' on XCD b' % 8 up to a fixed rotation, as TileMap assumes.  Every thread
-// of the workgroup calls this with the same arguments (the segment role
-// synchronises).  Returns true when the workgroup used the LDS (segment role).
+// latency-bound (Newton, gathers) and bulk work bandwidth-bound: placed
+// ahead of the bulk, the segments overlap the bulk tiles and stay out of the
+// launch's tail.  In 2-D they all go first (spreading them over the grid, or
+// placing them after the bulk rows they touch, measured slower).  A 3-D face
+// has so many segments that, all first, they hold most of the chip's wave
+// slots while they run and starve the bulk; there seg_every interleaves
+// them, one group of 8 after every seg_every groups of 8 bulk workgroups, over
+// the front of the grid.  Groups of 8 keep bulk workgroup b' on XCD b' % 8 up
+// to a fixed rotation, as TileMap assumes.  Every thread of the workgroup
+// calls this with the same arguments (the segment role synchronises).
+// Returns true when the workgroup used the LDS (segment role).
 // ROLLED keeps the Newton loop over directions rolled.  That caps the
 // register demand the segment role imposes on the whole kernel: 3-D FP32
 // 108 VGPRs, 4 waves/SIMD; 2-D FP16 70 VGPRs, 7 waves/SIMD (unrolled, 91
@@ -1168,17 +1174,33 @@ __device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename 
         return false;
     }
     const int b2 = b - a.nb_cap;
-    const int nseg = 8 * a.seg_groups;
-    if (b2 < nseg) {
+    // the segment workgroup sb, or (sb < 0) the bulk workgroup bb; one call
+    // site per role (a second one put the kernel's arguments in scratch)
+    int sb = -1, bb = b2 - 8 * a.seg_groups;
+    if (a.seg_every > 0) {
+        const int G = b2 >> 3, r = b2 & 7, per = a.seg_every + 1;
+        const int k = G / per, q = G - k * per;
+        if (k < a.seg_groups) {
+            if (q == 0)
+                sb = 8 * k + r;
+            else
+                bb = 8 * (k * a.seg_every + q - 1) + r;
+        } else {
+            bb = 8 * (a.seg_groups * a.seg_every + G - a.seg_groups * per) + r;
+        }
+    } else if (bb < 0) {
+        sb = b2;
+    }
+    if (sb >= 0) {
         if constexpr (SEG) {
-            if (b2 < a.nb_seg) {
-                role_segment<DIM, EQ, P, ROLLED, false, RG>(a, b2, lds);
+            if (sb < a.nb_seg) {
+                role_segment<DIM, EQ, P, ROLLED, false, RG>(a, sb, lds);
                 return true;
             }
         }
         return false;
     }
-    role_bulk_group<DIM, EQ, P, RG>(a, b2 - nseg);
+    role_bulk_group<DIM, EQ, P, RG>(a, bb);
     return false;
 }
 
@@ -1190,28 +1212,9 @@ __global__ __launch_bounds__(kBlock) void k_level(LevelArgs a)
     level_block<DIM, EQ, P, (DIM == 3 || P == 2), true, RG>(a, blockIdx.x, lds);
 }
 
-// The same level substep as two kernels that run side by side (3-D, FP16
-// storage): the bulk tiles alone, which then run at the occupancy of their
-// own register demand, and the probe, capture and interface-segment
-// workgroups.  The two write disjoint nodes and read only the source
-// buffers, so neither waits for the other.
-template <int DIM, int EQ, int P>
-__global__ __launch_bounds__(kBlock) void k_bulk(LevelArgs a)
-{
-    role_bulk_group<DIM, EQ, P>(a, blockIdx.x);
-}
-
-template <int DIM, int EQ, int P>
-__global__ __launch_bounds__(kBlock) void k_iface(LevelArgs a)
-{
-    using R = typename Form<P>::R;
-    __shared__ R lds[Lat<DIM>::Q * SegLimits<DIM>::TF];
-    level_block<DIM, EQ, P>(a, blockIdx.x, lds);   // the grid ends before the bulk tiles
-}
-
 // Level 0 has no parent interface, so its launch has no segment workgroups:
 // compiled without the segment role, the kernel needs only the bulk's
-// registers and runs at a higher occupancy (used for 2-D FP16 storage).
+// registers and runs at a higher occupancy (used for FP16 storage).
 template <int DIM, int EQ, int P, bool RG = false>
 __global__ __launch_bounds__(kBlock) void k_level_top(LevelArgs a)
 {

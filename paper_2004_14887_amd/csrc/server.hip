@@ -356,6 +356,7 @@ dclbm_status admit(Server& sv, Request& r, int k, size_t off)
                 return fail(DCLBM_ERR_INVALID, "internal: phase order mismatch");
             ha[(size_t)var * sv.NPH + p] = rec[next].args;
             ha[(size_t)var * sv.NPH + p].nb_probe = 0;   // the tail launch samples the probes
+            ha[(size_t)var * sv.NPH + p].seg_every = 0;  // virtual workgroups: segments first
             ++next;
         }
     }
