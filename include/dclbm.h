@@ -268,13 +268,25 @@ dclbm_status dclbm_save(dclbm_sim* sim, void* d_blob, size_t bytes);
 dclbm_status dclbm_load(dclbm_sim* sim, const void* d_blob, size_t bytes);
 
 /* Instrumentation: when on, steps run without graphs and every level-substep
- * launch carries start/stop events in its dispatch (a 3-D FP16 substep, which
- * runs as two kernels side by side, is timed from the fork to the join by
- * events on the stream); dclbm_bulk_time returns
+ * launch carries start/stop events in its dispatch (a split 3-D FP16 substep,
+ * two kernels side by side, is timed from the fork to the join by events on
+ * the stream); dclbm_bulk_time returns
  * the summed milliseconds, the launch count and the nodes one launch of that
  * level updates (active nodes minus the coarse co-located nodes, which the
  * child's synchronous substep updates). */
 dclbm_status dclbm_set_timing(dclbm_sim* sim, int32_t on);
+
+/* Launch layout (no effect on results, which are bit-identical either way):
+ * with FP16 storage in 3-D a refined level's substep runs either as one
+ * launch, its interface segments interleaved over the front of the grid, or
+ * split into two kernels side by side on a second stream (the bulk alone at
+ * a higher occupancy; the probe, capture and segment workgroups beside it).
+ * mode -1 (the default) splits where the bulk outweighs the segments by
+ * enough to pay for it, 0 never splits, 1 splits every substep with
+ * segments; other forms ignore it.  Synchronises and drops the cached
+ * coarse-step graphs, which the next step rebuilds.  Errors:
+ * DCLBM_ERR_INVALID for another mode. */
+dclbm_status dclbm_set_split(dclbm_sim* sim, int32_t mode);
 dclbm_status dclbm_bulk_time(dclbm_sim* sim, int32_t level, double* ms, int64_t* launches,
                              int64_t* nodes_per_launch);
 

@@ -130,6 +130,7 @@ _SIGS = {
     "dclbm_save": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "dclbm_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "dclbm_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+    "dclbm_set_split": (C.c_int, [C.c_void_p, C.c_int32]),
     "dclbm_bulk_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                   C.POINTER(C.c_int64)]),
     "dclbm_copy_calibration": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32,

@@ -1149,6 +1149,12 @@ dclbm_status dclbm_create(const dclbm_config* cfg, void* d_workspace, size_t byt
     HIPCHECK(hipGetDevice(&s.device));
     st = scratch_address(s.device, &s.d_scratch);
     if (st != DCLBM_OK) return st;
+    if (s.D == 3 && s.P == 2) {
+        // side stream (default priority) for the interface half of split substeps
+        HIPCHECK(hipStreamCreateWithFlags(&s.side, hipStreamNonBlocking));
+        HIPCHECK(hipEventCreateWithFlags(&s.ev_fork, hipEventDisableTiming));
+        HIPCHECK(hipEventCreateWithFlags(&s.ev_join, hipEventDisableTiming));
+    }
     HIPCHECK(hipStreamSynchronize(s.stream));
     *out = h.release();
     return DCLBM_OK;
@@ -1169,7 +1175,7 @@ dclbm_status dclbm_destroy(dclbm_sim* sim)
             (void)hipEventDestroy(e.second);
         }
     }
-    delete sim;
+    delete sim;   // releases the side stream and its events
     return DCLBM_OK;
 }
 
@@ -1492,6 +1498,24 @@ dclbm_status dclbm_interface_bytes(const dclbm_sim* sim, int32_t level, double* 
         b += 0.5 * (double)L.tf_meta.size() * s.Q * ts;
     }
     *bytes_per_launch = b;
+    return DCLBM_OK;
+}
+
+dclbm_status dclbm_set_split(dclbm_sim* sim, int32_t mode)
+{
+    if (!sim) return fail(DCLBM_ERR_INVALID, "null simulation");
+    if (mode < -1 || mode > 1) return fail(DCLBM_ERR_INVALID, "split mode %d is not -1, 0 or 1", mode);
+    Sim& s = sim->s;
+    if (mode == s.split_mode) return DCLBM_OK;
+    // the coarse-step graphs hold the launches of the old choice
+    if (s.stream) HIPCHECK(hipStreamSynchronize(s.stream));
+    for (int p = 0; p < 2; ++p) {
+        if (s.gexec[p]) HIPCHECK(hipGraphExecDestroy(s.gexec[p]));
+        if (s.graph[p]) HIPCHECK(hipGraphDestroy(s.graph[p]));
+        s.gexec[p] = nullptr;
+        s.graph[p] = nullptr;
+    }
+    s.split_mode = mode;
     return DCLBM_OK;
 }
 

@@ -161,6 +161,9 @@ struct Sim {
     std::vector<ProbeLoc> probes;
     std::vector<int32_t> probe_xyz;
     hipStream_t stream = nullptr;
+    // second stream and fork/join events of the split 3-D FP16 level substeps
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     char* ws = nullptr;
     size_t ws_bytes = 0, need_bytes = 0;
     int64_t off_series = 0, off_counter = 0, off_flags = 0, off_partial = 0, off_bal = 0, off_probe_args = 0;
@@ -181,6 +184,7 @@ struct Sim {
     int device = -1;                  // device current at creation
     double* d_scratch = nullptr;      // that device's static scratch array (dclbm_balance_static)
     std::unique_ptr<Engine> eng;
+    int split_mode = -1;              // 3-D FP16 split substeps: -1 by weight, 0 never, 1 wherever segments exist
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
     int64_t steps_done = 0;
@@ -203,6 +207,16 @@ struct Sim {
     T* at(int64_t off) const
     {
         return reinterpret_cast<T*>(ws + off);
+    }
+
+    ~Sim()
+    {
+        if (side) {
+            (void)hipStreamSynchronize(side);
+            (void)hipStreamDestroy(side);
+        }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
     }
 };
 

@@ -48,6 +48,31 @@ struct EngineImpl final : Engine {
             }
             return;
         }
+        if (split_substep(s, a)) {
+            // the bulk on the simulation's stream, the probe, capture and
+            // segment workgroups beside it on the side stream (fork, launch
+            // both, join)
+            const unsigned g_bulk = (unsigned)bulk_groups(a.tm.per, bulk_k(DIM, P)), g_if = grid - g_bulk;
+            LevelArgs ai = a;
+            ai.seg_every = 0;   // its grid holds the segments alone
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (s.timing) {
+                s.note(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+                s.note(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+                s.note(hipEventRecord(e0, s.stream));
+            }
+            s.note(hipEventRecord(s.ev_fork, s.stream));
+            s.note(hipStreamWaitEvent(s.side, s.ev_fork, 0));
+            hipLaunchKernelGGL((k_iface<DIM, EQ, P>), dim3(g_if), dim3(kBlock), 0, s.side, ai);
+            hipLaunchKernelGGL((k_bulk<DIM, EQ, P>), dim3(g_bulk), dim3(kBlock), 0, s.stream, a);
+            s.note(hipEventRecord(s.ev_join, s.side));
+            s.note(hipStreamWaitEvent(s.stream, s.ev_join, 0));
+            if (s.timing) {
+                s.note(hipEventRecord(e1, s.stream));
+                s.tev[l].push_back({e0, e1});
+            }
+            return;
+        }
         const void* f = level_kernel(s, l, a);
         LevelArgs arg = a;
         void* params[1] = {&arg};
@@ -63,6 +88,24 @@ struct EngineImpl final : Engine {
         } else {
             s.note(hipLaunchKernel(f, dim3(grid), dim3(kBlock), params, 0, s.stream));
         }
+    }
+    // 3-D FP16 storage: a level substep whose bulk outweighs its segments by
+    // kSplitRatio or more bulk groups per segment group runs as two kernels
+    // side by side, the bulk alone at 8 waves/SIMD (49 VGPRs instead of
+    // 108), which its 2-byte loads need (the 512^3 4-level mesh's finest
+    // launch: 20.6 -> 18.3 ms).  Where the faces weigh more, one launch with
+    // the segments interleaved over its front is faster (the 256^3 2-level
+    // mesh's level 1: 364 -> 333 us).  Levels without segments use
+    // k_level_top.
+    static constexpr int kSplitRatio = 150;
+    // (dclbm_set_split overrides the choice.)
+    static bool split_substep(const Sim& s, const LevelArgs& a)
+    {
+        if constexpr (DIM == 3 && P == 2) {
+            if (!s.side || a.seg_groups == 0 || s.split_mode == 0) return false;
+            return s.split_mode == 1 || bulk_groups(a.tm.per, bulk_k(DIM, P)) / 8 >= kSplitRatio * a.seg_groups;
+        }
+        return false;
     }
     // The level-substep kernel of level l: without the segment role on
     // level 0 with FP16 storage (2-D: 38 VGPRs and 8 waves/SIMD instead of
@@ -81,8 +124,10 @@ struct EngineImpl final : Engine {
                    : reinterpret_cast<const void*>(&k_level<DIM, EQ, P>);
     }
     // The same launches as level_step, as graph nodes with explicit
-    // dependencies (no stream capture, so no events take part in building a
-    // graph): one node per launch, in a chain.
+    // dependencies (no stream capture, so no events or side stream take part
+    // in building a graph): one node per launch in a chain, except the two
+    // kernels of a split substep, which both depend on the previous node(s)
+    // and not on each other.
     static hipError_t kernel_node(hipGraph_t g, const void* func, unsigned grid, void* args,
                                   const std::vector<hipGraphNode_t>& deps, hipGraphNode_t* out)
     {
@@ -110,6 +155,17 @@ struct EngineImpl final : Engine {
             e = kernel_node(g, reinterpret_cast<const void*>(&k_hrr_collide<DIM, EQ, P>), g_bulk, &h, {n0}, &n1);
             deps.assign(1, n1);
             return e;
+        }
+        if (split_substep(s, a)) {
+            const unsigned g_bulk = (unsigned)bulk_groups(a.tm.per, bulk_k(DIM, P)), g_if = r.grid - g_bulk;
+            LevelArgs ai = a;
+            ai.seg_every = 0;   // its grid holds the segments alone
+            e = kernel_node(g, reinterpret_cast<const void*>(&k_iface<DIM, EQ, P>), g_if, &ai, deps, &n0);
+            if (e != hipSuccess) return e;
+            e = kernel_node(g, reinterpret_cast<const void*>(&k_bulk<DIM, EQ, P>), g_bulk, &a, deps, &n1);
+            if (e != hipSuccess) return e;
+            deps.assign({n0, n1});
+            return hipSuccess;
         }
         e = kernel_node(g, level_kernel(s, r.level, a), r.grid, &a, deps, &n0);
         deps.assign(1, n0);

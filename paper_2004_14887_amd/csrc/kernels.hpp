@@ -1212,6 +1212,26 @@ __global__ __launch_bounds__(kBlock) void k_level(LevelArgs a)
     level_block<DIM, EQ, P, (DIM == 3 || P == 2), true, RG>(a, blockIdx.x, lds);
 }
 
+// The same level substep as two kernels that run side by side (3-D, FP16
+// storage, levels whose bulk far outweighs their faces): the bulk tiles
+// alone, which then run at the occupancy of their own register demand, and
+// the probe, capture and interface-segment workgroups.  The two write
+// disjoint nodes and read only the source buffers, so neither waits for the
+// other.
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(kBlock) void k_bulk(LevelArgs a)
+{
+    role_bulk_group<DIM, EQ, P>(a, blockIdx.x);
+}
+
+template <int DIM, int EQ, int P>
+__global__ __launch_bounds__(kBlock) void k_iface(LevelArgs a)
+{
+    using R = typename Form<P>::R;
+    __shared__ R lds[Lat<DIM>::Q * SegLimits<DIM>::TF];
+    level_block<DIM, EQ, P>(a, blockIdx.x, lds);   // the grid ends before the bulk tiles (seg_every 0)
+}
+
 // Level 0 has no parent interface, so its launch has no segment workgroups:
 // compiled without the segment role, the kernel needs only the bulk's
 // registers and runs at a higher occupancy (used for FP16 storage).

@@ -256,6 +256,11 @@ class Simulation:
         self._sync_torch()
         _lib.check(self.lib.dclbm_load(self.h, C.c_void_p(blob.data_ptr()), blob.numel()))
 
+    def set_split(self, mode: int):
+        """3-D FP16 launch layout (dclbm_set_split): -1 by weight, 0 one
+        launch, 1 bulk and segments as two kernels side by side."""
+        _lib.check(self.lib.dclbm_set_split(self.h, int(mode)))
+
     def set_timing(self, on: bool):
         _lib.check(self.lib.dclbm_set_timing(self.h, 1 if on else 0))
 
