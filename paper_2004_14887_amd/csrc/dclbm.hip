@@ -136,9 +136,9 @@ LevelArgs level_args(const Sim& s, int l, int substep, int first, unsigned* grid
         a.tfc_meta = Pn.d_tfc;
         a.keep_parent = 1.0 - 1.0 / Pn.tau;
     }
-    // Segment workgroups go first: their latency-bound work then overlaps
-    // the bulk tiles that start behind them, and none of it lands in the
-    // launch's tail (spreading them over the grid measured slower).
+    // Segment workgroups go ahead of the bulk: their latency-bound work then
+    // overlaps the bulk tiles, and none of it lands in the launch's tail (in
+    // 2-D all first; in 3-D interleaved over the front, see seg_every below).
     a.seg_groups = (a.nb_seg + 7) / 8;
     if (l == 0) {
         a.nb_probe = 1;
