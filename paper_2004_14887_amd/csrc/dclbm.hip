@@ -147,7 +147,9 @@ LevelArgs level_args(const Sim& s, int l, int substep, int first, unsigned* grid
         a.counter = s.d_counter;
         a.psums = s.d_psum;
     }
-    const int nbg = bulk_groups(a.tm.per, bulk_k(s.D, s.P)) / 8;
+    // the tiles per bulk workgroup of the kernel this launch uses (with or
+    // without the segment role; a split substep sizes its bulk kernel itself)
+    const int nbg = bulk_groups(a.tm.per, bulk_k(s.D, s.P, a.nb_seg > 0)) / 8;
     if (s.D == 3 && a.seg_groups > 0) a.seg_every = std::min(kSegEvery3D, nbg / a.seg_groups);
     *grid = (unsigned)(a.nb_probe + a.nb_cap + 8 * a.seg_groups + 8 * nbg);
     return a;

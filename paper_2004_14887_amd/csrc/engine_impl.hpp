@@ -52,7 +52,8 @@ struct EngineImpl final : Engine {
             // the bulk on the simulation's stream, the probe, capture and
             // segment workgroups beside it on the side stream (fork, launch
             // both, join)
-            const unsigned g_bulk = (unsigned)bulk_groups(a.tm.per, bulk_k(DIM, P)), g_if = grid - g_bulk;
+            const unsigned g_bulk = (unsigned)bulk_groups(a.tm.per, bulk_k(DIM, P)),
+                           g_if = (unsigned)(a.nb_probe + a.nb_cap + 8 * a.seg_groups);
             LevelArgs ai = a;
             ai.seg_every = 0;   // its grid holds the segments alone
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -157,7 +158,8 @@ struct EngineImpl final : Engine {
             return e;
         }
         if (split_substep(s, a)) {
-            const unsigned g_bulk = (unsigned)bulk_groups(a.tm.per, bulk_k(DIM, P)), g_if = r.grid - g_bulk;
+            const unsigned g_bulk = (unsigned)bulk_groups(a.tm.per, bulk_k(DIM, P)),
+                           g_if = (unsigned)(a.nb_probe + a.nb_cap + 8 * a.seg_groups);
             LevelArgs ai = a;
             ai.seg_every = 0;   // its grid holds the segments alone
             e = kernel_node(g, reinterpret_cast<const void*>(&k_iface<DIM, EQ, P>), g_if, &ai, deps, &n0);

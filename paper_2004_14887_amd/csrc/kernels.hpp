@@ -1057,16 +1057,21 @@ __device__ __forceinline__ void role_bulk(const LevelArgs& a, int bb)
 
 // Bulk workgroup b of a launch: bulk_k tiles, fetched together, then
 // collided and stored in turn (twice the bytes in flight per wave for the
-// same per-node work; measured faster only for 2-D FP16 storage, whose
-// 2-byte loads keep the fewest bytes in flight).  Workgroup b = 8 q + c
-// (on XCD c) takes the tiles 8 (q k + j) + c, j < k, so each XCD still
-// walks whole tile rows.
-__host__ __device__ constexpr int bulk_k(int dim, int p) { return dim == 2 && p == 2 ? 2 : 1; }
+// same per-node work).  Two tiles pay only with FP16 storage, whose 2-byte
+// loads keep the fewest bytes in flight: in every 2-D kernel, and in the 3-D
+// kernel that carries the segment role (seg), whose registers hold it at 4
+// waves per SIMD (256^3 level 1: 331 -> 310 us); the 3-D FP16 kernels
+// without it run at 8 waves, where a second tile cost 2-7% (the 512^3
+// 4-level mesh).  Workgroup b = 8 q + c (on XCD c) takes the tiles
+// 8 (q k + j) + c, j < k, so each XCD still walks whole tile rows.
+__host__ __device__ constexpr int bulk_k(int dim, int p, bool seg = false)
+{
+    return p == 2 && (dim == 2 || seg) ? 2 : 1;
+}
 
-template <int DIM, int EQ, int P, bool RG = false>
+template <int DIM, int EQ, int P, bool RG = false, int K = bulk_k(DIM, P)>
 __device__ __forceinline__ void role_bulk_group(const LevelArgs& a, int b)
 {
-    constexpr int K = bulk_k(DIM, P);
     if constexpr (K == 1) {
         role_bulk<DIM, EQ, P, RG>(a, b);
     } else {
@@ -1200,7 +1205,7 @@ __device__ __forceinline__ bool level_block(const LevelArgs& a, int b, typename 
         }
         return false;
     }
-    role_bulk_group<DIM, EQ, P, RG>(a, bb);
+    role_bulk_group<DIM, EQ, P, RG, bulk_k(DIM, P, SEG)>(a, bb);
     return false;
 }
 
