@@ -94,9 +94,9 @@ struct EngineImpl final : Engine {
     // kSplitRatio or more bulk groups per segment group runs as two kernels
     // side by side, the bulk alone at 8 waves/SIMD (49 VGPRs instead of
     // 108), which its 2-byte loads need (the 512^3 4-level mesh's finest
-    // launch: 20.6 -> 18.3 ms).  Where the faces weigh more, one launch with
+    // launch: 19.3 -> 18.3 ms).  Where the faces weigh more, one launch with
     // the segments interleaved over its front is faster (the 256^3 2-level
-    // mesh's level 1: 364 -> 333 us).  Levels without segments use
+    // mesh's level 1: 365 -> 310 us).  Levels without segments use
     // k_level_top.
     static constexpr int kSplitRatio = 150;
     // (dclbm_set_split overrides the choice.)
