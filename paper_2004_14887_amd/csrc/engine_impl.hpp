@@ -173,6 +173,7 @@ struct EngineImpl final : Engine {
         deps.assign(1, n0);
         return e;
     }
+    static constexpr int kHrrSegEvery = 32;
     static HrrArgs hrr_args(const Sim& s, const LevelArgs& a, int l)
     {
         const HostLevel& L = s.lv[l];
@@ -210,6 +211,9 @@ struct EngineImpl final : Engine {
         for (int e = 0; e < 3; ++e) h.plo[e] = L.plo[e];
         h.ie_tf = L.d_ie_tf;
         h.nb_bulk = bulk_groups(h.a.tm.per, 1);
+        // 3-D: the segments interleaved over the front of the macroscopic
+        // launch, one group of 8 after every kHrrSegEvery bulk groups
+        h.a.seg_every = DIM == 3 && a.seg_groups > 0 ? std::min(kHrrSegEvery, (h.nb_bulk / 8) / a.seg_groups) : 0;
         return h;
     }
     void hrr_open(Sim& s, int l, int substep, int first) override
@@ -217,7 +221,7 @@ struct EngineImpl final : Engine {
         unsigned grid = 0;
         const LevelArgs a = level_args(s, l, substep, first, &grid);
         const HrrArgs h = hrr_args(s, a, l);
-        const dim3 grid_m(a.nb_probe + a.nb_seg + a.nb_cap + h.nb_bulk);
+        const dim3 grid_m(a.nb_probe + a.nb_cap + (h.a.seg_every > 0 ? 8 * a.seg_groups : a.nb_seg) + h.nb_bulk);
         if (a.nb_seg > 0 && s.lv[l].d_cls)
             hipLaunchKernelGGL((k_hrr_macros<DIM, EQ, P, true, true>), grid_m, dim3(kBlock), 0, s.stream, h);
         else if (a.nb_seg > 0)

@@ -1437,14 +1437,16 @@ __device__ __forceinline__ void hrr_collide_node(const LevelDev& g, const Ref<ty
     }
 }
 
-// Workgroups of an H-RR macroscopic launch: the probe (level 0), the
-// interface segments (refined levels: completion of the co-located and
-// hanging nodes without collision), the coarse capture (levels with a
-// child), then the bulk tiles, each bulk node writing its post-streaming
-// (drho, du) into M and, next to the child's box, into the newest slot of
-// the level's ring.  The segments come first, so that their latency-bound
-// work overlaps the bulk (one launch measured 13% faster per coarse step
-// than the segments in a launch of their own beside it on a second stream).
+// Workgroups of an H-RR macroscopic launch: the probe (level 0), the coarse
+// capture (levels with a child), the interface segments (refined levels:
+// completion of the co-located and hanging nodes without collision), then
+// the bulk tiles, each bulk node writing its post-streaming (drho, du) into
+// M and, next to the child's box, into the newest slot of the level's ring.
+// The segments go ahead of the bulk, so that their latency-bound work
+// overlaps it (one launch measured 13% faster per coarse step than the
+// segments in a launch of their own beside it on a second stream); in 3-D
+// they are interleaved over the front of the bulk in groups of 8, as in the
+// BGK launch (LevelArgs::seg_every).
 // SEG: the level has segments (without them the kernel holds no LDS and
 // needs fewer registers); RG: they lie on a refined region's boundary.
 template <int DIM, int EQ, int P, bool SEG, bool RG = false>
@@ -1465,18 +1467,35 @@ __global__ __launch_bounds__(kBlock) void k_hrr_macros(HrrArgs h)
         return;
     }
     b -= a.nb_probe;
-    if constexpr (SEG) {
-        if (b < a.nb_seg) {
-            role_segment<DIM, EQ, P, true, true, RG>(a, b, lds);
-            return;
-        }
-        b -= a.nb_seg;
-    }
     if (b < a.nb_cap) {
         role_capture<DIM, P>(a, b);
         return;
     }
     b -= a.nb_cap;
+    if constexpr (SEG) {
+        // the segment workgroup sb, or (sb < 0) the bulk workgroup b
+        int sb = -1;
+        if (a.seg_every > 0) {
+            const int G = b >> 3, r = b & 7, per = a.seg_every + 1;
+            const int k = G / per, q = G - k * per;
+            if (k < a.seg_groups) {
+                if (q == 0)
+                    sb = 8 * k + r;
+                else
+                    b = 8 * (k * a.seg_every + q - 1) + r;
+            } else {
+                b = 8 * (a.seg_groups * a.seg_every + G - a.seg_groups * per) + r;
+            }
+        } else if (b < a.nb_seg) {
+            sb = b;
+        } else {
+            b -= a.nb_seg;
+        }
+        if (sb >= 0) {
+            if (sb < a.nb_seg) role_segment<DIM, EQ, P, true, true, RG>(a, sb, lds);
+            return;
+        }
+    }
     R s[Q];
     int64_t e0 = 0;
     int xyz[3];
