@@ -123,6 +123,16 @@ def test_checkpoint_entry_points_reject_null_arguments():
     assert "null" in lib.dclbm_last_error().decode()
 
 
+def test_probe_sum_and_layout_entry_points_reject_null_arguments():
+    import ctypes as C
+    lib = _lib()
+    n = C.c_int64(7)
+    assert lib.dclbm_set_probe_window(None, 0, 1) == -1
+    assert lib.dclbm_read_probe_sums(None, None, C.byref(n)) == -1 and n.value == 7
+    assert lib.dclbm_set_split(None, 0) == -1
+    assert "null" in lib.dclbm_last_error().decode()
+
+
 def test_hrr_configuration_validation():
     _lib()
     from paper_2004_14887_amd._lib import DclbmError
