@@ -708,6 +708,12 @@ dclbm_status build_geometry(Sim& s)
             L.xface = 1;
             L.xf_elems = 2 * (int64_t)Q * L.nz * L.ny;
             for (int b = 0; b < 2; ++b) L.off_xf[b] = take(L.xf_elems * (int64_t)s.tsize);
+            // with BGK in FP32 and FP64, the directions the faces pull from
+            // the next planes once more, in the same layout (256^3 level 1:
+            // 508 -> 497 us FP32, 1001 -> 986 us FP64; FP16 lost 2%, and
+            // H-RR keeps the row blocks)
+            if (!s.hrr && s.P != DCLBM_FP32_FP16)
+                for (int b = 0; b < 2; ++b) L.off_xn[b] = take(L.xf_elems * (int64_t)s.tsize);
         }
         if (!L.tf_meta.empty()) {
             L.off_tf = take((int64_t)L.tf_meta.size() * 16);
@@ -764,6 +770,7 @@ dclbm_status sim_attach(Sim& s, void* d_workspace, size_t bytes, hipStream_t str
         for (int b = 0; b < 2; ++b) {
             L.f[b] = s.ws + L.off_f[b];
             L.xf[b] = L.xface ? s.ws + L.off_xf[b] : nullptr;
+            L.xn[b] = L.off_xn[b] > 0 ? s.ws + L.off_xn[b] : nullptr;   // laid out only where used
         }
         if (!L.tf_meta.empty()) {
             L.d_tf = s.at<int4>(L.off_tf);
@@ -1048,6 +1055,7 @@ static void state_regions(const Sim& s, Fn&& fn)
     for (const HostLevel& L : s.lv) {
         fn(L.f[L.parity], L.elems * (int64_t)s.tsize);
         if (L.xface) fn(L.xf[L.parity], L.xf_elems * (int64_t)s.tsize);
+        if (L.xn[0]) fn(L.xn[L.parity], L.xf_elems * (int64_t)s.tsize);
         if (!L.tf_meta.empty()) fn(L.X, (int64_t)L.tf_meta.size() * 4 * (int64_t)s.rsize);
         if (!L.tfc_meta.empty()) fn(L.H, (int64_t)L.tfc_meta.size() * 3 * s.Q * (int64_t)s.rsize);
         if (L.d_Mring) fn(L.d_Mring, 3 * 4 * L.n_dense() * (int64_t)s.rsize);

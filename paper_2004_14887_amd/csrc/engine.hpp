@@ -59,6 +59,8 @@ struct HostLevel {
     // device pointers
     void* f[2] = {nullptr, nullptr};
     void* xf[2] = {nullptr, nullptr};
+    int64_t off_xn[2] = {0, 0};
+    void* xn[2] = {nullptr, nullptr};   // BGK: second copies of what the x faces pull from the next planes
     int4 *d_tf = nullptr, *d_ie = nullptr, *d_tfc = nullptr, *d_seg_info = nullptr;
     int *d_seg_tf = nullptr, *d_seg_ie = nullptr, *d_seg_sten = nullptr;
     int4* d_seg_tfm = nullptr;
@@ -94,6 +96,8 @@ struct HostLevel {
         g.xface = xface;
         g.xf[0] = xf[0];
         g.xf[1] = xf[1];
+        g.xn[0] = xn[0];
+        g.xn[1] = xn[1];
         g.cls = d_cls;
         return g;
     }

@@ -117,6 +117,11 @@ struct LevelDev {
     // that the interface tiles of those faces read and write whole lines
     int xface;
     void* xf[2];
+    // 3-D refined levels with BGK: the directions that the x-face nodes pull
+    // from the planes next to them (x = 1 with xi_x = -1, x = nx - 2 with
+    // xi_x = +1), kept a second time in y-fastest buffers laid out like xf;
+    // null: the faces pull from the row blocks (one cache line per lane)
+    void* xn[2];
     // a level shaped by a refined region of level-0 cells (and its parent):
     // one class byte per node, x fastest (kClsBulk, kClsHole for holes and for
     // refined-level nodes outside the region, kClsTfc, kClsTf, kClsIe); null
@@ -276,6 +281,22 @@ __device__ __forceinline__ int64_t xfoff(const LevelDev& g, int x, int i, int y,
     return (((int64_t)(x == 0 ? 0 : 1) * Lat<DIM>::Q + i) * g.nz + z) * g.ny + y;
 }
 
+// Direction i of node (x, y, z) is one that an x-face node pulls from the
+// plane next to it (and so is kept in xn as well).
+template <int DIM>
+__device__ __forceinline__ bool on_xnext(const LevelDev& g, int x, int i)
+{
+    return DIM == 3 && g.xn[0] != nullptr &&
+           ((x == 1 && cdir<DIM>(i, 0) == -1) || (x == g.nx - 2 && cdir<DIM>(i, 0) == 1));
+}
+
+// Its element in xn[par] (side 0 for x = 1, side 1 for x = nx - 2).
+template <int DIM>
+__device__ __forceinline__ int64_t xnoff(const LevelDev& g, int x, int i, int y, int z)
+{
+    return xfoff<DIM>(g, x == 1 ? 0 : g.nx - 1, i, y, z);
+}
+
 // Direction i of node (x, y, z) in the state of parity par (base = f[par]).
 template <int DIM, typename T>
 __device__ __forceinline__ T* node_elem(const LevelDev& g, T* base, int par, int i, int x, int y, int z)
@@ -307,7 +328,19 @@ __device__ __forceinline__ const T* pull_elem(const LevelDev& g, const T* src, i
         sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
         if (DIM == 3) sz = sz < 0 ? sz + g.nz : (sz >= g.nz ? sz - g.nz : sz);
     }
+    if (on_xnext<DIM>(g, sx, i)) return reinterpret_cast<const T*>(g.xn[par]) + xnoff<DIM>(g, sx, i, sy, sz);
     return node_elem<DIM>(g, const_cast<T*>(src), par, i, sx, sy, sz);
+}
+
+// Store of direction i of node (x, y, z) into the state of parity par
+// through the cache, with its second copy where an x face pulls it.
+template <int DIM, int P>
+__device__ __forceinline__ void store_node_wb(const LevelDev& g, typename Form<P>::T* base, int par, int i, int x,
+                                              int y, int z, typename Form<P>::R v)
+{
+    using T = typename Form<P>::T;
+    Form<P>::store_wb(node_elem<DIM>(g, base, par, i, x, y, z), v);
+    if (on_xnext<DIM>(g, x, i)) Form<P>::store_wb(reinterpret_cast<T*>(g.xn[par]) + xnoff<DIM>(g, x, i, y, z), v);
 }
 
 // A box level's interface nodes and holes (from its box and its child's).
@@ -665,8 +698,8 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const R e0 = eq0(i);
-                F::store_wb(node_elem<DIM>(a.g, dst, a.par ^ 1, i, m.x, m.y, m.z),
-                            HRR ? R(col[i * TFM]) : e0 + keep * (col[i * TFM] - e0));
+                store_node_wb<DIM, P>(a.g, dst, a.par ^ 1, i, m.x, m.y, m.z,
+                                      HRR ? R(col[i * TFM]) : e0 + keep * (col[i * TFM] - e0));
             }
             if constexpr (HRR)
                 put_mac<DIM, R>(a.M, (int64_t)a.g.nx * a.g.ny * a.g.nz, dense_index<DIM>(a.g, m.x, m.y, m.z), mx.drho,
@@ -731,7 +764,7 @@ __device__ __forceinline__ void role_segment(const LevelArgs& a, int sgi, typena
         else
             bgk<DIM, EQ, SH, R>(s, rf, make_mac<DIM, SH, R>(rf, drho, du), R(a.keep));
 #pragma unroll
-        for (int i = 0; i < Q; ++i) F::store_wb(node_elem<DIM>(a.g, dst, a.par ^ 1, i, m.x, m.y, m.z), s[i]);
+        for (int i = 0; i < Q; ++i) store_node_wb<DIM, P>(a.g, dst, a.par ^ 1, i, m.x, m.y, m.z, s[i]);
     }
 }
 
@@ -1043,6 +1076,18 @@ __device__ __forceinline__ void bulk_finish(const LevelArgs& a, BulkTile<DIM, P>
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         B::st_nt(t.rd, (uint32_t)(t.ox[1] + i * ((int)sizeof(T) << kRowShift)), to_bits<P>(t.s[i]));
+    if constexpr (DIM == 3) {
+        // the planes next to the x faces: the directions the faces pull,
+        // a second time into xn
+        const LevelDev& g = a.g;
+        if (g.xn[0] && t.v && (t.x == 1 || t.x == g.nx - 2)) {
+            T* xb = reinterpret_cast<T*>(g.xn[a.par ^ 1]);
+            const int c = t.x == 1 ? -1 : 1;
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                if (cdir<DIM>(i, 0) == c) F::store_wb(xb + xnoff<DIM>(g, t.x, i, t.y, t.z), t.s[i]);
+        }
+    }
 }
 
 template <int DIM, int EQ, int P, bool RG = false>
@@ -1866,7 +1911,7 @@ __global__ __launch_bounds__(256) void k_init(LevelDev g, typename Form<P>::T* _
     const Mac<double> mc = make_mac<DIM, SH, double>(rf, rho[d] - F::rho0, du);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        F::store(node_elem<DIM>(g, dst, par, i, x, y, z), R(eq_s<DIM, EQ, SH, double>(i, rf, mc)));
+        store_node_wb<DIM, P>(g, dst, par, i, x, y, z, R(eq_s<DIM, EQ, SH, double>(i, rf, mc)));
 }
 
 template <int DIM, int EQ, int P>
